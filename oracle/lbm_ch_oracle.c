@@ -1,0 +1,477 @@
+/*
+ * FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY (see lbm_ch_oracle.h).
+ *
+ * Zhang, Guo & Liang, "A high-order lattice Boltzmann model for the Cahn-Hilliard
+ * equation", arXiv:1805.00007.  Plain full-grid loops, double precision, in the
+ * order of Sec. II.  OpenMP splits the row loops only; every value is computed by
+ * the same expression whatever the thread count, so results do not depend on it.
+ */
+#include "lbm_ch_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* D2Q9 lattice of Sec. II.B: c_0 = 0, c_1 = -c_3 = (1,0), c_2 = -c_4 = (0,1),
+ * c_5 = -c_7 = (1,1), c_6 = -c_8 = (-1,1); weights below Eq. geq. */
+static const int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+static const double W[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                            1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+static const double CS2 = 1.0 / 3.0; /* c_s^2 = c^2/3 with c = 1 */
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+/* ---------------------------------------------------------------- parameters */
+
+int orc_coeffs_from(const orc_params* p, orc_coeffs* c) {
+  double dphi = p->phi_a - p->phi_b;
+  if (!(p->tau_g > 0.5) || dphi == 0.0) return -1;
+  double ad = fabs(dphi);
+  /* Eq. betakappa */
+  c->beta = 12.0 * p->sigma / (p->width * ad * ad * ad * ad);
+  c->kappa = 3.0 * p->sigma * p->width / (2.0 * ad * ad);
+  /* M = cs^2 eta (tau_g - 1/2), stated below Eq. phit3 */
+  c->eta = p->mobility / (CS2 * (p->tau_g - 0.5));
+  /* K below Eq. F2-1 */
+  c->K = (p->tau_g - 1.0 / 6.0 - p->tau_g * p->tau_g) / (p->tau_g - 0.5);
+  /* Eq. rho */
+  c->a = (p->rho_a - p->rho_b) / dphi;
+  c->b = (p->rho_b * p->phi_a - p->phi_b * p->rho_a) / dphi;
+  return 0;
+}
+
+/* ---------------------------------------------------------- node primitives */
+
+/* s_i(u) = c_i.u/cs^2 + (c_i.u)^2/(2 cs^4) - u^2/(2 cs^2), the bracket of Eq. geq. */
+static double s_poly(int i, double ux, double uy) {
+  double cu = CX[i] * ux + CY[i] * uy;
+  double u2 = ux * ux + uy * uy;
+  return cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - u2 / (2.0 * CS2);
+}
+
+/* Eq. geq. */
+void orc_equilibrium_g(double phi, double mu, double ux, double uy, double eta, double geq[9]) {
+  double u2 = ux * ux + uy * uy;
+  geq[0] = phi + (W[0] - 1.0) * eta * mu - W[0] * phi * u2 / (2.0 * CS2);
+  for (int i = 1; i < 9; ++i) geq[i] = W[i] * eta * mu + W[i] * phi * s_poly(i, ux, uy);
+}
+
+/* Eq. liangFi: S_i = w_i c_i . F / cs^2. */
+void orc_source_g(double fx, double fy, double s[9]) {
+  for (int i = 0; i < 9; ++i) s[i] = W[i] * (CX[i] * fx + CY[i] * fy) / CS2;
+}
+
+/* Navier-Stokes equilibrium (pressure-based incompressible form):
+ * f_0 = (w_0 - 1) p/cs^2 + rho w_0 s_0(u),  f_i = w_i p/cs^2 + rho w_i s_i(u),
+ * so that sum f = 0, sum c f = rho u, sum c c f = p I + rho u u. */
+void orc_equilibrium_f(double p, double rho, double ux, double uy, double feq[9]) {
+  feq[0] = (W[0] - 1.0) * p / CS2 + rho * W[0] * s_poly(0, ux, uy);
+  for (int i = 1; i < 9; ++i) feq[i] = W[i] * p / CS2 + rho * W[i] * s_poly(i, ux, uy);
+}
+
+/* Navier-Stokes forcing with moments sum G = u.grad rho, sum c G = F,
+ * sum c c G = u F + F u + cs^2 (u.grad rho I + u grad rho + grad rho u):
+ * G_i = w_i [ (c_i - u).F/cs^2 + (c_i.u)(c_i.F)/cs^4 + (c_i.u)(c_i.grad rho)/cs^2 ]. */
+void orc_source_f(double fx, double fy, double ux, double uy, double drx, double dry,
+                  double s[9]) {
+  for (int i = 0; i < 9; ++i) {
+    double cu = CX[i] * ux + CY[i] * uy;
+    double cf = CX[i] * fx + CY[i] * fy;
+    double cr = CX[i] * drx + CY[i] * dry;
+    double cmuf = (CX[i] - ux) * fx + (CY[i] - uy) * fy;
+    s[i] = W[i] * (cmuf / CS2 + cu * cf / (CS2 * CS2) + cu * cr / CS2);
+  }
+}
+
+/* ------------------------------------------------------------ grid helpers */
+
+static size_t nn(const orc_params* p) { return (size_t)p->nx * (size_t)p->ny; }
+
+/* Value of a grid field at any (x, y): x periodic; y periodic, or mirrored across
+ * the walls at y = -1/2 and y = ny - 1/2 with the given parity (+1 for phi, mu, p;
+ * -1 for the velocity, whose no-slip value on the wall is zero). */
+static double at(const orc_params* p, const double* a, int parity, int x, int y) {
+  int nx = p->nx, ny = p->ny;
+  x = ((x % nx) + nx) % nx;
+  if (!p->walls) {
+    y = ((y % ny) + ny) % ny;
+    return a[(size_t)y * nx + x];
+  }
+  if (y < 0) return parity * a[(size_t)(-1 - y) * nx + x];
+  if (y >= ny) return parity * a[(size_t)(2 * ny - 1 - y) * nx + x];
+  return a[(size_t)y * nx + x];
+}
+
+/* Isotropic central schemes (Sec. III), built from the lattice weights:
+ *   d_a psi(x) = (1/cs^2) sum_i w_i c_ia psi(x + c_i)
+ *   lap psi(x) = (2/cs^2) sum_i w_i [psi(x + c_i) - psi(x)]
+ * The gradient is exact for quadratics and the Laplacian for cubics. */
+static void grad_at(const orc_params* p, const double* a, int parity, int x, int y,
+                    double* gx, double* gy) {
+  double sx = 0.0, sy = 0.0;
+  for (int i = 1; i < 9; ++i) {
+    double v = at(p, a, parity, x + CX[i], y + CY[i]);
+    sx += W[i] * CX[i] * v;
+    sy += W[i] * CY[i] * v;
+  }
+  *gx = sx / CS2;
+  *gy = sy / CS2;
+}
+
+static double lap_at(const orc_params* p, const double* a, int parity, int x, int y) {
+  double c = at(p, a, parity, x, y);
+  double s = 0.0;
+  for (int i = 1; i < 9; ++i) s += W[i] * (at(p, a, parity, x + CX[i], y + CY[i]) - c);
+  return 2.0 * s / CS2;
+}
+
+void orc_grad(const orc_params* p, const double* psi, int parity, double* gx, double* gy) {
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < p->ny; ++y)
+    for (int x = 0; x < p->nx; ++x) {
+      size_t k = (size_t)y * p->nx + x;
+      grad_at(p, psi, parity, x, y, &gx[k], &gy[k]);
+    }
+}
+
+void orc_lap(const orc_params* p, const double* psi, int parity, double* out) {
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < p->ny; ++y)
+    for (int x = 0; x < p->nx; ++x) out[(size_t)y * p->nx + x] = lap_at(p, psi, parity, x, y);
+}
+
+/* df/dphi of Eq. bulk: 2 beta (phi - phi_A)(phi - phi_B)(2 phi - phi_A - phi_B). */
+static double dbulk(const orc_params* p, const orc_coeffs* c, double phi) {
+  return 2.0 * c->beta * (phi - p->phi_a) * (phi - p->phi_b) * (2.0 * phi - p->phi_a - p->phi_b);
+}
+
+/* Eq. mu. */
+void orc_chemical_potential(const orc_params* p, const double* phi, double* mu) {
+  orc_coeffs c;
+  orc_coeffs_from(p, &c);
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < p->ny; ++y)
+    for (int x = 0; x < p->nx; ++x) {
+      size_t k = (size_t)y * p->nx + x;
+      mu[k] = dbulk(p, &c, phi[k]) - c.kappa * lap_at(p, phi, +1, x, y);
+    }
+}
+
+/* Eq. macroscopicg. */
+static void order_parameter(const orc_params* p, const double* g, double* phi) {
+  size_t n = nn(p);
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < p->ny; ++y)
+    for (int x = 0; x < p->nx; ++x) {
+      size_t k = (size_t)y * p->nx + x;
+      double s = 0.0;
+      for (int i = 0; i < 9; ++i) s += g[i * n + k];
+      phi[k] = s;
+    }
+}
+
+/* Streaming g_i(x + c_i, t + 1) = g_i*(x, t) in pull form; with walls a
+ * population whose source lies beyond a wall is the one that left the same node in
+ * the opposite direction (half-way bounce-back). */
+static void stream(const orc_params* p, const double* post, double* out) {
+  size_t n = nn(p);
+  int nx = p->nx, ny = p->ny;
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x)
+      for (int i = 0; i < 9; ++i) {
+        int sx = ((x - CX[i]) % nx + nx) % nx;
+        int sy = y - CY[i];
+        size_t k = (size_t)y * nx + x;
+        if (p->walls && (sy < 0 || sy >= ny))
+          out[i * n + k] = post[OPP[i] * n + k];
+        else
+          out[i * n + k] = post[i * n + (size_t)((sy % ny + ny) % ny) * nx + sx];
+      }
+}
+
+/* ------------------------------------------------------------------- method */
+
+typedef struct {
+  double *phi, *mu, *mux, *muy, *lapmu, *phx, *phy; /* order parameter and derived   */
+  double *u, *v, *pr, *px, *py;                     /* velocity and pressure         */
+  double *qx, *qy, *dext;                           /* phi u and its divergence      */
+  double *fx, *fy, *ftx, *fty;                      /* CH force F; NS total force    */
+  double* post;                                     /* post-collision populations    */
+} orc_work;
+
+static double* zalloc(size_t n) { return (double*)calloc(n, sizeof(double)); }
+
+static void work_alloc(const orc_params* p, orc_work* w) {
+  size_t n = nn(p);
+  w->phi = zalloc(n); w->mu = zalloc(n); w->mux = zalloc(n); w->muy = zalloc(n);
+  w->lapmu = zalloc(n); w->phx = zalloc(n); w->phy = zalloc(n);
+  w->u = zalloc(n); w->v = zalloc(n); w->pr = zalloc(n); w->px = zalloc(n); w->py = zalloc(n);
+  w->qx = zalloc(n); w->qy = zalloc(n); w->dext = zalloc((size_t)p->nx * (p->ny + 2));
+  w->fx = zalloc(n); w->fy = zalloc(n); w->ftx = zalloc(n); w->fty = zalloc(n);
+  w->post = zalloc(9 * n);
+}
+
+static void work_free(orc_work* w) {
+  double* all[] = {w->phi, w->mu, w->mux, w->muy, w->lapmu, w->phx, w->phy, w->u, w->v,
+                   w->pr, w->px, w->py, w->qx, w->qy, w->dext, w->fx, w->fy, w->ftx,
+                   w->fty, w->post};
+  for (size_t i = 0; i < sizeof(all) / sizeof(all[0]); ++i) free(all[i]);
+}
+
+/* Navier-Stokes macroscopic step (the Rayleigh-Taylor coupling, Sec. III.E):
+ * total force F = F_s + F_b + u (drho/dphi) M lap(mu), where F_s = -phi grad mu is
+ * the surface-tension force of Eq. NS and the last term turns the conservative
+ * momentum balance that the LBE recovers into the non-conservative Eq. NS(b);
+ * rho u = sum_i c_i f_i + F/2 (solved for u); and
+ * p = cs^2/(1 - w_0) [sum_{i>0} f_i + u.grad rho / 2 + rho w_0 s_0(u)]. */
+static void ns_velocity_pressure(const orc_params* p, const orc_coeffs* c, const double* f,
+                                 orc_work* w) {
+  size_t n = nn(p);
+  double rho_mean = 0.5 * (p->rho_a + p->rho_b);
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < p->ny; ++y)
+    for (int x = 0; x < p->nx; ++x) {
+      size_t k = (size_t)y * p->nx + x;
+      double phi = w->phi[k];
+      double rho = c->a * phi + c->b;
+      double fsx = -phi * w->mux[k], fsy = -phi * w->muy[k];
+      double fbx = rho * p->accel_x, fby = -(rho - rho_mean) * p->gravity;
+      double mx = 0.0, my = 0.0;
+      for (int i = 0; i < 9; ++i) {
+        mx += CX[i] * f[i * n + k];
+        my += CY[i] * f[i * n + k];
+      }
+      double corr = c->a * p->mobility * w->lapmu[k];
+      double ux = (mx + 0.5 * (fsx + fbx)) / (rho - 0.5 * corr);
+      double uy = (my + 0.5 * (fsy + fby)) / (rho - 0.5 * corr);
+      w->u[k] = ux;
+      w->v[k] = uy;
+      w->ftx[k] = fsx + fbx + ux * corr;
+      w->fty[k] = fsy + fby + uy * corr;
+      double drx = c->a * w->phx[k], dry = c->a * w->phy[k];
+      double s = 0.0;
+      for (int i = 1; i < 9; ++i) s += f[i * n + k];
+      w->pr[k] = CS2 / (1.0 - W[0]) *
+                 (s + 0.5 * (ux * drx + uy * dry) + rho * W[0] * s_poly(0, ux, uy));
+    }
+}
+
+/* Order parameter, chemical potential and their gradients for the current g. */
+static void phase_fields(const orc_params* p, const orc_coeffs* c, const double* g, orc_work* w) {
+  (void)c;
+  order_parameter(p, g, w->phi);
+  orc_chemical_potential(p, w->phi, w->mu);
+  orc_grad(p, w->mu, +1, w->mux, w->muy);
+  if (p->ns) {
+    orc_lap(p, w->mu, +1, w->lapmu);
+    orc_grad(p, w->phi, +1, w->phx, w->phy);
+  }
+}
+
+/* Velocity at step n: prescribed (factor times base field) or from the NS populations. */
+static void velocity_fields(const orc_params* p, const orc_coeffs* c, const double* f,
+                            const double* ux, const double* uy, double tfac, orc_work* w) {
+  size_t n = nn(p);
+  if (p->ns) {
+    ns_velocity_pressure(p, c, f, w);
+    orc_grad(p, w->pr, +1, w->px, w->py);
+    return;
+  }
+  for (size_t k = 0; k < n; ++k) {
+    w->u[k] = ux ? tfac * ux[k] : 0.0;
+    w->v[k] = uy ? tfac * uy[k] : 0.0;
+    w->pr[k] = 0.0;
+    w->px[k] = 0.0;
+    w->py[k] = 0.0;
+  }
+}
+
+/* F = F1 (+ F2): Eq. t0-phiu and Eq. mark3. */
+static void ch_force(const orc_params* p, const orc_coeffs* c, orc_work* w) {
+  size_t n = nn(p);
+  int nx = p->nx, ny = p->ny;
+  double rho_mean = 0.5 * (p->rho_a + p->rho_b);
+  /* F1 = (phi/rho) (F_s + F_b - grad p), F_s = -phi grad mu.  With a prescribed
+   * velocity there is no pressure field or body force: grad p = 0, F_b = 0. */
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      size_t k = (size_t)y * nx + x;
+      double phi = w->phi[k];
+      double rho = c->a * phi + c->b;
+      double tx = -phi * w->mux[k] - w->px[k];
+      double ty = -phi * w->muy[k] - w->py[k];
+      if (p->ns) {
+        tx += rho * p->accel_x;
+        ty += -(rho - rho_mean) * p->gravity;
+      }
+      w->fx[k] = phi / rho * tx;
+      w->fy[k] = phi / rho * ty;
+    }
+  if (p->model != 2) return;
+  /* F2 = 3 cs^2 K grad(div(phi u)): two composed isotropic gradients.  q = phi u
+   * takes the velocity's ghost parity (-1) across walls; div q is evaluated on the
+   * rows -1..ny (stored with a one-row offset) so that its gradient reaches every
+   * fluid row. */
+  for (size_t k = 0; k < n; ++k) {
+    w->qx[k] = w->phi[k] * w->u[k];
+    w->qy[k] = w->phi[k] * w->v[k];
+  }
+  int ylo = p->walls ? -1 : 0, yhi = p->walls ? ny : ny - 1;
+#pragma omp parallel for schedule(static)
+  for (int y = ylo; y <= yhi; ++y)
+    for (int x = 0; x < nx; ++x) {
+      double ax, ay, bx, by;
+      grad_at(p, w->qx, -1, x, y, &ax, &ay);
+      grad_at(p, w->qy, -1, x, y, &bx, &by);
+      w->dext[(size_t)(y + 1) * nx + x] = ax + by;
+    }
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      double sx = 0.0, sy = 0.0;
+      for (int i = 1; i < 9; ++i) {
+        int xx = ((x + CX[i]) % nx + nx) % nx;
+        int yy = y + CY[i];
+        if (!p->walls) yy = (yy % ny + ny) % ny;
+        double d = w->dext[(size_t)(yy + 1) * nx + xx];
+        sx += W[i] * CX[i] * d;
+        sy += W[i] * CY[i] * d;
+      }
+      size_t k = (size_t)y * nx + x;
+      w->fx[k] += 3.0 * CS2 * c->K * (sx / CS2);
+      w->fy[k] += 3.0 * CS2 * c->K * (sy / CS2);
+    }
+}
+
+/* Eq. LB collision for g (and the NS collision for f), then streaming. */
+static void collide_stream(const orc_params* p, const orc_coeffs* c, double* g, double* f,
+                           orc_work* w) {
+  size_t n = nn(p);
+  double tg = p->tau_g;
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < p->ny; ++y)
+    for (int x = 0; x < p->nx; ++x) {
+      size_t k = (size_t)y * p->nx + x;
+      double geq[9], s[9];
+      orc_equilibrium_g(w->phi[k], w->mu[k], w->u[k], w->v[k], c->eta, geq);
+      orc_source_g(w->fx[k], w->fy[k], s);
+      for (int i = 0; i < 9; ++i)
+        w->post[i * n + k] = g[i * n + k] - (g[i * n + k] - geq[i]) / tg + (1.0 - 0.5 / tg) * s[i];
+    }
+  stream(p, w->post, g);
+  if (!p->ns) return;
+  double tf = p->tau_f;
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < p->ny; ++y)
+    for (int x = 0; x < p->nx; ++x) {
+      size_t k = (size_t)y * p->nx + x;
+      double feq[9], s[9];
+      double rho = c->a * w->phi[k] + c->b;
+      orc_equilibrium_f(w->pr[k], rho, w->u[k], w->v[k], feq);
+      orc_source_f(w->ftx[k], w->fty[k], w->u[k], w->v[k], c->a * w->phx[k], c->a * w->phy[k], s);
+      for (int i = 0; i < 9; ++i)
+        w->post[i * n + k] = f[i * n + k] - (f[i * n + k] - feq[i]) / tf + (1.0 - 0.5 / tf) * s[i];
+    }
+  stream(p, w->post, f);
+}
+
+void orc_init(const orc_params* p, const double* phi0, const double* ux0, const double* uy0,
+              double* g, double* f) {
+  orc_coeffs c;
+  orc_coeffs_from(p, &c);
+  size_t n = nn(p);
+  double* mu = zalloc(n);
+  orc_chemical_potential(p, phi0, mu);
+  for (size_t k = 0; k < n; ++k) {
+    double geq[9];
+    orc_equilibrium_g(phi0[k], mu[k], ux0 ? ux0[k] : 0.0, uy0 ? uy0[k] : 0.0, c.eta, geq);
+    for (int i = 0; i < 9; ++i) g[i * n + k] = geq[i];
+    if (p->ns && f) {
+      double feq[9];
+      orc_equilibrium_f(0.0, c.a * phi0[k] + c.b, ux0 ? ux0[k] : 0.0, uy0 ? uy0[k] : 0.0, feq);
+      for (int i = 0; i < 9; ++i) f[i * n + k] = feq[i];
+    }
+  }
+  free(mu);
+}
+
+void orc_run(const orc_params* p, double* g, double* f, const double* ux, const double* uy,
+             const double* tf, long nsteps) {
+  orc_coeffs c;
+  if (orc_coeffs_from(p, &c) != 0) return;
+  orc_work w;
+  work_alloc(p, &w);
+  for (long s = 0; s < nsteps; ++s) {
+    phase_fields(p, &c, g, &w);
+    velocity_fields(p, &c, f, ux, uy, tf ? tf[s] : 1.0, &w);
+    ch_force(p, &c, &w);
+    collide_stream(p, &c, g, f, &w);
+  }
+  work_free(&w);
+}
+
+void orc_fields(const orc_params* p, const double* g, const double* f, const double* ux,
+                const double* uy, double tfac, double* phi, double* mu, double* u, double* v,
+                double* pr) {
+  orc_coeffs c;
+  orc_coeffs_from(p, &c);
+  orc_work w;
+  work_alloc(p, &w);
+  size_t n = nn(p);
+  phase_fields(p, &c, g, &w);
+  velocity_fields(p, &c, f, ux, uy, tfac, &w);
+  if (phi) memcpy(phi, w.phi, n * sizeof(double));
+  if (mu) memcpy(mu, w.mu, n * sizeof(double));
+  if (u) memcpy(u, w.u, n * sizeof(double));
+  if (v) memcpy(v, w.v, n * sizeof(double));
+  if (pr) memcpy(pr, w.pr, n * sizeof(double));
+  work_free(&w);
+}
+
+void orc_diag(const orc_params* p, const double* phi, const double* phi_ref, double out[8]) {
+  orc_coeffs c;
+  orc_coeffs_from(p, &c);
+  double s = 0, sa = 0, e = 0, d2 = 0, r2 = 0, mx = -INFINITY, mn = INFINITY, bad = 0;
+  for (int y = 0; y < p->ny; ++y)
+    for (int x = 0; x < p->nx; ++x) {
+      size_t k = (size_t)y * p->nx + x;
+      double v = phi[k];
+      if (!isfinite(v)) { bad += 1; continue; }
+      s += v;
+      sa += fabs(v);
+      /* Eq. freeEnergy with the bulk density of Eq. bulk */
+      double gx, gy;
+      grad_at(p, phi, +1, x, y, &gx, &gy);
+      double fa = v - p->phi_a, fb = v - p->phi_b;
+      e += c.beta * fa * fa * fb * fb + 0.5 * c.kappa * (gx * gx + gy * gy);
+      if (phi_ref) {
+        d2 += (v - phi_ref[k]) * (v - phi_ref[k]);
+        r2 += phi_ref[k] * phi_ref[k];
+      }
+      if (v > mx) mx = v;
+      if (v < mn) mn = v;
+    }
+  out[0] = s; out[1] = sa; out[2] = e; out[3] = d2; out[4] = r2; out[5] = mx; out[6] = mn;
+  out[7] = bad;
+}

@@ -1,0 +1,335 @@
+"""Pins of the oracle's time stepping (phase field, prescribed velocity).
+
+* exact mass conservation (Eq. conservation + streaming is a permutation);
+* the tau_g = 1 identity: the collision is then memoryless (g* = g^eq + S/2), so one
+  step of Eq. LB is the macroscopic finite-difference scheme
+      phi' = phi + M lap(mu) + sum_i w_i [phi s_i(u)](x - c_i) - div(F)/2,
+  written here independently with numpy rolls; with u = 0 this is explicit Euler for
+  the Cahn-Hilliard equation (Eq. CH) with the extra mobility of the F1 term;
+* the closed-form linear response of a Fourier mode (any tau_g via the 9x9 linearised
+  update; tau_g = 1 in closed form), which fixes the stencils, the sign and size of
+  F1 and F2, the eta-M relation and the streaming direction;
+* with sigma = 0, F2 of Eq. mark3 cancels the leading third-order phase error of the
+  lattice advection at tau_g = 1 (Model-II) while Model-I keeps it;
+* constant states are fixed points; a planar tanh is stationary to O((dx/W)^2);
+  phi -> -phi with rho_A <-> rho_B and mirror x -> -x are symmetries;
+* the wall rule equals the periodic run on the mirrored doubled domain.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+CS2 = 1.0 / 3.0
+CX, CY, W = oracle.CX, oracle.CY, oracle.W
+
+
+def _state(p, phi0, vel=None, field=None):
+    if vel is not None:
+        U, V = workloads.separable_field(vel)
+        return oracle.State(p, phi0, U, V, vel["tf"])
+    if field is not None:
+        return oracle.State(p, phi0, *field)
+    return oracle.State(p, phi0)
+
+
+# ------------------------------------------------------------------------- mass
+
+@pytest.mark.parametrize("walls", [0, 1])
+def test_mass_conserved(walls):
+    n = 48
+    w = workloads.vortex(n, period=400, steps=200)
+    p = oracle.Params(nx=n, ny=n, walls=walls, **w.phys)
+    s = _state(p, w.phi0, w.velocity)
+    m0 = s.phi.sum()
+    s.run(200)
+    assert abs(s.phi.sum() - m0) / np.abs(w.phi0).sum() < 1e-13
+
+
+# ------------------------------------------------------------- tau = 1 identity
+
+def _E(a):  # value at x + (1, 0)
+    return np.roll(a, -1, axis=1)
+
+
+def _Wst(a):
+    return np.roll(a, 1, axis=1)
+
+
+def _N(a):
+    return np.roll(a, -1, axis=0)
+
+
+def _S(a):
+    return np.roll(a, 1, axis=0)
+
+
+def _dx(a):
+    return (_E(a) - _Wst(a)) / 3 + (_N(_E(a)) + _S(_E(a)) - _N(_Wst(a)) - _S(_Wst(a))) / 12
+
+
+def _dy(a):
+    return (_N(a) - _S(a)) / 3 + (_N(_E(a)) + _N(_Wst(a)) - _S(_E(a)) - _S(_Wst(a))) / 12
+
+
+def _lap(a):
+    side = _E(a) + _Wst(a) + _N(a) + _S(a)
+    diag = _N(_E(a)) + _N(_Wst(a)) + _S(_E(a)) + _S(_Wst(a))
+    return (4 * side + diag - 20 * a) / 6
+
+
+def macro_step_tau1(phi, U, V, beta, kappa, M, a, b, K, model):
+    mu = 4 * beta * (phi ** 3 - phi) - kappa * _lap(phi)
+    rho = a * phi + b
+    fx = -(phi ** 2 / rho) * _dx(mu)
+    fy = -(phi ** 2 / rho) * _dy(mu)
+    if model == 2:
+        d = _dx(phi * U) + _dy(phi * V)
+        fx = fx + K * _dx(d)
+        fy = fy + K * _dy(d)
+    adv = np.zeros_like(phi)
+    usq = U * U + V * V
+    for i in range(9):
+        cu = CX[i] * U + CY[i] * V
+        term = W[i] * phi * (3 * cu + 4.5 * cu * cu - 1.5 * usq)
+        adv += np.roll(np.roll(term, CY[i], axis=0), CX[i], axis=1)  # value at x - c_i
+    return phi + M * _lap(mu) + adv - 0.5 * (_dx(fx) + _dy(fy))
+
+
+@pytest.mark.parametrize("model", [1, 2])
+def test_tau1_identity_macroscopic_scheme(model):
+    n = 40
+    w = workloads.vortex(n, period=100, steps=30, model=model)
+    p = oracle.Params(nx=n, ny=n, **w.phys)
+    c = oracle.coeffs(p)
+    U, V = workloads.separable_field(w.velocity)
+    s = _state(p, w.phi0, w.velocity)
+    phi = w.phi0.copy()
+    for k in range(30):
+        tf = w.velocity["tf"][k]
+        phi = macro_step_tau1(phi, tf * U, tf * V, c["beta"], c["kappa"], p.mobility, c["a"],
+                              c["b"], c["K"], model)
+    s.run(30)
+    np.testing.assert_allclose(s.phi, phi, atol=1e-13, rtol=0)
+
+
+def test_tau1_zero_velocity_is_explicit_euler_cahn_hilliard():
+    """u = 0, rho_A = rho_B = 1: phi' = phi + (M + phi^2/2) grad.grad mu to O(dx^2) --
+    checked in its exact discrete form (M lap mu - div(F)/2, F = -phi^2 grad mu)."""
+    n = 32
+    rng = np.random.default_rng(5)
+    phi0 = 0.1 * rng.standard_normal((n, n))
+    p = oracle.Params(nx=n, ny=n, rho_a=1.0, rho_b=1.0, mobility=0.02, sigma=0.02)
+    c = oracle.coeffs(p)
+    s = _state(p, phi0).run(1)
+    mu = 4 * c["beta"] * (phi0 ** 3 - phi0) - c["kappa"] * _lap(phi0)
+    want = (phi0 + 0.02 * _lap(mu)
+            + 0.5 * (_dx(phi0 ** 2 * _dx(mu)) + _dy(phi0 ** 2 * _dy(mu))))
+    np.testing.assert_allclose(s.phi, want, atol=1e-15)
+
+
+# ----------------------------------------------------------- linear response
+
+def _mode_amplitude(phi, m, l):
+    ny, nx = phi.shape
+    return 2 * np.fft.fft2(phi)[l % ny, m % nx] / (nx * ny)
+
+
+def _symbols(kx, ky):
+    gx = 2 * math.sin(kx) / 3 + (math.sin(kx + ky) + math.sin(kx - ky)) / 6
+    gy = 2 * math.sin(ky) / 3 + (math.sin(kx + ky) - math.sin(kx - ky)) / 6
+    lam = -(8 * (math.cos(kx) + math.cos(ky)) + 2 * math.cos(kx + ky)
+            + 2 * math.cos(kx - ky) - 20) / 6
+    return np.array([gx, gy]), lam
+
+
+def _linear_update(tau, kx, ky, phibar, u, beta, kappa, eta, a, b, K, model):
+    """9x9 matrix T with g_hat(n+1) = T g_hat(n) for the mode e^{i k.x} (Eq. LB linearised
+    about a uniform state), and the initial vector of g = g^eq(phi0)."""
+    G, lam = _symbols(kx, ky)
+    m = 4 * beta * (3 * phibar ** 2 - 1) + kappa * lam          # mu_hat / phi_hat
+    rho = a * phibar + b
+    F = -(phibar ** 2 / rho) * 1j * G * m                        # F1_hat / phi_hat
+    if model == 2:
+        F = F - K * G * (G @ u)                                   # F2_hat / phi_hat
+    usq = u @ u
+    eq = np.zeros(9, complex)
+    src = np.zeros(9, complex)
+    for i in range(9):
+        cu = CX[i] * u[0] + CY[i] * u[1]
+        s_i = 3 * cu + 4.5 * cu * cu - 1.5 * usq
+        eq[i] = W[i] * eta * m + W[i] * s_i + (1 - eta * m if i == 0 else 0)
+        src[i] = 3 * W[i] * (CX[i] * F[0] + CY[i] * F[1])
+    om = 1 / tau
+    v = om * eq + (1 - om / 2) * src
+    E = np.diag([np.exp(-1j * (kx * CX[i] + ky * CY[i])) for i in range(9)])
+    T = E @ ((1 - om) * np.eye(9) + np.outer(v, np.ones(9)))
+    return T, eq
+
+
+@pytest.mark.parametrize("tau,model", [(1.0, 2), (1.0, 1), (0.8, 2), (1.4, 2), (0.62, 1)])
+def test_linear_response_of_a_mode(tau, model):
+    nx, ny = 32, 24
+    m_, l_ = 3, 2
+    kx, ky = 2 * math.pi * m_ / nx, 2 * math.pi * l_ / ny
+    phibar, eps = 0.8, 1e-6
+    u = np.array([0.03, -0.02])
+    p = oracle.Params(nx=nx, ny=ny, tau_g=tau, model=model, sigma=0.05, width=3.0,
+                      mobility=0.03, rho_a=1.0, rho_b=0.4)
+    c = oracle.coeffs(p)
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    phi0 = phibar + eps * np.cos(kx * x + ky * y)
+    s = oracle.State(p, phi0, np.full((ny, nx), u[0]), np.full((ny, nx), u[1]))
+    nsteps = 5
+    s.run(nsteps)
+    T, eq = _linear_update(tau, kx, ky, phibar, u, c["beta"], c["kappa"], c["eta"], c["a"],
+                           c["b"], c["K"], model)
+    want = np.ones(9) @ np.linalg.matrix_power(T, nsteps) @ eq
+    got = _mode_amplitude(s.phi, m_, l_) / eps
+    assert abs(got - want) < 2e-5 * abs(want)
+    # the uniform background is a fixed point
+    assert abs(s.phi.mean() - phibar) < 1e-12
+    if tau == 1.0:
+        # closed form at tau = 1
+        G, lam = _symbols(kx, ky)
+        mm = 4 * c["beta"] * (3 * phibar ** 2 - 1) + c["kappa"] * lam
+        rho = c["a"] * phibar + c["b"]
+        adv = sum(W[i] * (3 * (CX[i] * u[0] + CY[i] * u[1])
+                          + 4.5 * (CX[i] * u[0] + CY[i] * u[1]) ** 2 - 1.5 * (u @ u))
+                  * np.exp(-1j * (kx * CX[i] + ky * CY[i])) for i in range(9))
+        A = 1 - p.mobility * lam * mm + adv - 0.5 * (phibar ** 2 / rho) * mm * (G @ G)
+        if model == 2:
+            A += 0.5j * c["K"] * (G @ G) * (G @ u)
+        got1 = _mode_amplitude(oracle.State(p, phi0, np.full((ny, nx), u[0]),
+                                            np.full((ny, nx), u[1])).run(1).phi, m_, l_) / eps
+        assert abs(got1 - A) < 2e-6 * abs(A)
+
+
+def test_model2_cancels_third_order_advection_error():
+    """sigma = 0 makes the scheme linear and pure advection; the exact one-step factor is
+    exp(-i k.u).  Model-I carries the (i/6)(k.u)|k|^2 error of D2Q9 advection; the F2
+    term of Eq. mark3 with K(1) = -1/3 removes it."""
+    n = 128
+    y, x = np.mgrid[0:n, 0:n].astype(float)
+    u = np.array([0.04, 0.03])
+    errs = {}
+    for model in (1, 2):
+        for m_ in (4, 8):
+            kx, ky = 2 * math.pi * m_ / n, 2 * math.pi * (m_ // 2) / n
+            p = oracle.Params(nx=n, ny=n, sigma=0.0, model=model, rho_a=1.0, rho_b=1.0)
+            phi0 = np.cos(kx * x + ky * y)
+            s = oracle.State(p, phi0, np.full((n, n), u[0]), np.full((n, n), u[1])).run(1)
+            A = _mode_amplitude(s.phi, m_, m_ // 2)
+            errs[model, m_] = abs(A - np.exp(-1j * (kx * u[0] + ky * u[1])))
+    # Model-I error scales like k^3, Model-II at least like k^4 and is far smaller
+    assert 6 < errs[1, 8] / errs[1, 4] < 10
+    assert errs[2, 8] < 0.15 * errs[1, 8]
+    assert errs[2, 8] / errs[2, 4] > 12
+
+
+# ------------------------------------------------------------- invariants
+
+def test_constant_state_is_fixed_point():
+    n = 16
+    p = oracle.Params(nx=n, ny=n, tau_g=0.9)
+    s = oracle.State(p, np.full((n, n), 0.37), np.full((n, n), 0.03), np.full((n, n), -0.01))
+    g0 = s.g.copy()
+    s.run(10)
+    np.testing.assert_allclose(s.g, g0, atol=1e-15)
+
+
+def test_planar_tanh_is_nearly_stationary():
+    """Eq. analytical with u = 0: stays within O((dx/W)^2) of the tanh, and the deviation
+    falls by more than 4x when W doubles."""
+    devs = []
+    for width in (4.0, 8.0):
+        phi0 = workloads.band(4, 128, width)
+        p = oracle.Params(nx=4, ny=128, width=width)
+        s = oracle.State(p, phi0).run(3000)
+        devs.append(np.abs(s.phi - phi0).max())
+    assert devs[0] < 0.03 and devs[1] < devs[0] / 4
+
+
+def test_free_energy_decreases_without_flow():
+    """Eq. CH with u = 0 is a gradient flow of Eq. freeEnergy.  The initial field is
+    smooth (a few long-wave modes): the gradient form of the energy with the isotropic
+    gradient does not resolve grid-scale noise, whose symbol |G(k)|^2 vanishes at k = pi."""
+    n = 48
+    rng = np.random.default_rng(6)
+    y, x = np.mgrid[0:n, 0:n] * (2 * math.pi / n)
+    phi0 = sum(0.2 * rng.standard_normal() * np.cos(a * x + b * y + rng.uniform(0, 6))
+               for a, b in [(1, 0), (0, 1), (1, 1), (2, -1), (1, 2)])
+    p = oracle.Params(nx=n, ny=n, sigma=0.02, width=3.0)
+    s = oracle.State(p, phi0)
+    e = [oracle.diag(p, s.phi)["energy"]]
+    for _ in range(8):
+        e.append(oracle.diag(p, s.run(25).phi)["energy"])
+    assert all(b <= a for a, b in zip(e, e[1:]))
+
+
+def test_phase_swap_symmetry():
+    """phi -> -phi together with rho_A <-> rho_B maps solutions to solutions."""
+    n = 40
+    w = workloads.vortex(n, period=200, steps=60)
+    base = dict(w.phys)
+    p1 = oracle.Params(nx=n, ny=n, **base)
+    base2 = dict(base, rho_a=base["rho_b"], rho_b=base["rho_a"])
+    p2 = oracle.Params(nx=n, ny=n, **base2)
+    a = _state(p1, w.phi0, w.velocity).run(60).phi
+    b = _state(p2, -w.phi0, w.velocity).run(60).phi
+    np.testing.assert_allclose(a, -b, atol=1e-13)
+
+
+def test_mirror_symmetry():
+    """x -> -x (node i -> nx-1-i) with u -> -u maps solutions to solutions."""
+    n = 40
+    rng = np.random.default_rng(7)
+    phi0 = np.tanh(rng.standard_normal((n, n)))
+    U = 0.03 * rng.uniform(-1, 1, (n, n))
+    V = 0.03 * rng.uniform(-1, 1, (n, n))
+    p = oracle.Params(nx=n, ny=n, tau_g=0.85)
+    a = oracle.State(p, phi0, U, V).run(20).phi
+    b = oracle.State(p, phi0[:, ::-1].copy(), -U[:, ::-1].copy(), V[:, ::-1].copy()).run(20).phi
+    np.testing.assert_allclose(a[:, ::-1], b, atol=1e-13)
+
+
+def test_walls_equal_mirrored_periodic_domain():
+    """A field uniform in x with u = 0 between walls evolves exactly like the periodic
+    run of the domain doubled by reflection (half-way bounce-back equals specular
+    reflection for x-symmetric populations)."""
+    nx, ny = 6, 32
+    phi_col = np.tanh((np.arange(ny) - 11.3) / 2.0)
+    phi0 = np.repeat(phi_col[:, None], nx, axis=1)
+    for model in (1, 2):
+        pw = oracle.Params(nx=nx, ny=ny, walls=1, model=model, tau_g=0.9)
+        pp = oracle.Params(nx=nx, ny=2 * ny, walls=0, model=model, tau_g=0.9)
+        a = oracle.State(pw, phi0).run(50).phi
+        b = oracle.State(pp, np.concatenate([phi0, phi0[::-1]], axis=0)).run(50).phi
+        np.testing.assert_allclose(a, b[:ny], atol=1e-14)
+
+
+def test_translation_returns_and_model2_beats_model1():
+    """Diagonal translation (128^2, R = 25, W = 4, u = (0.04, 0.04)) returns after one
+    period (3200 steps); Model-II tracks the interface better than Model-I at tau = 1."""
+    errs = {}
+    for model in (1, 2):
+        w = workloads.translation(128, 3200, model=model)
+        p = oracle.Params(nx=128, ny=128, **w.phys)
+        s = _state(p, w.phi0, w.velocity).run(3200)
+        errs[model] = oracle.rel_l2(s.phi, w.phi0)
+    assert errs[2] < 0.05
+    assert errs[2] < 0.5 * errs[1]
+
+
+def test_vortex_reversibility_model2_beats_model1():
+    errs = {}
+    for model in (1, 2):
+        w = workloads.vortex(96, period=1600, model=model)
+        p = oracle.Params(nx=96, ny=96, **w.phys)
+        s = _state(p, w.phi0, w.velocity).run(1600)
+        errs[model] = oracle.rel_l2(s.phi, w.phi0)
+    assert errs[2] < 0.05
+    assert errs[2] < errs[1]

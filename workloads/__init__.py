@@ -1,0 +1,224 @@
+"""Seeded synthetic inputs for the lattice Boltzmann Cahn-Hilliard workloads.
+
+This module only describes workloads: initial order-parameter fields, prescribed
+velocity fields and the physical parameters of each run.  It holds none of the
+method's arithmetic (no chemical potential, equilibrium, source or collision), so
+the GPU path and the oracle can both take their inputs from it.
+
+Conventions
+-----------
+* Lattice units: dx = dt = 1.  Node (i, j) of a periodic grid sits at (x, y) = (i, j);
+  with walls in y (walls at y = -1/2 and y = ny - 1/2) node j sits at y = j + 1/2.
+* A field is a float64 array of shape (ny, nx).
+* A separable velocity is a dict of 1-D float64 tables with
+  ``u(x, y, t_n) = tf[n] * ax[x] * ay[y]`` and ``v(x, y, t_n) = tf[n] * bx[x] * by[y]``.
+  Every prescribed flow of Sec. III of the paper has this form.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+
+# --------------------------------------------------------------------------- fields
+
+def tanh_profile(dist, width, phi_a=1.0, phi_b=-1.0):
+    """Planar equilibrium profile of Eq. analytical evaluated at signed distance ``dist``
+    (positive inside phase A)."""
+    return 0.5 * (phi_a + phi_b) + 0.5 * (phi_a - phi_b) * np.tanh(2.0 * dist / width)
+
+
+def circle(nx, ny, cx, cy, radius, width, phi_a=1.0, phi_b=-1.0):
+    """Circular drop of phase A (phi = phi_a inside) centred at (cx, cy) in node units."""
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    r = np.sqrt((x - cx) ** 2 + (y - cy) ** 2)
+    return tanh_profile(radius - r, width, phi_a, phi_b)
+
+
+def band(nx, ny, width, phi_a=1.0, phi_b=-1.0):
+    """Horizontal band of phase A between y = ny/4 and y = 3 ny/4 (two planar interfaces)."""
+    y = np.arange(ny, dtype=np.float64)[:, None] * np.ones((1, nx))
+    d = np.minimum(y - ny / 4.0, 3.0 * ny / 4.0 - y)
+    return tanh_profile(d, width, phi_a, phi_b)
+
+
+def rayleigh_taylor(nx, ny, width, amp_frac=0.1):
+    """Heavy phase (phi = +1) above a cosine-perturbed interface at mid-height:
+    phi = tanh(2 (y - h(x)) / W), h = ny/2 + amp_frac * nx * cos(2 pi x / nx), with
+    cell-centred coordinates (walls at y = 0 and y = ny in these units)."""
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    x += 0.5
+    y += 0.5
+    h = ny / 2.0 + amp_frac * nx * np.cos(2.0 * math.pi * x / nx)
+    return np.tanh(2.0 * (y - h) / width)
+
+
+def random_blobs(n, seed, width):
+    """1-3 circles or ellipses of phase A with radii 0.1-0.3 of the side, union by max."""
+    rng = np.random.default_rng(seed)
+    y, x = np.mgrid[0:n, 0:n].astype(np.float64)
+    phi = -np.ones((n, n))
+    for _ in range(int(rng.integers(1, 4))):
+        cx, cy = rng.uniform(0.25, 0.75, size=2) * n
+        a, b = rng.uniform(0.1, 0.3, size=2) * n
+        th = rng.uniform(0, math.pi)
+        xr = (x - cx) * math.cos(th) + (y - cy) * math.sin(th)
+        yr = -(x - cx) * math.sin(th) + (y - cy) * math.cos(th)
+        r_ell = np.sqrt((xr / a) ** 2 + (yr / b) ** 2)
+        phi = np.maximum(phi, np.tanh(2.0 * min(a, b) * (1.0 - r_ell) / width))
+    return phi
+
+
+def perturbed_uniform(nx, ny, mean, amp, seed):
+    """Uniform state plus seeded uniform noise (used by small parity cases)."""
+    rng = np.random.default_rng(seed)
+    return mean + amp * rng.uniform(-1.0, 1.0, size=(ny, nx))
+
+
+# ----------------------------------------------------------------------- velocities
+
+def uniform_velocity(nx, ny, u0, v0, nsteps):
+    """Constant translation velocity (Sec. III.A)."""
+    return dict(ax=np.full(nx, float(u0)), ay=np.ones(ny), bx=np.full(nx, float(v0)),
+                by=np.ones(ny), tf=np.ones(nsteps + 1))
+
+
+def single_vortex(n, umax, period, nsteps):
+    """Time-reversing single vortex: psi = A sin^2(pi x/L) sin^2(pi y/L) cos(pi t/T),
+    u = d psi/dy, v = -d psi/dx, with A = umax L / pi so that max |u| = umax."""
+    L = float(n)
+    A = umax * L / math.pi
+    x = np.arange(n, dtype=np.float64)
+    k = math.pi / L
+    return dict(ax=A * k * np.sin(k * x) ** 2, ay=np.sin(2 * k * x),
+                bx=-A * k * np.sin(2 * k * x), by=np.sin(k * x) ** 2,
+                tf=np.cos(math.pi * np.arange(nsteps + 1) / period))
+
+
+def rigid_rotation(n, u0, nsteps):
+    """Zalesak rotation field of Sec. III.B: u = -U0 pi (y/L - 1/2), v = U0 pi (x/L - 1/2)."""
+    x = np.arange(n, dtype=np.float64)
+    return dict(ax=np.full(n, -u0 * math.pi), ay=x / n - 0.5, bx=u0 * math.pi * (x / n - 0.5),
+                by=np.ones(n), tf=np.ones(nsteps + 1))
+
+
+def shear_reversal(n, u0, period, nsteps):
+    """Shear flow of Sec. III.C, reversed at t = T."""
+    x = np.arange(n, dtype=np.float64)
+    s = math.pi * (x / n - 0.5)
+    t = np.arange(nsteps + 1)
+    return dict(ax=-u0 * math.pi * np.cos(s), ay=np.sin(s), bx=u0 * math.pi * np.sin(s),
+                by=np.cos(s), tf=np.where(t < period, 1.0, -1.0))
+
+
+def deformation(n, u0, nvort, period, nsteps):
+    """Deformation field of Sec. III.D with n vortices and reversal time T0."""
+    x = np.arange(n, dtype=np.float64)
+    s = nvort * math.pi * (x / n + 0.5)
+    return dict(ax=-u0 * np.sin(s), ay=np.sin(s), bx=-u0 * np.cos(s), by=np.cos(s),
+                tf=np.cos(math.pi * np.arange(nsteps + 1) / period))
+
+
+def separable_field(tables):
+    """Full (U, V) base fields (ny, nx) of a separable velocity at factor 1."""
+    U = np.outer(tables["ay"], tables["ax"])
+    V = np.outer(tables["by"], tables["bx"])
+    return U, V
+
+
+def random_stream_function(n, modes, seed, umax):
+    """Divergence-free field from psi = sum a_kl sin(2 pi k x/n) sin(2 pi l y/n),
+    k, l = 1..modes, a_kl ~ N(0,1)/(k^2+l^2) from the seed, scaled to max |u| = umax
+    (the scale is computed once from the sampled field and then fixed)."""
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((modes, modes)) / (
+        np.arange(1, modes + 1)[:, None] ** 2 + np.arange(1, modes + 1)[None, :] ** 2)
+    return stream_function_field(n, a, umax)
+
+
+def stream_function_field(n, coeffs, umax=None):
+    """u = d psi/dy, v = -d psi/dx of psi = sum_kl c_kl sin(2 pi k x/n) sin(2 pi l y/n)."""
+    modes = coeffs.shape[0]
+    x = np.arange(n, dtype=np.float64)
+    kk = 2 * math.pi * np.arange(1, modes + 1) / n
+    sx, cx = np.sin(np.outer(kk, x)), np.cos(np.outer(kk, x))  # (modes, n)
+    # u = sum c_kl sin(k x) l cos(l y),  v = -sum c_kl k cos(k x) sin(l y)
+    U = np.einsum("kl,lj,ki->ji", coeffs * kk[None, :], cx, sx)
+    V = -np.einsum("kl,lj,ki->ji", coeffs * kk[:, None], sx, cx)
+    if umax is not None:
+        s = umax / max(np.abs(U).max(), np.abs(V).max())
+        U, V = U * s, V * s
+    return U, V
+
+
+# -------------------------------------------------------------------------- configs
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    nx: int
+    ny: int
+    steps: int
+    phys: dict           # keyword arguments of the solver parameters
+    phi0: np.ndarray
+    velocity: dict | None = None     # separable tables, or None
+    field: tuple | None = None       # stored (U, V) base fields, or None
+
+
+# Prescribed-flow defaults of Sec. III: tau_g = 1, sigma = 0.01, rho_A = 1, rho_B = 0.5.
+PRESCRIBED = dict(tau_g=1.0, mobility=0.01, sigma=0.01, width=4.0, phi_a=1.0, phi_b=-1.0,
+                  rho_a=1.0, rho_b=0.5, model=2)
+
+
+def translation(n=128, steps=3200, model=2):
+    """Diagonal translation of a circle (radius 25 at n = 128) at u = (0.04, 0.04):
+    one period is n / 0.04 = 3200 steps at n = 128."""
+    phys = dict(PRESCRIBED, model=model)
+    return Workload("translation%d" % n, n, n, steps, phys,
+                    circle(n, n, n / 2, n / 2, 25.0 * n / 128, 4.0),
+                    uniform_velocity(n, n, 0.04, 0.04, steps))
+
+
+def vortex(n=512, period=20000, steps=None, radius_frac=77.0 / 512, model=2):
+    """Circle (radius 77 at n = 512, centre (n/2, 3n/4)) in the time-reversing single vortex
+    with max |u| = 0.05; the field returns at t = period."""
+    steps = period if steps is None else steps
+    phys = dict(PRESCRIBED, model=model)
+    return Workload("vortex%d" % n, n, n, steps, phys,
+                    circle(n, n, n / 2, 3 * n / 4, radius_frac * n, 4.0),
+                    single_vortex(n, 0.05, period, max(steps, period)))
+
+
+def metric2048(steps=1000):
+    """The throughput workload: 2048^2 periodic, Model-II, tau_g = 1, circle of radius
+    0.15 L at (L/2, 3L/4) in the single vortex (max |u| = 0.05, T = 80000)."""
+    n = 2048
+    return Workload("vortex2048", n, n, steps, dict(PRESCRIBED),
+                    circle(n, n, n / 2, 3 * n / 4, 0.15 * n, 4.0),
+                    single_vortex(n, 0.05, 80000, max(steps, 1)))
+
+
+def rt_params(nx=256, atwood=0.5, reynolds=3000.0, sqrt_gl=0.04, sigma=5e-5, width=4.0,
+              peclet=1000.0):
+    """Rayleigh-Taylor parameters (Sec. III.E) from the dimensionless groups.
+    rho_h = 1, rho_l = rho_h (1 - At)/(1 + At); g = sqrt_gl^2 / L;
+    nu = L sqrt(At g L / (1 + At)) / Re, tau_f = 1/2 + 3 nu;
+    Pe = U* W / (M beta (phi_A - phi_B)^2) with U* = sqrt(g L), so with
+    beta = 12 sigma / (16 W) this gives M = U* W / (Pe * 12 sigma / (16 W) * 4)."""
+    L = float(nx)
+    g = sqrt_gl ** 2 / L
+    nu = L * math.sqrt(atwood * g * L / (1.0 + atwood)) / reynolds
+    rho_h = 1.0
+    rho_l = rho_h * (1.0 - atwood) / (1.0 + atwood)
+    beta_lit = 12.0 * sigma / (width * 16.0)   # Pe's beta for phi_A - phi_B = 2
+    mob = sqrt_gl * width / (peclet * beta_lit * 4.0)
+    return dict(tau_g=1.0, mobility=mob, sigma=sigma, width=width, phi_a=1.0, phi_b=-1.0,
+                rho_a=rho_h, rho_b=rho_l, model=2, tau_f=0.5 + 3.0 * nu, gravity=g)
+
+
+def rayleigh_taylor_case(nx=256, ny=1024, steps=40000, **kw):
+    phys = rt_params(nx=nx, **kw)
+    return Workload("rayleigh_taylor%dx%d" % (nx, ny), nx, ny, steps, phys,
+                    rayleigh_taylor(nx, ny, phys["width"]))
