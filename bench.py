@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Throughput of the fused FP32 phase-field step on one MI355X.
+
+Workload: 2048^2 periodic lattice, Model-II, tau_g = 1, M = 0.01, sigma = 0.01, W = 4,
+a circle of radius 0.15 L at (L/2, 3L/4) in the time-reversing single vortex
+(max |u| = 0.05, T = 80000 steps), velocity from separable 1-D tables (seeded
+synthetic inputs shaped like the paper's deformation tests).
+
+A step is one launch of the fused kernel (pull, phi, mu, F1 + F2, collision,
+store) over the whole lattice.  Prints one JSON line:
+  value        MLUPS = nx*ny*steps / time of the timed steps (inputs resident in HBM)
+  roofline     algorithmic bytes (72 B per node update: 9 float32 populations read and
+               9 written) / average kernel duration from HIP events, against the
+               8 TB/s HBM peak; traffic = measured HBM bytes per launch from the committed
+               rocprofv3 counter summary (null when the kernel source changed since)
+  cpu_baseline the FP64 oracle on the host cores on a bounded number of steps
+  accuracy     relative L2 of phi after 1000 steps against stored FP64 oracle samples
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("MLUPS and % HBM peak (FP32 fused step, 2048^2) vs FP64 oracle accuracy; "
+          "adjoint ms")
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_LU = 72.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1805_00007_amd", "csrc", "lbm_ch_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "phi_step_vortex2048_traffic.txt")
+GOLDEN = os.path.join(ROOT, "tests", "golden", "vortex2048_oracle_1000.npz")
+
+
+def kernel_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """Bytes per launch from the committed counter summary, if the kernel is unchanged."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha") != kernel_sha():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(w, steps):
+    import numpy as np
+    import oracle
+    import workloads
+    oracle.build(force=False)
+    p = oracle.Params(nx=w.nx, ny=w.ny, **w.phys)
+    U, V = workloads.separable_field(w.velocity)
+    s = oracle.State(p, w.phi0, U, V, w.velocity["tf"])
+    t0 = time.perf_counter()
+    s.run(steps)
+    dt = time.perf_counter() - t0
+    assert np.isfinite(s.g).all()
+    return {"value": round(w.nx * w.ny * steps / dt / 1e6, 3), "unit": "MLUPS",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "%d steps of the %dx%d workload (FP64, OpenMP over rows), %.1f s"
+                      % (steps, w.nx, w.ny, dt)}
+
+
+def accuracy(lbm, w, torch):
+    """phi after 1000 steps at stored oracle sample points (tests/golden)."""
+    import numpy as np
+    if not os.path.exists(GOLDEN):
+        return None
+    g = np.load(GOLDEN)
+    s = lbm.solver_for(w)
+    s.step(int(g["steps"]))
+    d = s.diagnostics()
+    phi = s.phi().double().cpu().numpy().ravel()
+    idx = g["index"]
+    ref = g["phi"]
+    rel = float(np.sqrt(((phi[idx] - ref) ** 2).sum() / (ref ** 2).sum()))
+    drift = abs(d["mass"] - float(g["mass0"])) / float(g["abs_mass0"])
+    s.close()
+    return {"steps": int(g["steps"]), "rel_l2_phi_sampled": rel, "samples": int(len(idx)),
+            "max_abs_err": float(np.abs(phi[idx] - ref).max()), "mass_drift": drift}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--cpu-steps", type=int, default=25,
+                    help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--no-accuracy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only; the multi-GPU domain "
+              "decomposition is a design, not a runnable path (--gpus must be 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads
+    import paper_1805_00007_amd as lbm
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = workloads.metric2048(steps=args.steps + args.warmup)
+    s = lbm.solver_for(w)
+    stream = s.stream
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+
+    # timed region: exactly `steps` steps, bracketed by synchronisation
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    t0 = time.perf_counter()
+    s.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_ms = ev0.elapsed_time(ev1)
+
+    # average duration of one launch of the fused kernel: HIP events around single
+    # launches on the stream the kernel runs on
+    nprobe = min(200, max(20, args.steps // 5))
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(nprobe)]
+    for a, b in evs:
+        a.record(stream)
+        s.step(1)
+        b.record(stream)
+    torch.cuda.synchronize()
+    k_ms = sum(a.elapsed_time(b) for a, b in evs) / nprobe
+    d = s.diagnostics()
+    assert d["nonfinite"] == 0, "non-finite phi in the benchmark run"
+    s.close()
+
+    nodes = w.nx * w.ny
+    mlups = nodes * args.steps / (t_ms * 1e-3) / 1e6
+    algo = BYTES_PER_LU * nodes
+    achieved = algo / (k_ms * 1e-3) / 1e9
+    traffic = measured_traffic()
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "model": "II", "tau_g": 1.0,
+                   "velocity": "single vortex, separable tables", "boundary": "periodic",
+                   "storage": "f32"},
+        "effective_GBps": round(mlups * BYTES_PER_LU / 1e3, 1),
+        "hbm_frac_effective": round(mlups * BYTES_PER_LU / 1e3 / HBM_PEAK_GBS, 4),
+        "wall_s_timed": round(wall, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_phi_step",
+                     "kernel_avg_us": round(k_ms * 1e3, 2),
+                     "algorithmic_bytes_per_launch": algo},
+    }
+    if not args.no_accuracy:
+        out["accuracy"] = accuracy(lbm, workloads.metric2048(steps=1000), torch)
+    if args.cpu_steps > 0:
+        out["cpu_baseline"] = cpu_baseline(workloads.metric2048(steps=args.cpu_steps),
+                                           args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

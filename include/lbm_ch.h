@@ -1,0 +1,182 @@
+/*
+ * lbm_ch -- C ABI of the MI355X (gfx950) lattice Boltzmann solver for the
+ * Cahn-Hilliard equation of Zhang, Guo & Liang, "A high-order lattice Boltzmann
+ * model for the Cahn-Hilliard equation" (arXiv:1805.00007).
+ *
+ * What one time step computes (Sec. II of the paper, in this order):
+ *   phi = sum_i g_i                                            Eq. macroscopicg
+ *   mu  = df/dphi - kappa lap(phi), f of Eq. bulk,
+ *         beta and kappa from sigma and W                      Eqs. bulk, mu, betakappa
+ *   F1  = (phi/rho)(F_s + F_b - grad p), F_s = -phi grad mu,
+ *         rho = a phi + b                                      Eqs. NS, rho, t0-phiu
+ *   F2  = 3 cs^2 K grad(div(phi u))   (Model-II only)          Eq. mark3, K below Eq. F2-1
+ *   g_i^eq, S_i = w_i c_i.F/cs^2                               Eqs. geq, liangFi
+ *   g_i(x + c_i, t + 1) = g_i - (g_i - g_i^eq)/tau_g
+ *                         + (1 - 1/(2 tau_g)) S_i              Eq. LB
+ * on the D2Q9 lattice of Sec. II.B (c_0..c_8 = (0,0) (1,0) (0,1) (-1,0) (0,-1)
+ * (1,1) (-1,1) (-1,-1) (1,-1)).  The gradient and Laplacian are the isotropic
+ * central schemes named in Sec. III:
+ *   d_a psi = (1/cs^2) sum_i w_i c_ia psi(x + c_i),
+ *   lap psi = (2/cs^2) sum_i w_i [psi(x + c_i) - psi(x)].
+ * The velocity u is prescribed (the tests of Sec. III.A-D; then grad p = 0 and
+ * F_b = 0) or comes from a coupled Navier-Stokes D2Q9 step (the Rayleigh-Taylor
+ * test of Sec. III.E).  The paper calls that NS LBE standard without printing it;
+ * the one used is a pressure-based incompressible BGK model:
+ *   f_0^eq = (w_0 - 1) p/cs^2 + rho w_0 s_0(u),  f_i^eq = w_i p/cs^2 + rho w_i s_i(u),
+ *   s_i(u) = 3 c_i.u + 4.5 (c_i.u)^2 - 1.5 u^2,
+ *   G_i = w_i [ 3 (c_i - u).F + 9 (c_i.u)(c_i.F) + 3 (c_i.u)(c_i.grad rho) ],
+ *   f_i(x + c_i, t + 1) = f_i - (f_i - f_i^eq)/tau_f + (1 - 1/(2 tau_f)) G_i,
+ *   F = F_s + F_b + u a M lap(mu),  F_b = (rho accel_x, -(rho - (rho_A + rho_B)/2) g),
+ *   rho u = sum_i c_i f_i + F/2,
+ *   p = cs^2/(1 - w_0) [sum_{i>0} f_i + u.grad rho/2 + rho w_0 s_0(u)],
+ * with kinematic viscosity nu = cs^2 (tau_f - 1/2).
+ *
+ * Boundaries: x is periodic.  y is periodic, or bounded by no-slip walls half a
+ * node below row 0 and above row ny-1: populations leaving through a wall come back
+ * in the opposite direction at the same node (half-way bounce-back), and the
+ * stencils see mirror images across the walls (phi, mu, p even; u, v odd).
+ *
+ * Memory and ownership
+ * --------------------
+ * The library never allocates device memory.  The caller supplies one device
+ * workspace of lbm_ch_workspace_bytes() bytes (256-byte aligned) and keeps it,
+ * and every device array it passes to lbm_ch_init, alive until lbm_ch_destroy.
+ * Device arrays are float32, row-major (index y*nx + x), unless stated.  Host
+ * arrays are copied during the call.  The context itself is host memory owned by
+ * the library.
+ *
+ * Streams and errors
+ * ------------------
+ * Calls that take a stream enqueue their device work on it and return without
+ * waiting for it, except lbm_ch_check_finite, which synchronises that stream.
+ * Every call returns an lbm_ch_status; no exception crosses the ABI.  On an
+ * invalid argument nothing is enqueued and the context is unchanged.  A HIP
+ * runtime error is returned as LBM_CH_EHIP (lbm_ch_last_hip_error() gives the
+ * code).  Calls on one context must not overlap in time from several host threads.
+ */
+#ifndef LBM_CH_H
+#define LBM_CH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ch_ctx lbm_ch_ctx; /* opaque, host-side */
+
+typedef enum {
+  LBM_CH_OK = 0,
+  LBM_CH_EINVAL = -1,       /* invalid parameter, size, pointer or alignment        */
+  LBM_CH_EUNSUPPORTED = -2, /* valid but not implemented combination                */
+  LBM_CH_EHIP = -3,         /* HIP runtime error                                    */
+  LBM_CH_ENONFINITE = -4,   /* the order parameter holds NaN or Inf                 */
+  LBM_CH_ESTATE = -5        /* call out of order (e.g. NULL or destroyed context)   */
+} lbm_ch_status;
+
+enum {
+  LBM_CH_VEL_NONE = 0,      /* u = 0                                                */
+  LBM_CH_VEL_SEPARABLE = 1, /* u = tf[n] ax[x] ay[y], v = tf[n] bx[x] by[y]         */
+  LBM_CH_VEL_FIELD = 2,     /* u = tf[n] ux[y*nx+x], v = tf[n] uy[y*nx+x]           */
+  LBM_CH_VEL_NS = 3         /* u and p from the coupled Navier-Stokes step          */
+};
+
+enum {
+  LBM_CH_STORE_F32 = 0      /* populations stored as float32                         */
+};
+
+typedef struct {
+  int32_t nx, ny;         /* lattice nodes; 4 <= nx, ny and 9*nx*ny < 2^31          */
+  int32_t walls;          /* 0: periodic in y; 1: no-slip walls (see above)         */
+  int32_t model;          /* 1: F = F1 (Model-I); 2: F = F1 + F2 (Model-II), Eq. reFi */
+  int32_t velocity_mode;  /* LBM_CH_VEL_*                                           */
+  int32_t storage;        /* LBM_CH_STORE_*                                         */
+  double tau_g;           /* relaxation time of g, > 1/2 (Eq. LB)                   */
+  double mobility;        /* M = cs^2 eta (tau_g - 1/2)                             */
+  double sigma, width;    /* surface tension and interface width W (Eq. betakappa)  */
+  double phi_a, phi_b;    /* bulk values of the two phases (Eq. bulk), phi_a != phi_b */
+  double rho_a, rho_b;    /* densities of the two phases (Eq. rho), > 0             */
+  double tau_f;           /* NS relaxation time, > 1/2 (LBM_CH_VEL_NS only)        */
+  double gravity;         /* NS: g along -y, as the force -(rho - rho_mean) g      */
+  double accel_x;         /* NS: uniform acceleration along +x, force rho accel_x  */
+} lbm_ch_params;
+
+typedef struct {
+  /* LBM_CH_VEL_SEPARABLE: device tables ax[nx], ay[ny], bx[nx], by[ny].            */
+  const float *ax, *ay, *bx, *by;
+  /* LBM_CH_VEL_FIELD: device fields ux[nx*ny], uy[nx*ny].
+   * LBM_CH_VEL_NS: optional initial velocity fields (NULL: fluid at rest).       */
+  const float *ux, *uy;
+  /* Host array of per-step factors tf[n], n = 0.. (copied).  NULL: tf = 1.  Steps
+   * beyond the table reuse its last entry.  Not used by LBM_CH_VEL_NS.           */
+  const double* time_factor;
+  int64_t n_time_factor;
+} lbm_ch_velocity;
+
+/* Bytes of device workspace lbm_ch_init needs for these parameters, or 0 if the
+ * parameters are invalid. */
+size_t lbm_ch_workspace_bytes(const lbm_ch_params* p);
+
+/* Validate the parameters, bind the workspace and velocity inputs, and enqueue the
+ * initial state on `stream`: g_i = g_i^eq(phi0, mu[phi0], u(t_0)) with no source
+ * term (and f_i = f_i^eq(p = 0, rho(phi0), u0) with NS).  phi0 is a device array of
+ * nx*ny floats; it is read during the call's device work only.  *out receives the
+ * context.  Errors: LBM_CH_EINVAL for tau_g <= 1/2, tau_f <= 1/2 (NS), sizes out of
+ * range, phi_a == phi_b, rho_a or rho_b <= 0, model not 1 or 2, a NULL or unaligned
+ * (4-byte) array the mode needs, a workspace smaller than lbm_ch_workspace_bytes or
+ * not 256-byte aligned; LBM_CH_EUNSUPPORTED for a storage mode not built. */
+int lbm_ch_init(lbm_ch_ctx** out, const lbm_ch_params* p, const lbm_ch_velocity* vel,
+                void* workspace, size_t workspace_bytes, const float* phi0,
+                hipStream_t stream);
+
+/* Enqueue nsteps >= 0 time steps (Eq. LB plus streaming; with NS also the coupled
+ * NS step) on `stream`.  The step counter n advances by nsteps. */
+int lbm_ch_step(lbm_ch_ctx* ctx, int64_t nsteps, hipStream_t stream);
+
+/* Enqueue the macroscopic fields of the current state into caller device arrays of
+ * nx*ny floats (any may be NULL): phi (Eq. macroscopicg), mu (Eq. mu), the velocity
+ * u, v at the current time and the pressure p (0 for a prescribed velocity). */
+int lbm_ch_moments(lbm_ch_ctx* ctx, float* phi, float* mu, float* ux, float* uy, float* p,
+                   hipStream_t stream);
+
+/* Enqueue FP64 reductions of the current order parameter into the caller device
+ * array out[8]: sum phi, sum |phi|, free energy (Eq. freeEnergy with the isotropic
+ * gradient), sum (phi - phi_ref)^2, sum phi_ref^2, max phi, min phi, number of
+ * non-finite values (finite values only enter the other entries).  phi_ref may be
+ * NULL (entries 3 and 4 are then 0).  The reduction order is fixed, so results are
+ * bitwise reproducible. */
+int lbm_ch_diagnostics(lbm_ch_ctx* ctx, const float* phi_ref, double* out, hipStream_t stream);
+
+/* Synchronise `stream`, count non-finite phi values and return LBM_CH_ENONFINITE if
+ * there are any, LBM_CH_OK otherwise. */
+int lbm_ch_check_finite(lbm_ch_ctx* ctx, hipStream_t stream);
+
+/* Current step counter n. */
+int64_t lbm_ch_step_count(const lbm_ch_ctx* ctx);
+
+/* Bytes of the solver state (populations g, and f with NS). */
+size_t lbm_ch_state_bytes(const lbm_ch_ctx* ctx);
+
+/* Enqueue a device-to-device copy of the state into dst (checkpoint), or from src
+ * (resume; the step counter is set to `step`).  Sizes must equal
+ * lbm_ch_state_bytes. */
+int lbm_ch_save_state(lbm_ch_ctx* ctx, void* dst, size_t bytes, hipStream_t stream);
+int lbm_ch_load_state(lbm_ch_ctx* ctx, const void* src, size_t bytes, int64_t step,
+                      hipStream_t stream);
+
+/* Release the context (host memory only).  NULL is accepted. */
+int lbm_ch_destroy(lbm_ch_ctx* ctx);
+
+/* Static description of a status code; thread-safe. */
+const char* lbm_ch_strerror(int status);
+
+/* hipError_t of the last LBM_CH_EHIP returned on this thread. */
+int lbm_ch_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_CH_H */

@@ -1,0 +1,257 @@
+"""MI355X (gfx950) lattice Boltzmann solver for the Cahn-Hilliard equation of
+Zhang, Guo & Liang, arXiv:1805.00007.
+
+A thin ctypes binding of the C ABI in ``include/lbm_ch.h`` (same call names).  Every
+step of the method runs in the HIP kernels of ``liblbm_ch.so``; this module only
+marshals arguments.  PyTorch provides device memory (the workspace and the caller's
+arrays are CUDA tensors) and the stream (the current torch stream).  Importing the
+module does not need a GPU; calls that reach the library raise if the built library
+is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm_ch.so")
+
+# Status codes and modes (include/lbm_ch.h).
+OK, EINVAL, EUNSUPPORTED, EHIP, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5
+VEL_NONE, VEL_SEPARABLE, VEL_FIELD, VEL_NS = 0, 1, 2, 3
+STORE_F32 = 0
+
+# Every symbol include/lbm_ch.h declares.
+EXPORTS = ("lbm_ch_workspace_bytes", "lbm_ch_init", "lbm_ch_step", "lbm_ch_moments",
+           "lbm_ch_diagnostics", "lbm_ch_check_finite", "lbm_ch_step_count",
+           "lbm_ch_state_bytes", "lbm_ch_save_state", "lbm_ch_load_state", "lbm_ch_destroy",
+           "lbm_ch_strerror", "lbm_ch_last_hip_error")
+
+
+class LbmChError(RuntimeError):
+    def __init__(self, status, call):
+        self.status = status
+        msg = lib().lbm_ch_strerror(status).decode()
+        if status == EHIP:
+            msg += " (hipError %d)" % lib().lbm_ch_last_hip_error()
+        super().__init__("%s: %s (%d)" % (call, msg, status))
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("walls", ctypes.c_int32),
+                ("model", ctypes.c_int32), ("velocity_mode", ctypes.c_int32),
+                ("storage", ctypes.c_int32),
+                ("tau_g", ctypes.c_double), ("mobility", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("width", ctypes.c_double),
+                ("phi_a", ctypes.c_double), ("phi_b", ctypes.c_double),
+                ("rho_a", ctypes.c_double), ("rho_b", ctypes.c_double),
+                ("tau_f", ctypes.c_double), ("gravity", ctypes.c_double),
+                ("accel_x", ctypes.c_double)]
+
+
+class Velocity(ctypes.Structure):
+    _fields_ = [("ax", ctypes.c_void_p), ("ay", ctypes.c_void_p), ("bx", ctypes.c_void_p),
+                ("by", ctypes.c_void_p), ("ux", ctypes.c_void_p), ("uy", ctypes.c_void_p),
+                ("time_factor", ctypes.POINTER(ctypes.c_double)),
+                ("n_time_factor", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("liblbm_ch.so is not built: run paper_1805_00007_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        PP = ctypes.POINTER(Params)
+        L.lbm_ch_workspace_bytes.argtypes = [PP]
+        L.lbm_ch_workspace_bytes.restype = ctypes.c_size_t
+        L.lbm_ch_init.argtypes = [ctypes.POINTER(vp), PP, ctypes.POINTER(Velocity), vp,
+                                  ctypes.c_size_t, vp, vp]
+        L.lbm_ch_step.argtypes = [vp, i64, vp]
+        L.lbm_ch_moments.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.lbm_ch_diagnostics.argtypes = [vp, vp, vp, vp]
+        L.lbm_ch_check_finite.argtypes = [vp, vp]
+        L.lbm_ch_step_count.argtypes = [vp]
+        L.lbm_ch_step_count.restype = i64
+        L.lbm_ch_state_bytes.argtypes = [vp]
+        L.lbm_ch_state_bytes.restype = ctypes.c_size_t
+        L.lbm_ch_save_state.argtypes = [vp, vp, ctypes.c_size_t, vp]
+        L.lbm_ch_load_state.argtypes = [vp, vp, ctypes.c_size_t, i64, vp]
+        L.lbm_ch_destroy.argtypes = [vp]
+        L.lbm_ch_strerror.argtypes = [i32]
+        L.lbm_ch_strerror.restype = ctypes.c_char_p
+        L.lbm_ch_last_hip_error.restype = i32
+        for name in EXPORTS:
+            assert hasattr(L, name), name
+        _lib = L
+    return _lib
+
+
+def _check(status, call):
+    if status != OK:
+        raise LbmChError(status, call)
+
+
+def make_params(nx, ny, *, walls=0, model=2, velocity_mode=VEL_SEPARABLE, storage=STORE_F32,
+                tau_g=1.0, mobility=0.01, sigma=0.01, width=4.0, phi_a=1.0, phi_b=-1.0,
+                rho_a=1.0, rho_b=0.5, tau_f=1.0, gravity=0.0, accel_x=0.0, ns=None):
+    if ns:
+        velocity_mode = VEL_NS
+    return Params(nx, ny, walls, model, velocity_mode, storage, tau_g, mobility, sigma, width,
+                  phi_a, phi_b, rho_a, rho_b, tau_f, gravity, accel_x)
+
+
+def workspace_bytes(params: Params) -> int:
+    return lib().lbm_ch_workspace_bytes(ctypes.byref(params))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One lattice: ``Solver(nx, ny, phi0, velocity=..., **params)``.
+
+    ``phi0``: (ny, nx) array or tensor.  ``velocity``: a dict of separable tables
+    ``ax, ay, bx, by`` (and ``tf``), or ``field=(U, V)`` (with optional ``tf``), or
+    ``ns=True`` for the coupled Navier-Stokes velocity (optional ``u0=(U, V)``).
+    Keyword parameters are those of ``lbm_ch_params``.
+    """
+
+    def __init__(self, nx, ny, phi0, velocity=None, field=None, tf=None, u0=None,
+                 device="cuda", stream=None, **kw):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        L = lib()
+        if field is not None:
+            mode = VEL_FIELD
+        elif kw.get("ns"):
+            mode = VEL_NS
+        elif velocity is not None:
+            mode = VEL_SEPARABLE
+        else:
+            mode = VEL_NONE
+        kw.pop("ns", None)
+        self.params = make_params(nx, ny, velocity_mode=mode, **kw)
+        nbytes = L.lbm_ch_workspace_bytes(ctypes.byref(self.params))
+        if nbytes == 0:
+            raise LbmChError(EINVAL, "lbm_ch_workspace_bytes")
+        f32 = dict(dtype=torch.float32, device=self.device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.nx, self.ny = nx, ny
+        self._keep = []
+        vel = Velocity()
+        if mode == VEL_SEPARABLE:
+            tabs = [torch.as_tensor(np.asarray(velocity[k]), **f32).contiguous()
+                    for k in ("ax", "ay", "bx", "by")]
+            self._keep += tabs
+            vel.ax, vel.ay, vel.bx, vel.by = [t.data_ptr() for t in tabs]
+            if tf is None:
+                tf = velocity.get("tf")
+        elif mode == VEL_FIELD:
+            U, V = [torch.as_tensor(np.asarray(a), **f32).contiguous() for a in field]
+            self._keep += [U, V]
+            vel.ux, vel.uy = U.data_ptr(), V.data_ptr()
+        elif mode == VEL_NS and u0 is not None:
+            U, V = [torch.as_tensor(np.asarray(a), **f32).contiguous() for a in u0]
+            self._keep += [U, V]
+            vel.ux, vel.uy = U.data_ptr(), V.data_ptr()
+        tfa = None
+        if tf is not None:
+            tfa = np.ascontiguousarray(tf, dtype=np.float64)
+            vel.time_factor = tfa.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            vel.n_time_factor = len(tfa)
+        phi0 = torch.as_tensor(phi0, **f32).contiguous()
+        assert phi0.shape == (ny, nx)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        _check(L.lbm_ch_init(ctypes.byref(ctx), ctypes.byref(self.params), ctypes.byref(vel),
+                             ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                             ctypes.c_void_p(phi0.data_ptr()), self._s()), "lbm_ch_init")
+        self._phi0 = phi0  # read by the enqueued init; kept until the stream passes it
+        self.ctx = ctx
+
+    def _s(self):
+        return ctypes.c_void_p(self.stream.cuda_stream)
+
+    def step(self, n=1):
+        _check(lib().lbm_ch_step(self.ctx, int(n), self._s()), "lbm_ch_step")
+        return self
+
+    @property
+    def step_count(self):
+        return lib().lbm_ch_step_count(self.ctx)
+
+    def moments(self, which=("phi", "mu", "u", "v", "p")):
+        t = self.torch
+        out = {k: t.empty((self.ny, self.nx), dtype=t.float32, device=self.device)
+               for k in which}
+        _check(lib().lbm_ch_moments(self.ctx, _ptr(out.get("phi")), _ptr(out.get("mu")),
+                                    _ptr(out.get("u")), _ptr(out.get("v")), _ptr(out.get("p")),
+                                    self._s()), "lbm_ch_moments")
+        return out
+
+    def phi(self):
+        return self.moments(("phi",))["phi"]
+
+    def diagnostics(self, phi_ref=None):
+        t = self.torch
+        out = t.empty(8, dtype=t.float64, device=self.device)
+        ref = None
+        if phi_ref is not None:
+            ref = t.as_tensor(phi_ref, dtype=t.float32, device=self.device).contiguous()
+        _check(lib().lbm_ch_diagnostics(self.ctx, _ptr(ref), _ptr(out), self._s()),
+               "lbm_ch_diagnostics")
+        self.stream.synchronize()
+        v = out.cpu().numpy()
+        keys = ("mass", "abs_mass", "energy", "err2", "ref2", "max", "min", "nonfinite")
+        return dict(zip(keys, v.tolist()))
+
+    def check_finite(self):
+        return lib().lbm_ch_check_finite(self.ctx, self._s())
+
+    def save_state(self):
+        t = self.torch
+        n = lib().lbm_ch_state_bytes(self.ctx)
+        buf = t.empty(n, dtype=t.uint8, device=self.device)
+        _check(lib().lbm_ch_save_state(self.ctx, _ptr(buf), n, self._s()), "lbm_ch_save_state")
+        return buf, self.step_count
+
+    def load_state(self, buf, step):
+        _check(lib().lbm_ch_load_state(self.ctx, _ptr(buf), buf.numel(), int(step), self._s()),
+               "lbm_ch_load_state")
+        return self
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.stream.synchronize()
+            lib().lbm_ch_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solver_for(workload, device="cuda", **over):
+    """Solver for a workloads.Workload (separable velocity, field or NS)."""
+    kw = dict(workload.phys)
+    kw.update(over)
+    if kw.get("tau_f") is not None and kw.get("gravity") is not None and "ns" not in kw \
+            and workload.velocity is None and workload.field is None:
+        kw["ns"] = True
+    if workload.field is not None:
+        return Solver(workload.nx, workload.ny, workload.phi0, field=workload.field,
+                      device=device, **kw)
+    return Solver(workload.nx, workload.ny, workload.phi0, velocity=workload.velocity,
+                  device=device, **kw)

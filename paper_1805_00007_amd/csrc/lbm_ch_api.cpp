@@ -1,0 +1,420 @@
+// Host implementation of the C ABI declared in include/lbm_ch.h: parameter checks and
+// derivation (Eqs. betakappa, rho, the mobility relation below Eq. phit3, and K below
+// Eq. F2-1), the workspace layout, the tile choice and the launch sequence.
+#include "lbm_ch.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "lbm_ch_internal.h"
+
+using namespace lbmch;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int hip_fail(hipError_t e) {
+  g_last_hip = (int)e;
+  return LBM_CH_EHIP;
+}
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+  uint32_t plane;  // floats between population planes
+  size_t g_bytes;  // one population buffer (9 planes)
+  size_t off_ga, off_gb, off_fa, off_fb, off_u, off_v, off_p, off_phi, off_ztab, off_part,
+      off_diag, total;
+};
+
+bool valid_params(const lbm_ch_params* p) {
+  if (!p) return false;
+  if (p->nx < 4 || p->ny < 4) return false;
+  if ((double)p->nx * (double)p->ny * 9.0 * 4.0 >= 2147483648.0) return false;
+  if (p->walls != 0 && p->walls != 1) return false;
+  if (p->model != 1 && p->model != 2) return false;
+  if (p->velocity_mode < LBM_CH_VEL_NONE || p->velocity_mode > LBM_CH_VEL_NS) return false;
+  if (!(p->tau_g > 0.5) || !isfinite(p->tau_g)) return false;
+  if (!(p->phi_a != p->phi_b)) return false;
+  if (!(p->rho_a > 0.0) || !(p->rho_b > 0.0)) return false;
+  if (!isfinite(p->mobility) || !isfinite(p->sigma) || !(p->width > 0.0)) return false;
+  if (p->sigma < 0.0 || p->mobility < 0.0) return false;
+  if (p->velocity_mode == LBM_CH_VEL_NS) {
+    if (!(p->tau_f > 0.5) || !isfinite(p->tau_f)) return false;
+    if (!isfinite(p->gravity) || !isfinite(p->accel_x)) return false;
+  }
+  return true;
+}
+
+Layout layout_of(const lbm_ch_params* p) {
+  Layout L{};
+  const size_t nodes = (size_t)p->nx * p->ny;
+  L.plane = (uint32_t)((nodes + 63) / 64 * 64);
+  L.g_bytes = align_up((size_t)9 * L.plane * sizeof(float));
+  const bool ns = p->velocity_mode == LBM_CH_VEL_NS;
+  const size_t field = align_up(nodes * sizeof(float));
+  size_t o = 0;
+  L.off_ga = o; o += L.g_bytes;
+  L.off_gb = o; o += L.g_bytes;
+  L.off_fa = o; if (ns) o += L.g_bytes;
+  L.off_fb = o; if (ns) o += L.g_bytes;
+  L.off_u = o; o += field;
+  L.off_v = o; o += field;
+  L.off_p = o; o += field;
+  L.off_phi = o; o += field;
+  L.off_ztab = o; o += align_up((size_t)2 * (p->nx + p->ny) * sizeof(float));
+  L.off_part = o; o += align_up((size_t)diag_partial_blocks() * 8 * sizeof(double));
+  L.off_diag = o; o += align_up(8 * sizeof(double));
+  L.total = o;
+  return L;
+}
+
+bool aligned4(const void* q) { return ((uintptr_t)q & 3u) == 0; }
+
+}  // namespace
+
+struct lbm_ch_ctx {
+  lbm_ch_params p;
+  Coef c;
+  Layout L;
+  char* ws;
+  float *g[2], *f[2], *u, *v, *pr, *phi, *ztab;
+  double *part, *diag;
+  int cur;  // index of the buffer holding the current state
+  int64_t step;
+  int vmode;  // internal VelMode of the prescribed velocity
+  const float *ax, *ay, *bx, *by, *ux, *uy;
+  std::vector<double> tf;
+  int tx, ty, nstrips, nblocks, xcd_remap;
+  uint32_t magic;
+};
+
+static constexpr uint32_t CTX_MAGIC = 0x4c424d43u;
+
+static bool live(const lbm_ch_ctx* c) { return c && c->magic == CTX_MAGIC; }
+
+static float time_factor(const lbm_ch_ctx* c, int64_t n) {
+  if (c->tf.empty()) return 1.0f;
+  if (n < (int64_t)c->tf.size()) return (float)c->tf[(size_t)n];
+  return (float)c->tf.back();
+}
+
+// Tile choice: TX columns per block (one lane per column), TY rows per block.  The
+// defaults aim at several blocks per CU on 256 CUs; LBM_CH_TILE=TXxTY overrides.
+static void choose_tiles(lbm_ch_ctx* c) {
+  const int nx = c->p.nx, ny = c->p.ny;
+  int tx = nx >= 256 ? 256 : (nx >= 128 ? 128 : 64);
+  int ty = 16;
+  const char* env = getenv("LBM_CH_TILE");
+  if (env) {
+    int a = 0, b = 0;
+    if (sscanf(env, "%dx%d", &a, &b) == 2 && (a == 64 || a == 128 || a == 256) && b >= 1) {
+      tx = a;
+      ty = b;
+    }
+  }
+  if (ty > ny) ty = ny;
+  c->tx = tx;
+  c->ty = ty;
+  c->nstrips = (nx + tx - 1) / tx;
+  const int nchunks = (ny + ty - 1) / ty;
+  c->nblocks = c->nstrips * nchunks;
+  c->xcd_remap = (c->nblocks % 8 == 0) ? 1 : 0;
+}
+
+extern "C" {
+
+size_t lbm_ch_workspace_bytes(const lbm_ch_params* p) {
+  if (!valid_params(p)) return 0;
+  return layout_of(p).total;
+}
+
+int lbm_ch_init(lbm_ch_ctx** out, const lbm_ch_params* p, const lbm_ch_velocity* vel,
+                void* workspace, size_t workspace_bytes, const float* phi0,
+                hipStream_t stream) {
+  if (!out) return LBM_CH_EINVAL;
+  *out = nullptr;
+  if (!valid_params(p)) return LBM_CH_EINVAL;
+  if (p->storage != LBM_CH_STORE_F32) return LBM_CH_EUNSUPPORTED;
+  const Layout L = layout_of(p);
+  if (!workspace || ((uintptr_t)workspace % ALIGN) != 0 || workspace_bytes < L.total)
+    return LBM_CH_EINVAL;
+  if (!phi0 || !aligned4(phi0)) return LBM_CH_EINVAL;
+  const int vm = p->velocity_mode;
+  if (vm == LBM_CH_VEL_SEPARABLE) {
+    if (!vel || !vel->ax || !vel->ay || !vel->bx || !vel->by) return LBM_CH_EINVAL;
+    if (!aligned4(vel->ax) || !aligned4(vel->ay) || !aligned4(vel->bx) || !aligned4(vel->by))
+      return LBM_CH_EINVAL;
+  }
+  if (vm == LBM_CH_VEL_FIELD) {
+    if (!vel || !vel->ux || !vel->uy || !aligned4(vel->ux) || !aligned4(vel->uy))
+      return LBM_CH_EINVAL;
+  }
+  if (vm == LBM_CH_VEL_NS && vel && ((vel->ux != nullptr) != (vel->uy != nullptr)))
+    return LBM_CH_EINVAL;
+  if (vel && vel->time_factor && vel->n_time_factor < 0) return LBM_CH_EINVAL;
+
+  lbm_ch_ctx* c = new (std::nothrow) lbm_ch_ctx();
+  if (!c) return LBM_CH_EINVAL;
+  c->p = *p;
+  c->L = L;
+  c->ws = (char*)workspace;
+  c->g[0] = (float*)(c->ws + L.off_ga);
+  c->g[1] = (float*)(c->ws + L.off_gb);
+  const bool ns = vm == LBM_CH_VEL_NS;
+  c->f[0] = ns ? (float*)(c->ws + L.off_fa) : nullptr;
+  c->f[1] = ns ? (float*)(c->ws + L.off_fb) : nullptr;
+  c->u = (float*)(c->ws + L.off_u);
+  c->v = (float*)(c->ws + L.off_v);
+  c->pr = (float*)(c->ws + L.off_p);
+  c->phi = (float*)(c->ws + L.off_phi);
+  c->ztab = (float*)(c->ws + L.off_ztab);
+  c->part = (double*)(c->ws + L.off_part);
+  c->diag = (double*)(c->ws + L.off_diag);
+  c->cur = 0;
+  c->step = 0;
+
+  // Coefficients.
+  const double dphi = fabs(p->phi_a - p->phi_b);
+  const double beta = 12.0 * p->sigma / (p->width * dphi * dphi * dphi * dphi);  // Eq. betakappa
+  const double kappa = 3.0 * p->sigma * p->width / (2.0 * dphi * dphi);           // Eq. betakappa
+  const double cs2 = 1.0 / 3.0;
+  const double eta = p->mobility / (cs2 * (p->tau_g - 0.5));  // M = cs^2 eta (tau - 1/2)
+  const double K = (p->tau_g - 1.0 / 6.0 - p->tau_g * p->tau_g) / (p->tau_g - 0.5);
+  const double a = (p->rho_a - p->rho_b) / (p->phi_a - p->phi_b);                  // Eq. rho
+  const double b = (p->rho_b * p->phi_a - p->phi_b * p->rho_a) / (p->phi_a - p->phi_b);
+  Coef& k = c->c;
+  k.beta2 = (float)(2.0 * beta);
+  k.kappa = (float)kappa;
+  k.phia = (float)p->phi_a;
+  k.phib = (float)p->phi_b;
+  k.eta = (float)eta;
+  k.k2 = p->model == 2 ? (float)(3.0 * cs2 * K) : 0.0f;
+  k.a = (float)a;
+  k.b = (float)b;
+  k.omega = (float)(1.0 / p->tau_g);
+  k.srcg = (float)(3.0 * (1.0 - 0.5 / p->tau_g));
+  k.omega_f = ns ? (float)(1.0 / p->tau_f) : 0.0f;
+  k.srcf = ns ? (float)(1.0 - 0.5 / p->tau_f) : 0.0f;
+  k.gravity = ns ? (float)p->gravity : 0.0f;
+  k.accel_x = ns ? (float)p->accel_x : 0.0f;
+  k.rho_mean = (float)(0.5 * (p->rho_a + p->rho_b));
+  k.aM = (float)(a * p->mobility);
+
+  // Velocity inputs.  u = 0 is served by zero separable tables in the workspace.
+  float* z = c->ztab;
+  switch (vm) {
+    case LBM_CH_VEL_SEPARABLE:
+      c->vmode = VEL_SEP;
+      c->ax = vel->ax; c->ay = vel->ay; c->bx = vel->bx; c->by = vel->by;
+      break;
+    case LBM_CH_VEL_FIELD:
+      c->vmode = VEL_FIELD;
+      c->ux = vel->ux; c->uy = vel->uy;
+      break;
+    case LBM_CH_VEL_NS:
+      c->vmode = VEL_FIELD;  // for the initial state only
+      c->ux = vel ? vel->ux : nullptr;
+      c->uy = vel ? vel->uy : nullptr;
+      break;
+    default:
+      c->vmode = VEL_SEP;
+      c->ax = z; c->ay = z + p->nx; c->bx = z; c->by = z + p->nx;
+      break;
+  }
+  if (vm != LBM_CH_VEL_NS && vel && vel->time_factor && vel->n_time_factor > 0)
+    c->tf.assign(vel->time_factor, vel->time_factor + vel->n_time_factor);
+  choose_tiles(c);
+  c->magic = CTX_MAGIC;
+
+  hipError_t e = launch_fill(z, 0.0f, 2 * (int64_t)(p->nx + p->ny), stream);
+  if (e == hipSuccess)
+    e = launch_init(p->walls != 0, c->vmode, c->c, p->nx, p->ny, L.plane, phi0, c->ax, c->ay,
+                    c->bx, c->by, c->ux, c->uy, time_factor(c, 0), c->g[0], c->f[0], stream);
+  if (e != hipSuccess) {
+    c->magic = 0;
+    delete c;
+    return hip_fail(e);
+  }
+  if (ns) {
+    c->ux = nullptr;
+    c->uy = nullptr;
+  }
+  *out = c;
+  return LBM_CH_OK;
+}
+
+int lbm_ch_step(lbm_ch_ctx* c, int64_t nsteps, hipStream_t stream) {
+  if (!live(c)) return LBM_CH_ESTATE;
+  if (nsteps < 0) return LBM_CH_EINVAL;
+  const bool ns = c->p.velocity_mode == LBM_CH_VEL_NS;
+  const bool walls = c->p.walls != 0;
+  StepArgs a{};
+  a.plane = c->L.plane;
+  a.nx = c->p.nx;
+  a.ny = c->p.ny;
+  a.ty = c->ty;
+  a.nstrips = c->nstrips;
+  a.xcd_remap = c->xcd_remap;
+  a.c = c->c;
+  a.ax = c->ax; a.ay = c->ay; a.bx = c->bx; a.by = c->by;
+  a.ux = c->ux; a.uy = c->uy;
+  NsArgs n{};
+  if (ns) {
+    n.plane = c->L.plane;
+    n.nx = c->p.nx;
+    n.ny = c->p.ny;
+    n.ty = c->ty;
+    n.nstrips = c->nstrips;
+    n.xcd_remap = c->xcd_remap;
+    n.c = c->c;
+    n.u = c->u; n.v = c->v; n.p = c->pr;
+    a.ux = c->u; a.uy = c->v; a.pf = c->pr;
+  }
+  const int vmode = ns ? VEL_NSFIELD : c->vmode;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    const int src = c->cur, dst = 1 - c->cur;
+    hipError_t e;
+    if (ns) {
+      n.gsrc = c->g[src];
+      n.fsrc = c->f[src];
+      n.fdst = c->f[dst];
+      e = launch_ns_step(c->tx, walls, n, c->nblocks, stream);
+      if (e != hipSuccess) return hip_fail(e);
+      a.tf = 1.0f;
+    } else {
+      a.tf = time_factor(c, c->step);
+    }
+    a.src = c->g[src];
+    a.dst = c->g[dst];
+    e = launch_phi_step(c->tx, walls, vmode, c->p.model == 2, a, c->nblocks, stream);
+    if (e != hipSuccess) return hip_fail(e);
+    c->cur = dst;
+    c->step += 1;
+  }
+  return LBM_CH_OK;
+}
+
+int lbm_ch_moments(lbm_ch_ctx* c, float* phi, float* mu, float* ux, float* uy, float* p,
+                   hipStream_t stream) {
+  if (!live(c)) return LBM_CH_ESTATE;
+  float* outs[5] = {phi, mu, ux, uy, p};
+  for (float* o : outs)
+    if (o && !aligned4(o)) return LBM_CH_EINVAL;
+  const bool walls = c->p.walls != 0;
+  const int nx = c->p.nx, ny = c->p.ny;
+  const size_t fb = (size_t)nx * ny * sizeof(float);
+  const bool ns = c->p.velocity_mode == LBM_CH_VEL_NS;
+  float* ph = phi ? phi : c->phi;
+  hipError_t e = hipSuccess;
+  if (phi || mu || ns) e = launch_phi_field(walls, c->g[c->cur], c->L.plane, nx, ny, ph, stream);
+  if (e == hipSuccess && mu) e = launch_mu_field(walls, c->c, ph, nx, ny, mu, stream);
+  if (e != hipSuccess) return hip_fail(e);
+  if (ns) {
+    if (ux || uy || p) {
+      NsArgs n{};
+      n.gsrc = c->g[c->cur];
+      n.fsrc = c->f[c->cur];
+      n.fdst = nullptr;
+      n.u = c->u; n.v = c->v; n.p = c->pr;
+      n.plane = c->L.plane;
+      n.nx = nx; n.ny = ny;
+      n.ty = c->ty; n.nstrips = c->nstrips; n.xcd_remap = c->xcd_remap;
+      n.c = c->c;
+      e = launch_ns_step(c->tx, walls, n, c->nblocks, stream);
+      if (e == hipSuccess && ux) e = hipMemcpyAsync(ux, c->u, fb, hipMemcpyDeviceToDevice, stream);
+      if (e == hipSuccess && uy) e = hipMemcpyAsync(uy, c->v, fb, hipMemcpyDeviceToDevice, stream);
+      if (e == hipSuccess && p) e = hipMemcpyAsync(p, c->pr, fb, hipMemcpyDeviceToDevice, stream);
+    }
+  } else {
+    if (ux || uy)
+      e = launch_velocity_field(c->vmode, nx, ny, c->ax, c->ay, c->bx, c->by, c->ux, c->uy,
+                                time_factor(c, c->step), ux, uy, stream);
+    if (e == hipSuccess && p) e = launch_fill(p, 0.0f, (int64_t)nx * ny, stream);
+  }
+  return e == hipSuccess ? LBM_CH_OK : hip_fail(e);
+}
+
+int lbm_ch_diagnostics(lbm_ch_ctx* c, const float* phi_ref, double* out, hipStream_t stream) {
+  if (!live(c)) return LBM_CH_ESTATE;
+  if (!out || ((uintptr_t)out & 7u) != 0) return LBM_CH_EINVAL;
+  if (phi_ref && !aligned4(phi_ref)) return LBM_CH_EINVAL;
+  const bool walls = c->p.walls != 0;
+  hipError_t e = launch_phi_field(walls, c->g[c->cur], c->L.plane, c->p.nx, c->p.ny, c->phi, stream);
+  if (e == hipSuccess)
+    e = launch_diag(walls, c->c, c->phi, phi_ref, c->p.nx, c->p.ny, c->part, out, stream);
+  return e == hipSuccess ? LBM_CH_OK : hip_fail(e);
+}
+
+int lbm_ch_check_finite(lbm_ch_ctx* c, hipStream_t stream) {
+  if (!live(c)) return LBM_CH_ESTATE;
+  int r = lbm_ch_diagnostics(c, nullptr, c->diag, stream);
+  if (r != LBM_CH_OK) return r;
+  double h[8];
+  hipError_t e = hipMemcpyAsync(h, c->diag, sizeof(h), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e);
+  return h[7] > 0 ? LBM_CH_ENONFINITE : LBM_CH_OK;
+}
+
+int64_t lbm_ch_step_count(const lbm_ch_ctx* c) { return live(c) ? c->step : -1; }
+
+size_t lbm_ch_state_bytes(const lbm_ch_ctx* c) {
+  if (!live(c)) return 0;
+  const size_t g = (size_t)9 * c->L.plane * sizeof(float);
+  return c->p.velocity_mode == LBM_CH_VEL_NS ? 2 * g : g;
+}
+
+int lbm_ch_save_state(lbm_ch_ctx* c, void* dst, size_t bytes, hipStream_t stream) {
+  if (!live(c)) return LBM_CH_ESTATE;
+  if (!dst || bytes != lbm_ch_state_bytes(c)) return LBM_CH_EINVAL;
+  const size_t g = (size_t)9 * c->L.plane * sizeof(float);
+  hipError_t e = hipMemcpyAsync(dst, c->g[c->cur], g, hipMemcpyDeviceToDevice, stream);
+  if (e == hipSuccess && c->f[0])
+    e = hipMemcpyAsync((char*)dst + g, c->f[c->cur], g, hipMemcpyDeviceToDevice, stream);
+  return e == hipSuccess ? LBM_CH_OK : hip_fail(e);
+}
+
+int lbm_ch_load_state(lbm_ch_ctx* c, const void* src, size_t bytes, int64_t step,
+                      hipStream_t stream) {
+  if (!live(c)) return LBM_CH_ESTATE;
+  if (!src || bytes != lbm_ch_state_bytes(c) || step < 0) return LBM_CH_EINVAL;
+  const size_t g = (size_t)9 * c->L.plane * sizeof(float);
+  hipError_t e = hipMemcpyAsync(c->g[c->cur], src, g, hipMemcpyDeviceToDevice, stream);
+  if (e == hipSuccess && c->f[0])
+    e = hipMemcpyAsync(c->f[c->cur], (const char*)src + g, g, hipMemcpyDeviceToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e);
+  c->step = step;
+  return LBM_CH_OK;
+}
+
+int lbm_ch_destroy(lbm_ch_ctx* c) {
+  if (!c) return LBM_CH_OK;
+  if (!live(c)) return LBM_CH_ESTATE;
+  c->magic = 0;
+  delete c;
+  return LBM_CH_OK;
+}
+
+const char* lbm_ch_strerror(int status) {
+  switch (status) {
+    case LBM_CH_OK: return "ok";
+    case LBM_CH_EINVAL: return "invalid argument";
+    case LBM_CH_EUNSUPPORTED: return "unsupported combination";
+    case LBM_CH_EHIP: return "HIP runtime error";
+    case LBM_CH_ENONFINITE: return "non-finite order parameter";
+    case LBM_CH_ESTATE: return "invalid or destroyed context";
+    default: return "unknown status";
+  }
+}
+
+int lbm_ch_last_hip_error(void) { return g_last_hip; }
+
+}  // extern "C"

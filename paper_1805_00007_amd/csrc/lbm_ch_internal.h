@@ -1,0 +1,81 @@
+// Internal interface between the host ABI (lbm_ch_api.cpp) and the gfx950 kernels
+// (lbm_ch_kernels.hip).  Not installed; the public interface is include/lbm_ch.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbmch {
+
+// Per-run constants in the form the kernels use (all float32).
+struct Coef {
+  float beta2;      // 2 beta, with mu_bulk = 2 beta (phi - phi_a)(phi - phi_b)(2 phi - phi_a - phi_b)
+  float kappa;      // Eq. betakappa
+  float phia, phib;
+  float eta;        // M / (cs^2 (tau_g - 1/2))
+  float k2;         // 3 cs^2 K = K, the factor of F2 (Eq. mark3); 0 for Model-I
+  float a, b;       // rho = a phi + b (Eq. rho)
+  float omega;      // 1 / tau_g
+  float srcg;       // 3 (1 - 1/(2 tau_g)): S_i (1 - 1/(2 tau)) = srcg w_i c_i.F
+  // coupled Navier-Stokes
+  float omega_f;    // 1 / tau_f
+  float srcf;       // 1 - 1/(2 tau_f)
+  float gravity, accel_x, rho_mean;
+  float aM;         // a * M, the factor of u lap(mu) in the NS force
+};
+
+// Arguments of the fused phase-field step.
+struct StepArgs {
+  const float* src;   // populations at t_n: 9 planes of `plane` floats
+  float* dst;         // populations at t_{n+1}
+  uint32_t plane;     // floats between planes (>= nx*ny)
+  int nx, ny;
+  int ty;             // rows per block
+  int nstrips;        // ceil(nx / TX)
+  int xcd_remap;      // 1: the grid is a multiple of 8 blocks, map each XCD to a band
+  Coef c;
+  // prescribed separable velocity (u = tf ax[x] ay[y], v = tf bx[x] by[y])
+  const float *ax, *ay, *bx, *by;
+  // velocity field (u = tf ux, v = tf uy), and pressure field for the NS coupling
+  const float *ux, *uy, *pf;
+  float tf;
+};
+
+// Arguments of the coupled Navier-Stokes step.
+struct NsArgs {
+  const float* gsrc;  // phase-field populations at t_n
+  const float* fsrc;  // NS populations at t_n
+  float* fdst;        // NS populations at t_{n+1} (may be null: moments only)
+  float *u, *v, *p;   // velocity and pressure at t_n (written)
+  uint32_t plane;
+  int nx, ny;
+  int ty, nstrips, xcd_remap;
+  Coef c;
+};
+
+enum VelMode { VEL_SEP = 0, VEL_FIELD = 1, VEL_NSFIELD = 2 };
+
+// Launchers (return hipGetLastError() of the launch).
+hipError_t launch_phi_step(int tx, bool walls, int vmode, bool model2, const StepArgs& a,
+                           int nblocks, hipStream_t s);
+hipError_t launch_ns_step(int tx, bool walls, const NsArgs& a, int nblocks, hipStream_t s);
+
+hipError_t launch_init(bool walls, int vmode, const Coef& c, int nx, int ny, uint32_t plane,
+                       const float* phi0, const float* ax, const float* ay, const float* bx,
+                       const float* by, const float* ux, const float* uy, float tf, float* g,
+                       float* f, hipStream_t s);
+hipError_t launch_phi_field(bool walls, const float* g, uint32_t plane, int nx, int ny,
+                            float* phi, hipStream_t s);
+hipError_t launch_mu_field(bool walls, const Coef& c, const float* phi, int nx, int ny,
+                           float* mu, hipStream_t s);
+hipError_t launch_velocity_field(int vmode, int nx, int ny, const float* ax, const float* ay,
+                                 const float* bx, const float* by, const float* ux,
+                                 const float* uy, float tf, float* u, float* v,
+                                 hipStream_t s);
+hipError_t launch_fill(float* dst, float value, int64_t n, hipStream_t s);
+// FP64 reductions of a phi field; partial needs diag_partial_blocks()*8 doubles.
+int diag_partial_blocks();
+hipError_t launch_diag(bool walls, const Coef& c, const float* phi, const float* ref, int nx,
+                       int ny, double* partial, double* out, hipStream_t s);
+
+}  // namespace lbmch

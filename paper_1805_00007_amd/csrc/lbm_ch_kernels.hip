@@ -1,0 +1,852 @@
+// gfx950 kernels of the lattice Boltzmann Cahn-Hilliard solver
+// (Zhang, Guo & Liang, arXiv:1805.00007).  The public contract, the method and the
+// boundary rules are stated in include/lbm_ch.h; this file holds the device code.
+//
+// The hot kernel, k_phi_step, is one fused pull-scheme update of all nine
+// phase-field populations.  A block owns a strip of TX columns and marches down TY
+// rows of it.  Per row it keeps three rolling rings in LDS:
+//   stage 1, row y+2: pull g_i(x) = g_i*(x - c_i), phi = sum g_i, q = phi u   (Eq. macroscopicg)
+//   stage 2, row y+1: mu = f'(phi) - kappa lap(phi), D = div q                 (Eqs. mu, mark3)
+//   stage 3, row y  : grad mu, grad D (and grad p), F = F1 + F2, g^eq, S, BGK,
+//                     store g*                                                 (Eqs. t0-phiu, mark3, geq, liangFi, LB)
+// so every value is computed once per node and the only HBM traffic is the nine
+// populations in and out (72 bytes per node update in float32).  The pops of a row
+// are pulled two iterations before they are collided and stay in registers; the
+// pull for the next row is issued before the barriers so that its latency overlaps
+// the stencil work.  Four lanes of the block also compute phi (and mu, D) of the
+// two halo columns on each side.  A row strip of the domain is handed to blocks in
+// an order that keeps a band of neighbouring strips on one XCD (one L2), so the
+// halo rows a block re-reads are L2 hits.
+#include "lbm_ch_internal.h"
+
+#include <math.h>
+
+namespace lbmch {
+namespace {
+
+// D2Q9 lattice of Sec. II.B and its weights (below Eq. geq).
+constexpr int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr float WT[9] = {4.0f / 9, 1.0f / 9, 1.0f / 9, 1.0f / 9, 1.0f / 9,
+                         1.0f / 36, 1.0f / 36, 1.0f / 36, 1.0f / 36};
+
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Logical row r (may lie one or two rows outside the lattice) -> stored row and the
+// parity of the velocity there: periodic wrap, or mirror across the walls at
+// y = -1/2 and y = ny - 1/2 (velocity odd).
+template <bool WALLS>
+__device__ __forceinline__ int row_of(int r, int ny, float& vsign) {
+  if (WALLS) {
+    if (r < 0) { vsign = -1.0f; return -1 - r; }
+    if (r >= ny) { vsign = -1.0f; return 2 * ny - 1 - r; }
+    vsign = 1.0f;
+    return r;
+  }
+  vsign = 1.0f;
+  r = r % ny;
+  return r < 0 ? r + ny : r;
+}
+
+// Range-checked buffer access (gfx9 raw buffer, stride 0): an offset at or beyond
+// the descriptor's byte count reads 0 and drops the store, so no index can reach
+// memory outside the array it belongs to.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
+                                           0x00020000);
+}
+__device__ __forceinline__ float ldb(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void stb(rsrc_t r, float v, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+}
+
+// Pull of the nine populations arriving at (x, y): g_i(x, y) = g_i*(x - c_i, y - c_i).
+// With walls, a population whose source lies beyond a wall is the opposite one that
+// left (x, y) (half-way bounce-back).  y is a lattice row; xm/xp are x-1, x+1 wrapped;
+// pb is the plane stride in bytes.
+template <bool WALLS>
+__device__ __forceinline__ void pull9(rsrc_t s, uint32_t pb, int nx, int ny, int y, int xc,
+                                      int xm, int xp, float g[9]) {
+  const int ym = y == 0 ? ny - 1 : y - 1;
+  const int yp = y == ny - 1 ? 0 : y + 1;
+  const uint32_t rc = (uint32_t)y * nx, rm = (uint32_t)ym * nx, rp = (uint32_t)yp * nx;
+  g[0] = ldb(s, (rc + xc) * 4u, 0);
+  g[1] = ldb(s, (rc + xm) * 4u, pb);
+  g[3] = ldb(s, (rc + xp) * 4u, 3 * pb);
+  if (WALLS && y == 0) {
+    g[2] = ldb(s, (rc + xc) * 4u, 4 * pb);
+    g[5] = ldb(s, (rc + xc) * 4u, 7 * pb);
+    g[6] = ldb(s, (rc + xc) * 4u, 8 * pb);
+  } else {
+    g[2] = ldb(s, (rm + xc) * 4u, 2 * pb);
+    g[5] = ldb(s, (rm + xm) * 4u, 5 * pb);
+    g[6] = ldb(s, (rm + xp) * 4u, 6 * pb);
+  }
+  if (WALLS && y == ny - 1) {
+    g[4] = ldb(s, (rc + xc) * 4u, 2 * pb);
+    g[7] = ldb(s, (rc + xc) * 4u, 5 * pb);
+    g[8] = ldb(s, (rc + xc) * 4u, 6 * pb);
+  } else {
+    g[4] = ldb(s, (rp + xc) * 4u, 4 * pb);
+    g[7] = ldb(s, (rp + xp) * 4u, 7 * pb);
+    g[8] = ldb(s, (rp + xm) * 4u, 8 * pb);
+  }
+}
+
+// Order parameter of Eq. macroscopicg and mass bookkeeping.  The nine float32
+// populations are summed in FP64, which is exact for their range of magnitudes, and
+// the collision writes g_0* = (phi - sum_{i>0} g_i*) through the same FP64 sums, so
+// the exact sum of the stored floats moves only by the rounding of g_0* -- no bias
+// builds up in uniform regions, where every node would round identically.  In exact
+// arithmetic this equals the direct form of Eq. LB, because the collision conserves
+// sum_i g_i (Eqs. feqmoment, conservation).  phi itself (for the stencils) is the
+// float32 rounding of the FP64 sum; lo keeps the remainder.
+__device__ __forceinline__ double sum8_hi(const float g[9]) {
+  return (((double)g[1] + (double)g[2]) + ((double)g[3] + (double)g[4])) +
+         (((double)g[5] + (double)g[6]) + ((double)g[7] + (double)g[8]));
+}
+// Sets g[0] so that the exact sum of the nine floats equals m up to the rounding
+// of g[8]: g[0] takes the float part of m - sum_{i>0} g_i, and the remainder (exact
+// in FP64) goes into g[8].  g[8] is small (of order w_8 (eta mu + phi s_8(u))), so
+// its rounding is ~100x finer than that of g[0] ~ phi.
+__device__ __forceinline__ void close_mass(double m, float g[9]) {
+  const double e0 = m - sum8_hi(g);
+  g[0] = (float)e0;
+  g[8] = (float)((double)g[8] + (e0 - (double)g[0]));
+}
+__device__ __forceinline__ float sum9(const float g[9], float& lo) {
+  const double s = sum8_hi(g) + (double)g[0];
+  const float f = (float)s;
+  lo = (float)(s - (double)f);
+  return f;
+}
+__device__ __forceinline__ float sum9(const float g[9]) {
+  float lo;
+  return sum9(g, lo);
+}
+
+// Bulk part of Eq. mu for the double well of Eq. bulk.
+__device__ __forceinline__ float mu_bulk(const Coef& c, float phi) {
+  return c.beta2 * (phi - c.phia) * (phi - c.phib) * (2.0f * phi - c.phia - c.phib);
+}
+
+// Isotropic stencils on three LDS rows (rm: y-1, r0: y, rp: y+1) around column j:
+//   d_x = [4 (E - W) + (NE + SE - NW - SW)] / 12
+//   d_y = [4 (N - S) + (NE + NW - SE - SW)] / 12
+//   lap = [4 (E + W + N + S) + (NE + NW + SE + SW) - 20 C] / 6
+__device__ __forceinline__ float ddx(const float* rm, const float* r0, const float* rp, int j) {
+  return (4.0f * (r0[j + 1] - r0[j - 1]) + (rp[j + 1] + rm[j + 1] - rp[j - 1] - rm[j - 1])) *
+         (1.0f / 12.0f);
+}
+__device__ __forceinline__ float ddy(const float* rm, const float* r0, const float* rp, int j) {
+  return (4.0f * (rp[j] - rm[j]) + (rp[j + 1] + rp[j - 1] - rm[j + 1] - rm[j - 1])) *
+         (1.0f / 12.0f);
+}
+__device__ __forceinline__ float lap9(const float* rm, const float* r0, const float* rp, int j) {
+  return (4.0f * (r0[j + 1] + r0[j - 1] + rp[j] + rm[j]) +
+          (rp[j + 1] + rp[j - 1] + rm[j + 1] + rm[j - 1]) - 20.0f * r0[j]) *
+         (1.0f / 6.0f);
+}
+
+// Collision of Eq. LB with g^eq of Eq. geq and S_i = 3 w_i c_i.F (Eq. liangFi):
+//   g_i* = (1 - omega) g_i + omega g_i^eq + srcg w_i c_i.F
+__device__ __forceinline__ void collide_g(const Coef& c, float phi, float phi_lo, float mu,
+                                          float u, float v, float fx, float fy, float g[9]) {
+  const float em = c.eta * mu;
+  const float usq15 = 1.5f * (u * u + v * v);
+  const float A = em - phi * usq15;  // w_i (eta mu - 1.5 phi u^2) common to all i
+  const float om1 = 1.0f - c.omega;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const float cu = CX[i] * u + CY[i] * v;
+    const float cf = CX[i] * fx + CY[i] * fy;
+    const float eq = A + phi * cu * (3.0f + 4.5f * cu);
+    g[i] = om1 * g[i] + WT[i] * (c.omega * eq + c.srcg * cf);
+  }
+  // g_0* = (1 - omega) g_0 + omega g_0^eq, written through mass conservation
+  close_mass((double)phi + (double)phi_lo, g);
+}
+
+// ---------------------------------------------------------------------------------
+// Fused phase-field step.
+//   VMODE VEL_SEP: u = tf ax[x] ay[y]; VEL_FIELD: u = tf ux[y][x];
+//   VEL_NSFIELD: u, p from the NS step, F1 = (phi/rho)(F_s + F_b - grad p).
+template <int TX, bool WALLS, int VMODE>
+struct Pull {
+  static constexpr bool VF = VMODE != VEL_SEP;
+  static constexpr bool NSC = VMODE == VEL_NSFIELD;
+  float g[9];
+  float u, v, p;
+};
+
+template <int TX, bool WALLS, int VMODE, bool MODEL2>
+__global__ void __launch_bounds__(TX) k_phi_step(const StepArgs a) {
+  constexpr bool NSC = VMODE == VEL_NSFIELD;
+  constexpr bool VFIELD = VMODE != VEL_SEP;
+  constexpr int LW = TX + 4;
+  constexpr int QR = MODEL2 ? 4 : 1;
+  constexpr int PR = NSC ? 8 : 1;
+  __shared__ float s_phi[4][LW];
+  __shared__ float s_mu[4][LW];
+  __shared__ float s_qx[QR][LW];
+  __shared__ float s_qy[QR][LW];
+  __shared__ float s_d[QR][LW];
+  __shared__ float s_p[PR][LW];
+  using P = Pull<TX, WALLS, VMODE>;
+
+  const Coef& c = a.c;
+  const int nx = a.nx, ny = a.ny;
+  const uint32_t nodes = (uint32_t)nx * ny;
+  const uint32_t pb = a.plane * 4u;
+  const rsrc_t rsrc = make_rsrc(a.src, 9u * pb);
+  const rsrc_t rdst = make_rsrc(a.dst, 9u * pb);
+  rsrc_t ru, rv, rp;
+  if (VFIELD) {
+    ru = make_rsrc(a.ux, nodes * 4u);
+    rv = make_rsrc(a.uy, nodes * 4u);
+  }
+  if (NSC) rp = make_rsrc(a.pf, nodes * 4u);
+
+  const int t = threadIdx.x;
+  int L = blockIdx.x;
+  if (a.xcd_remap) {
+    const int per = gridDim.x >> 3;
+    L = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  }
+  const int x0 = (L % a.nstrips) * TX;
+  const int y0 = (L / a.nstrips) * a.ty;
+  const int rows = min(a.ty, ny - y0);
+
+  // Own column (wrapped) and its neighbours.
+  const int xl = x0 + t;
+  const bool active = xl < nx;
+  const int xc = xl % nx;
+  const int xm = xc == 0 ? nx - 1 : xc - 1;
+  const int xp = xc == nx - 1 ? 0 : xc + 1;
+  // Halo lanes t < 4: logical columns x0-2, x0-1, x0+TX, x0+TX+1 -> LDS 0, 1, TX+2, TX+3.
+  const bool hl = t < 4;
+  const int hlog = t < 2 ? x0 - 2 + t : x0 + TX - 2 + t;
+  const int hc = ((hlog % nx) + nx) % nx;
+  const int hm = hc == 0 ? nx - 1 : hc - 1;
+  const int hp = hc == nx - 1 ? 0 : hc + 1;
+  const int hj = t < 2 ? t : TX + t;
+  const int j = t + 2;
+  const int j2 = t == 0 ? 1 : TX + 2;  // stage-2 halo column of lanes 0 and 1
+
+  float axc = 0.f, bxc = 0.f, axh = 0.f, bxh = 0.f;
+  if (VMODE == VEL_SEP) {
+    axc = a.ax[xc];
+    bxc = a.bx[xc];
+    if (hl) {
+      axh = a.ax[hc];
+      bxh = a.bx[hc];
+    }
+  }
+
+  // Issue the pull of logical row r at column col (plus velocity and pressure in the
+  // field modes) so that one wait covers all of it.
+  auto issue = [&](int r, int col, int cm, int cq, P& Q) {
+    float sg;
+    const int sr = row_of<WALLS>(r, ny, sg);
+    pull9<WALLS>(rsrc, pb, nx, ny, sr, col, cm, cq, Q.g);
+    if (VFIELD) {
+      const uint32_t off = ((uint32_t)sr * nx + col) * 4u;
+      Q.u = ldb(ru, off, 0);
+      Q.v = ldb(rv, off, 0);
+      if (NSC) Q.p = ldb(rp, off, 0);
+    }
+  };
+  // Stage 1 for logical row r: phi (and q = phi u, p) into the rings at column jj.
+  auto stage1 = [&](int r, const P& Q, int jj, float axv, float bxv, float& phi, float& lo,
+                    float& u, float& v) {
+    float sg;
+    const int sr = row_of<WALLS>(r, ny, sg);
+    phi = sum9(Q.g, lo);
+    if (VMODE == VEL_SEP) {
+      u = a.tf * axv * a.ay[sr] * sg;
+      v = a.tf * bxv * a.by[sr] * sg;
+    } else {
+      u = a.tf * Q.u * sg;
+      v = a.tf * Q.v * sg;
+    }
+    s_phi[r & 3][jj] = phi;
+    if (MODEL2) {
+      s_qx[r & 3][jj] = phi * u;
+      s_qy[r & 3][jj] = phi * v;
+    }
+    if (NSC) s_p[r & 7][jj] = Q.p;
+  };
+  // Stage 2 for logical row r at LDS column jj: mu (Eq. mu) and D = div(phi u).
+  auto stage2 = [&](int r, int jj) {
+    const float* pm = s_phi[(r - 1) & 3];
+    const float* p0 = s_phi[r & 3];
+    const float* pp = s_phi[(r + 1) & 3];
+    s_mu[r & 3][jj] = mu_bulk(c, p0[jj]) - c.kappa * lap9(pm, p0, pp, jj);
+    if (MODEL2) {
+      s_d[r & 3][jj] = ddx(s_qx[(r - 1) & 3], s_qx[r & 3], s_qx[(r + 1) & 3], jj) +
+                       ddy(s_qy[(r - 1) & 3], s_qy[r & 3], s_qy[(r + 1) & 3], jj);
+    }
+  };
+
+  // Prologue: rows y0-2 .. y0+1 through stage 1, rows y0-1 and y0 through stage 2,
+  // and the pull of row y0+2 in flight.
+  P P0, P1, P2, H;
+  float phi0, l0, u0, v0, phi1, l1, u1, v1, phi2, l2, u2, v2, dphi, dl, du, dv;
+  {
+    P A, B;
+    issue(y0 - 2, xc, xm, xp, A);
+    issue(y0 - 1, xc, xm, xp, B);
+    issue(y0, xc, xm, xp, P0);
+    issue(y0 + 1, xc, xm, xp, P1);
+    stage1(y0 - 2, A, j, axc, bxc, dphi, dl, du, dv);
+    stage1(y0 - 1, B, j, axc, bxc, dphi, dl, du, dv);
+    if (hl) {
+      issue(y0 - 2, hc, hm, hp, A);
+      issue(y0 - 1, hc, hm, hp, B);
+    }
+    stage1(y0, P0, j, axc, bxc, phi0, l0, u0, v0);
+    stage1(y0 + 1, P1, j, axc, bxc, phi1, l1, u1, v1);
+    if (hl) {
+      stage1(y0 - 2, A, hj, axh, bxh, dphi, dl, du, dv);
+      stage1(y0 - 1, B, hj, axh, bxh, dphi, dl, du, dv);
+      issue(y0, hc, hm, hp, A);
+      issue(y0 + 1, hc, hm, hp, B);
+      stage1(y0, A, hj, axh, bxh, dphi, dl, du, dv);
+      stage1(y0 + 1, B, hj, axh, bxh, dphi, dl, du, dv);
+    }
+  }
+  issue(y0 + 2, xc, xm, xp, P2);
+  if (hl) issue(y0 + 2, hc, hm, hp, H);
+  __syncthreads();
+  stage2(y0 - 1, j);
+  stage2(y0, j);
+  if (t < 2) {
+    stage2(y0 - 1, j2);
+    stage2(y0, j2);
+  }
+  __syncthreads();
+
+#pragma unroll 1
+  for (int k = 0; k < rows; ++k) {
+    const int y = y0 + k;
+    // issue row y+3, then stage 1 of row y+2 (pulled one iteration ago)
+    P PN;
+    if (k + 1 < rows) issue(y + 3, xc, xm, xp, PN);
+    stage1(y + 2, P2, j, axc, bxc, phi2, l2, u2, v2);
+    if (hl) {
+      stage1(y + 2, H, hj, axh, bxh, dphi, dl, du, dv);
+      if (k + 1 < rows) issue(y + 3, hc, hm, hp, H);
+    }
+    __syncthreads();
+    // stage 2, row y+1
+    stage2(y + 1, j);
+    if (t < 2) stage2(y + 1, j2);
+    __syncthreads();
+    // stage 3, row y
+    if (active) {
+      const float* mm = s_mu[(y - 1) & 3];
+      const float* m0 = s_mu[y & 3];
+      const float* mp = s_mu[(y + 1) & 3];
+      const float mux = ddx(mm, m0, mp, j), muy = ddy(mm, m0, mp, j);
+      const float rho = c.a * phi0 + c.b;
+      float tx = -phi0 * mux, ty = -phi0 * muy;
+      if (NSC) {
+        const float* qm = s_p[(y - 1) & 7];
+        const float* q0 = s_p[y & 7];
+        const float* qp = s_p[(y + 1) & 7];
+        tx += rho * c.accel_x - ddx(qm, q0, qp, j);
+        ty += -(rho - c.rho_mean) * c.gravity - ddy(qm, q0, qp, j);
+      }
+      const float s1 = phi0 * rcp(rho);
+      float fx = s1 * tx, fy = s1 * ty;
+      if (MODEL2) {
+        const float* dm = s_d[(y - 1) & 3];
+        const float* d0 = s_d[y & 3];
+        const float* dp = s_d[(y + 1) & 3];
+        fx += c.k2 * ddx(dm, d0, dp, j);
+        fy += c.k2 * ddy(dm, d0, dp, j);
+      }
+      collide_g(c, phi0, l0, m0[j], u0, v0, fx, fy, P0.g);
+      const uint32_t off = ((uint32_t)y * nx + xc) * 4u;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) stb(rdst, P0.g[i], off, i * pb);
+    }
+    // rotate the register pipeline
+    P0 = P1;
+    phi0 = phi1; l0 = l1; u0 = u1; v0 = v1;
+    P1 = P2;
+    phi1 = phi2; l1 = l2; u1 = u2; v1 = v2;
+    P2 = PN;
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Coupled Navier-Stokes step (pressure-based incompressible D2Q9 BGK, see lbm_ch.h).
+// Same marching layout: stage 1 pulls g for phi, stage 2 computes mu, stage 3 pulls
+// f, forms the force, velocity and pressure, writes u, v, p and (if fdst) collides
+// and stores f.
+template <int TX, bool WALLS>
+__global__ void __launch_bounds__(TX) k_ns_step(const NsArgs a) {
+  constexpr int LW = TX + 4;
+  __shared__ float s_phi[8][LW];
+  __shared__ float s_mu[4][LW];
+  const Coef& c = a.c;
+  const int nx = a.nx, ny = a.ny;
+  const uint32_t nodes = (uint32_t)nx * ny;
+  const uint32_t pb = a.plane * 4u;
+  const rsrc_t rg = make_rsrc(a.gsrc, 9u * pb);
+  const rsrc_t rf = make_rsrc(a.fsrc, 9u * pb);
+  const rsrc_t rfd = make_rsrc(a.fdst, a.fdst ? 9u * pb : 0u);
+  const rsrc_t ru = make_rsrc(a.u, nodes * 4u);
+  const rsrc_t rv = make_rsrc(a.v, nodes * 4u);
+  const rsrc_t rpr = make_rsrc(a.p, nodes * 4u);
+  const int t = threadIdx.x;
+  int L = blockIdx.x;
+  if (a.xcd_remap) {
+    const int per = gridDim.x >> 3;
+    L = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  }
+  const int x0 = (L % a.nstrips) * TX;
+  const int y0 = (L / a.nstrips) * a.ty;
+  const int rows = min(a.ty, ny - y0);
+  const int xl = x0 + t;
+  const bool active = xl < nx;
+  const int xc = xl % nx;
+  const int xm = xc == 0 ? nx - 1 : xc - 1;
+  const int xp = xc == nx - 1 ? 0 : xc + 1;
+  const bool hl = t < 4;
+  const int hlog = t < 2 ? x0 - 2 + t : x0 + TX - 2 + t;
+  const int hc = ((hlog % nx) + nx) % nx;
+  const int hm = hc == 0 ? nx - 1 : hc - 1;
+  const int hp = hc == nx - 1 ? 0 : hc + 1;
+  const int hj = t < 2 ? t : TX + t;
+  const int j = t + 2;
+  const int j2 = t == 0 ? 1 : TX + 2;
+
+  auto phi_at = [&](int r, int col, int cm, int cq) {
+    float sg, g[9];
+    const int sr = row_of<WALLS>(r, ny, sg);
+    pull9<WALLS>(rg, pb, nx, ny, sr, col, cm, cq, g);
+    return sum9(g);
+  };
+  auto stage2 = [&](int r, int jj) {
+    const float* pm = s_phi[(r - 1) & 7];
+    const float* p0 = s_phi[r & 7];
+    const float* pp = s_phi[(r + 1) & 7];
+    s_mu[r & 3][jj] = mu_bulk(c, p0[jj]) - c.kappa * lap9(pm, p0, pp, jj);
+  };
+
+#pragma unroll 1
+  for (int r = y0 - 2; r <= y0 + 1; ++r) {
+    s_phi[r & 7][j] = phi_at(r, xc, xm, xp);
+    if (hl) s_phi[r & 7][hj] = phi_at(r, hc, hm, hp);
+  }
+  __syncthreads();
+  stage2(y0 - 1, j);
+  stage2(y0, j);
+  if (t < 2) {
+    stage2(y0 - 1, j2);
+    stage2(y0, j2);
+  }
+  float fpop[9];
+  pull9<WALLS>(rf, pb, nx, ny, y0, xc, xm, xp, fpop);
+  __syncthreads();
+
+#pragma unroll 1
+  for (int k = 0; k < rows; ++k) {
+    const int y = y0 + k;
+    float fnext[9];
+    if (k + 1 < rows) pull9<WALLS>(rf, pb, nx, ny, y + 1, xc, xm, xp, fnext);
+    s_phi[(y + 2) & 7][j] = phi_at(y + 2, xc, xm, xp);
+    if (hl) s_phi[(y + 2) & 7][hj] = phi_at(y + 2, hc, hm, hp);
+    __syncthreads();
+    stage2(y + 1, j);
+    if (t < 2) stage2(y + 1, j2);
+    __syncthreads();
+    if (active) {
+      const float* pm = s_phi[(y - 1) & 7];
+      const float* p0 = s_phi[y & 7];
+      const float* pp = s_phi[(y + 1) & 7];
+      const float* mm = s_mu[(y - 1) & 3];
+      const float* m0 = s_mu[y & 3];
+      const float* mp = s_mu[(y + 1) & 3];
+      const float phi = p0[j];
+      const float rho = c.a * phi + c.b;
+      const float fsx = -phi * ddx(mm, m0, mp, j), fsy = -phi * ddy(mm, m0, mp, j);
+      const float fbx = rho * c.accel_x, fby = -(rho - c.rho_mean) * c.gravity;
+      const float corr = c.aM * lap9(mm, m0, mp, j);
+      float mx = 0.f, my = 0.f, s = 0.f;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        mx += CX[i] * fpop[i];
+        my += CY[i] * fpop[i];
+        if (i > 0) s += fpop[i];
+      }
+      const float inv = rcp(rho - 0.5f * corr);
+      const float u = (mx + 0.5f * (fsx + fbx)) * inv;
+      const float v = (my + 0.5f * (fsy + fby)) * inv;
+      const float Fx = fsx + fbx + u * corr, Fy = fsy + fby + v * corr;
+      const float drx = c.a * ddx(pm, p0, pp, j), dry = c.a * ddy(pm, p0, pp, j);
+      const float usq15 = 1.5f * (u * u + v * v);
+      // p = cs^2/(1 - w0) [sum_{i>0} f_i + u.grad rho / 2 + rho w0 s_0(u)], cs^2/(1-w0) = 3/5
+      const float pr = 0.6f * (s + 0.5f * (u * drx + v * dry) - WT[0] * rho * usq15);
+      const uint32_t off = ((uint32_t)y * nx + xc) * 4u;
+      stb(ru, u, off, 0);
+      stb(rv, v, off, 0);
+      stb(rpr, pr, off, 0);
+      if (a.fdst) {
+        const float om = c.omega_f, om1 = 1.0f - om;
+        const float p3 = 3.0f * pr;  // p / cs^2
+        const float uF = u * Fx + v * Fy;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          const float cu = CX[i] * u + CY[i] * v;
+          const float cF = CX[i] * Fx + CY[i] * Fy;
+          const float cr = CX[i] * drx + CY[i] * dry;
+          const float su = cu * (3.0f + 4.5f * cu) - usq15;
+          const float feq = WT[i] * (p3 + rho * su) - (i == 0 ? p3 : 0.0f);
+          const float G = WT[i] * (3.0f * (cF - uF) + 9.0f * cu * cF + 3.0f * cu * cr);
+          stb(rfd, om1 * fpop[i] + om * feq + c.srcf * G, off, i * pb);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fpop[i] = fnext[i];
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Initial state: g = g^eq(phi0, mu[phi0], u(t0)); with NS f = f^eq(0, rho(phi0), u0).
+template <bool WALLS>
+__device__ __forceinline__ float field_at(const float* f, int nx, int ny, int x, int y) {
+  x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
+  float sg;
+  y = row_of<WALLS>(y, ny, sg);
+  return f[(uint32_t)y * nx + x];
+}
+
+template <bool WALLS>
+__device__ __forceinline__ void stencil_at(const float* f, int nx, int ny, int x, int y,
+                                           float& gx, float& gy, float& lap) {
+  float v[3][3];
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) v[dy + 1][dx + 1] = field_at<WALLS>(f, nx, ny, x + dx, y + dy);
+  gx = ddx(v[0], v[1], v[2], 1);
+  gy = ddy(v[0], v[1], v[2], 1);
+  lap = lap9(v[0], v[1], v[2], 1);
+}
+
+// The stored buffer holds post-collision populations, which the next step pulls:
+// g_i(y) = stored_i(y - c_i), or stored_opp(i)(y) when y - c_i lies beyond a wall.
+// The initial state is written in that form, so that the first pull returns
+// g_i = g_i^eq(phi0, mu[phi0], u(t0)) (and f_i = f_i^eq(0, rho(phi0), u0)) at every node.
+template <bool WALLS>
+__device__ __forceinline__ uint32_t push_index(int nx, int ny, uint32_t plane, int x, int y,
+                                               int i) {
+  int ty = y - CY[i];
+  if (WALLS && (ty < 0 || ty >= ny)) {
+    constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    return (uint32_t)OPP[i] * plane + (uint32_t)y * nx + x;
+  }
+  int tx = x - CX[i];
+  tx = tx < 0 ? tx + nx : (tx >= nx ? tx - nx : tx);
+  ty = ty < 0 ? ty + ny : (ty >= ny ? ty - ny : ty);
+  return (uint32_t)i * plane + (uint32_t)ty * nx + tx;
+}
+
+template <bool WALLS, int VMODE>
+__global__ void __launch_bounds__(256) k_init(const Coef c, int nx, int ny, uint32_t plane,
+                                              const float* __restrict__ phi0, const float* ax,
+                                              const float* ay, const float* bx, const float* by,
+                                              const float* ux, const float* uy, float tf,
+                                              float* __restrict__ g, float* __restrict__ f) {
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+  if (x >= nx) return;
+  const uint32_t k = (uint32_t)y * nx + x;
+  float gx, gy, lap;
+  stencil_at<WALLS>(phi0, nx, ny, x, y, gx, gy, lap);
+  const float phi = phi0[k];
+  const float mu = mu_bulk(c, phi) - c.kappa * lap;
+  float u = 0.f, v = 0.f;
+  if (VMODE == VEL_SEP) {
+    u = tf * ax[x] * ay[y];
+    v = tf * bx[x] * by[y];
+  } else if (ux) {
+    u = tf * ux[k];
+    v = tf * uy[k];
+  }
+  // g^eq of Eq. geq (no source term); g_0 through sum_i g_i^eq = phi as in collide_g
+  const float em = c.eta * mu, usq15 = 1.5f * (u * u + v * v), A = em - phi * usq15;
+  float geq[9];
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const float cu = CX[i] * u + CY[i] * v;
+    geq[i] = WT[i] * (A + phi * cu * (3.0f + 4.5f * cu));
+  }
+  close_mass((double)phi, geq);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) g[push_index<WALLS>(nx, ny, plane, x, y, i)] = geq[i];
+  if (f) {
+    const float rho = c.a * phi + c.b;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const float cu = CX[i] * u + CY[i] * v;
+      f[push_index<WALLS>(nx, ny, plane, x, y, i)] = WT[i] * rho * (cu * (3.0f + 4.5f * cu) - usq15);
+    }
+  }
+}
+
+template <bool WALLS>
+__global__ void __launch_bounds__(256) k_phi_field(const float* __restrict__ g, uint32_t plane,
+                                                   int nx, int ny, float* __restrict__ phi) {
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+  if (x >= nx) return;
+  float p[9];
+  pull9<WALLS>(make_rsrc(g, 9u * plane * 4u), plane * 4u, nx, ny, y, x, x == 0 ? nx - 1 : x - 1,
+               x == nx - 1 ? 0 : x + 1, p);
+  phi[(uint32_t)y * nx + x] = sum9(p);
+}
+
+template <bool WALLS>
+__global__ void __launch_bounds__(256) k_mu_field(const Coef c, const float* __restrict__ phi,
+                                                  int nx, int ny, float* __restrict__ mu) {
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+  if (x >= nx) return;
+  float gx, gy, lap;
+  stencil_at<WALLS>(phi, nx, ny, x, y, gx, gy, lap);
+  mu[(uint32_t)y * nx + x] = mu_bulk(c, phi[(uint32_t)y * nx + x]) - c.kappa * lap;
+}
+
+__global__ void __launch_bounds__(256) k_velocity(int vmode, int nx, int ny, const float* ax,
+                                                  const float* ay, const float* bx,
+                                                  const float* by, const float* ux,
+                                                  const float* uy, float tf, float* u,
+                                                  float* v) {
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+  if (x >= nx) return;
+  const uint32_t k = (uint32_t)y * nx + x;
+  if (vmode == VEL_SEP) {
+    if (u) u[k] = tf * ax[x] * ay[y];
+    if (v) v[k] = tf * bx[x] * by[y];
+  } else {
+    if (u) u[k] = ux ? tf * ux[k] : 0.0f;
+    if (v) v[k] = uy ? tf * uy[k] : 0.0f;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_fill(float* d, float value, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) d[i] = value;
+}
+
+// ---------------------------------------------------------------------------------
+// FP64 diagnostics: a fixed grid of blocks, each thread a fixed strided set of nodes,
+// then a fixed-order tree in LDS and one final block: bitwise reproducible.
+constexpr int DIAG_BLOCKS = 512;
+constexpr int DIAG_THREADS = 256;
+constexpr int NDIAG = 8;
+
+template <bool WALLS>
+__global__ void __launch_bounds__(DIAG_THREADS) k_diag_partial(const Coef c,
+                                                               const float* __restrict__ phi,
+                                                               const float* __restrict__ ref,
+                                                               int nx, int ny,
+                                                               double* __restrict__ part) {
+  __shared__ double sh[NDIAG][DIAG_THREADS];
+  double acc[NDIAG] = {0, 0, 0, 0, 0, -INFINITY, INFINITY, 0};
+  const int64_t n = (int64_t)nx * ny;
+  for (int64_t k = (int64_t)blockIdx.x * DIAG_THREADS + threadIdx.x; k < n;
+       k += (int64_t)DIAG_BLOCKS * DIAG_THREADS) {
+    const float pf = phi[k];
+    if (!isfinite(pf)) {
+      acc[7] += 1.0;
+      continue;
+    }
+    const int y = (int)(k / nx), x = (int)(k - (int64_t)y * nx);
+    float gx, gy, lap;
+    stencil_at<WALLS>(phi, nx, ny, x, y, gx, gy, lap);
+    const double v = pf;
+    const double fa = v - c.phia, fb = v - c.phib;
+    acc[0] += v;
+    acc[1] += fabs(v);
+    // Eq. freeEnergy: beta (phi - phi_a)^2 (phi - phi_b)^2 + kappa/2 |grad phi|^2
+    acc[2] += 0.5 * (double)c.beta2 * fa * fa * fb * fb +
+              0.5 * (double)c.kappa * ((double)gx * gx + (double)gy * gy);
+    if (ref) {
+      const double r = ref[k];
+      acc[3] += (v - r) * (v - r);
+      acc[4] += r * r;
+    }
+    acc[5] = fmax(acc[5], v);
+    acc[6] = fmin(acc[6], v);
+  }
+#pragma unroll
+  for (int q = 0; q < NDIAG; ++q) sh[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int s = DIAG_THREADS / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+#pragma unroll
+      for (int q = 0; q < NDIAG; ++q) {
+        const double o = sh[q][threadIdx.x + s];
+        double& m = sh[q][threadIdx.x];
+        m = q == 5 ? fmax(m, o) : (q == 6 ? fmin(m, o) : m + o);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < NDIAG) part[blockIdx.x * NDIAG + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(DIAG_THREADS) k_diag_final(const double* __restrict__ part,
+                                                             double* __restrict__ out) {
+  __shared__ double sh[NDIAG][DIAG_THREADS];
+  double acc[NDIAG] = {0, 0, 0, 0, 0, -INFINITY, INFINITY, 0};
+  for (int b = threadIdx.x; b < DIAG_BLOCKS; b += DIAG_THREADS) {
+#pragma unroll
+    for (int q = 0; q < NDIAG; ++q) {
+      const double o = part[b * NDIAG + q];
+      acc[q] = q == 5 ? fmax(acc[q], o) : (q == 6 ? fmin(acc[q], o) : acc[q] + o);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NDIAG; ++q) sh[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int s = DIAG_THREADS / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+#pragma unroll
+      for (int q = 0; q < NDIAG; ++q) {
+        const double o = sh[q][threadIdx.x + s];
+        double& m = sh[q][threadIdx.x];
+        m = q == 5 ? fmax(m, o) : (q == 6 ? fmin(m, o) : m + o);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < NDIAG) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+template <int TX, bool WALLS, int VMODE>
+hipError_t phi_step_m(bool model2, const StepArgs& a, int nb, hipStream_t s) {
+  if (model2)
+    hipLaunchKernelGGL((k_phi_step<TX, WALLS, VMODE, true>), dim3(nb), dim3(TX), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_phi_step<TX, WALLS, VMODE, false>), dim3(nb), dim3(TX), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int TX, bool WALLS>
+hipError_t phi_step_v(int vmode, bool model2, const StepArgs& a, int nb, hipStream_t s) {
+  switch (vmode) {
+    case VEL_SEP: return phi_step_m<TX, WALLS, VEL_SEP>(model2, a, nb, s);
+    case VEL_FIELD: return phi_step_m<TX, WALLS, VEL_FIELD>(model2, a, nb, s);
+    default: return phi_step_m<TX, WALLS, VEL_NSFIELD>(model2, a, nb, s);
+  }
+}
+
+template <int TX>
+hipError_t phi_step_w(bool walls, int vmode, bool model2, const StepArgs& a, int nb,
+                      hipStream_t s) {
+  return walls ? phi_step_v<TX, true>(vmode, model2, a, nb, s)
+               : phi_step_v<TX, false>(vmode, model2, a, nb, s);
+}
+
+}  // namespace
+
+hipError_t launch_phi_step(int tx, bool walls, int vmode, bool model2, const StepArgs& a,
+                           int nblocks, hipStream_t s) {
+  switch (tx) {
+    case 64: return phi_step_w<64>(walls, vmode, model2, a, nblocks, s);
+    case 128: return phi_step_w<128>(walls, vmode, model2, a, nblocks, s);
+    case 256: return phi_step_w<256>(walls, vmode, model2, a, nblocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_ns_step(int tx, bool walls, const NsArgs& a, int nblocks, hipStream_t s) {
+  switch (tx) {
+    case 64:
+      if (walls) hipLaunchKernelGGL((k_ns_step<64, true>), dim3(nblocks), dim3(64), 0, s, a);
+      else hipLaunchKernelGGL((k_ns_step<64, false>), dim3(nblocks), dim3(64), 0, s, a);
+      break;
+    case 128:
+      if (walls) hipLaunchKernelGGL((k_ns_step<128, true>), dim3(nblocks), dim3(128), 0, s, a);
+      else hipLaunchKernelGGL((k_ns_step<128, false>), dim3(nblocks), dim3(128), 0, s, a);
+      break;
+    case 256:
+      if (walls) hipLaunchKernelGGL((k_ns_step<256, true>), dim3(nblocks), dim3(256), 0, s, a);
+      else hipLaunchKernelGGL((k_ns_step<256, false>), dim3(nblocks), dim3(256), 0, s, a);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_init(bool walls, int vmode, const Coef& c, int nx, int ny, uint32_t plane,
+                       const float* phi0, const float* ax, const float* ay, const float* bx,
+                       const float* by, const float* ux, const float* uy, float tf, float* g,
+                       float* f, hipStream_t s) {
+  const dim3 grid((nx + 255) / 256, ny);
+  const bool sep = vmode == VEL_SEP;
+  if (walls && sep)
+    hipLaunchKernelGGL((k_init<true, VEL_SEP>), grid, dim3(256), 0, s, c, nx, ny, plane, phi0, ax, ay, bx, by, ux, uy, tf, g, f);
+  else if (walls)
+    hipLaunchKernelGGL((k_init<true, VEL_FIELD>), grid, dim3(256), 0, s, c, nx, ny, plane, phi0, ax, ay, bx, by, ux, uy, tf, g, f);
+  else if (sep)
+    hipLaunchKernelGGL((k_init<false, VEL_SEP>), grid, dim3(256), 0, s, c, nx, ny, plane, phi0, ax, ay, bx, by, ux, uy, tf, g, f);
+  else
+    hipLaunchKernelGGL((k_init<false, VEL_FIELD>), grid, dim3(256), 0, s, c, nx, ny, plane, phi0, ax, ay, bx, by, ux, uy, tf, g, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_phi_field(bool walls, const float* g, uint32_t plane, int nx, int ny,
+                            float* phi, hipStream_t s) {
+  const dim3 grid((nx + 255) / 256, ny);
+  if (walls) hipLaunchKernelGGL((k_phi_field<true>), grid, dim3(256), 0, s, g, plane, nx, ny, phi);
+  else hipLaunchKernelGGL((k_phi_field<false>), grid, dim3(256), 0, s, g, plane, nx, ny, phi);
+  return hipGetLastError();
+}
+
+hipError_t launch_mu_field(bool walls, const Coef& c, const float* phi, int nx, int ny,
+                           float* mu, hipStream_t s) {
+  const dim3 grid((nx + 255) / 256, ny);
+  if (walls) hipLaunchKernelGGL((k_mu_field<true>), grid, dim3(256), 0, s, c, phi, nx, ny, mu);
+  else hipLaunchKernelGGL((k_mu_field<false>), grid, dim3(256), 0, s, c, phi, nx, ny, mu);
+  return hipGetLastError();
+}
+
+hipError_t launch_velocity_field(int vmode, int nx, int ny, const float* ax, const float* ay,
+                                 const float* bx, const float* by, const float* ux,
+                                 const float* uy, float tf, float* u, float* v,
+                                 hipStream_t s) {
+  const dim3 grid((nx + 255) / 256, ny);
+  hipLaunchKernelGGL(k_velocity, grid, dim3(256), 0, s, vmode, nx, ny, ax, ay, bx, by, ux, uy,
+                     tf, u, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(float* dst, float value, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dst, value, n);
+  return hipGetLastError();
+}
+
+int diag_partial_blocks() { return DIAG_BLOCKS; }
+
+hipError_t launch_diag(bool walls, const Coef& c, const float* phi, const float* ref, int nx,
+                       int ny, double* partial, double* out, hipStream_t s) {
+  if (walls)
+    hipLaunchKernelGGL((k_diag_partial<true>), dim3(DIAG_BLOCKS), dim3(DIAG_THREADS), 0, s, c, phi, ref, nx, ny, partial);
+  else
+    hipLaunchKernelGGL((k_diag_partial<false>), dim3(DIAG_BLOCKS), dim3(DIAG_THREADS), 0, s, c, phi, ref, nx, ny, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(DIAG_THREADS), 0, s, partial, out);
+  return hipGetLastError();
+}
+
+}  // namespace lbmch

@@ -1,0 +1,88 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every function
+include/lbm_ch.h declares, and rejects invalid arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1805_00007_amd as lbm
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                      "include", "lbm_ch.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_ch_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert len(names) >= 13
+    L = ctypes.CDLL(lbm.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(lbm.EXPORTS)
+
+
+def _params(**kw):
+    return lbm.make_params(64, 48, **kw)
+
+
+@pytest.mark.parametrize("bad", [dict(tau_g=0.5), dict(tau_g=0.2), dict(model=3),
+                                 dict(rho_a=0.0), dict(rho_b=-1.0), dict(phi_a=-1.0),
+                                 dict(width=0.0), dict(walls=2), dict(velocity_mode=7),
+                                 dict(ns=True, tau_f=0.5), dict(sigma=float("nan"))])
+def test_invalid_params_rejected(bad):
+    p = _params(**bad)
+    assert lbm.lib().lbm_ch_workspace_bytes(ctypes.byref(p)) == 0
+    ctx = ctypes.c_void_p()
+    st = lbm.lib().lbm_ch_init(ctypes.byref(ctx), ctypes.byref(p), None,
+                               ctypes.c_void_p(1 << 20), 1 << 40, ctypes.c_void_p(1 << 20), None)
+    assert st == lbm.EINVAL and not ctx.value
+
+
+def test_sizes_rejected():
+    for nx, ny in [(3, 64), (64, 3), (40000, 40000)]:
+        p = lbm.make_params(nx, ny)
+        assert lbm.lib().lbm_ch_workspace_bytes(ctypes.byref(p)) == 0
+
+
+def test_workspace_and_alignment_checks():
+    L = lbm.lib()
+    p = _params()
+    need = L.lbm_ch_workspace_bytes(ctypes.byref(p))
+    assert need >= 2 * 9 * 64 * 48 * 4
+    pns = _params(ns=True, tau_f=0.8)
+    assert L.lbm_ch_workspace_bytes(ctypes.byref(pns)) >= 2 * need - 4 * 64 * 48 * 8
+    ctx = ctypes.c_void_p()
+    vel = lbm.Velocity()
+    args = lambda ws, nb, phi: L.lbm_ch_init(ctypes.byref(ctx), ctypes.byref(p),
+                                             ctypes.byref(vel), ctypes.c_void_p(ws), nb,
+                                             ctypes.c_void_p(phi), None)
+    assert args(0, need, 4096) == lbm.EINVAL                 # no workspace
+    assert args(4096 + 64, need, 4096) == lbm.EINVAL         # workspace not 256-aligned
+    assert args(4096, need - 1, 4096) == lbm.EINVAL          # workspace too small
+    assert args(4096, need, 0) == lbm.EINVAL                 # no phi0
+    assert args(4096, need, 4098) == lbm.EINVAL              # phi0 not 4-aligned
+    # separable mode without tables
+    p.velocity_mode = lbm.VEL_SEPARABLE
+    assert args(4096, need, 4096) == lbm.EINVAL
+    # a storage mode that is not built
+    p.velocity_mode = lbm.VEL_NONE
+    p.storage = 9
+    assert args(4096, need, 4096) == lbm.EUNSUPPORTED
+
+
+def test_context_calls_reject_null_and_strerror():
+    L = lbm.lib()
+    assert L.lbm_ch_step(None, 1, None) == lbm.ESTATE
+    assert L.lbm_ch_moments(None, None, None, None, None, None, None) == lbm.ESTATE
+    assert L.lbm_ch_diagnostics(None, None, None, None) == lbm.ESTATE
+    assert L.lbm_ch_step_count(None) == -1
+    assert L.lbm_ch_destroy(None) == lbm.OK
+    for st in (lbm.OK, lbm.EINVAL, lbm.EUNSUPPORTED, lbm.EHIP, lbm.ENONFINITE, lbm.ESTATE):
+        assert L.lbm_ch_strerror(st)
+    assert L.lbm_ch_strerror(12345) == b"unknown status"

@@ -1,0 +1,195 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle, element by
+element, on the same seeded inputs.
+
+Tolerance.  The GPU computes in float32.  After n steps the FP32 rounding of a
+lattice Boltzmann update accumulates roughly like a random walk of ~1e-7 relative
+per step, and the diffusive part of the scheme damps it, so the relative L2 error
+of phi after 1000 steps is expected around 1e-6 - 1e-5; the gate is the stated
+1e-4 (relative L2 of phi) with mass drift |sum phi(t) - sum phi(0)| / sum |phi(0)|
+<= 1e-6, and a pointwise max error bound of 1e-3 on phi in [-1, 1].
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+REL_L2 = 1e-4
+MAX_ABS = 1e-3
+DRIFT = 1e-6
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import paper_1805_00007_amd as lbm
+    lbm.lib()
+    return lbm
+
+
+def _oracle_state(w, p):
+    if w.field is not None:
+        return oracle.State(p, w.phi0, *w.field)
+    if w.velocity is not None:
+        U, V = workloads.separable_field(w.velocity)
+        return oracle.State(p, w.phi0, U, V, w.velocity["tf"])
+    return oracle.State(p, w.phi0)
+
+
+def _compare(lbm, w, steps, walls=0, ns=False, check_fields=False, **over):
+    phys = dict(w.phys)
+    phys.update(over)
+    kw = dict(phys)
+    if ns:
+        kw["ns"] = True
+    s = (lbm.Solver(w.nx, w.ny, w.phi0, field=w.field, walls=walls, **kw) if w.field is not None
+         else lbm.Solver(w.nx, w.ny, w.phi0, velocity=w.velocity, walls=walls, **kw))
+    s.step(steps)
+    m = s.moments()
+    torch.cuda.synchronize()
+    got = {k: v.double().cpu().numpy() for k, v in m.items()}
+    op = oracle.Params(nx=w.nx, ny=w.ny, walls=walls, ns=1 if ns else 0,
+                       **{k: v for k, v in phys.items() if k != "ns"})
+    o = _oracle_state(w, op).run(steps)
+    phi, mu, u, v, p = o.fields()
+    err = oracle.rel_l2(got["phi"], phi)
+    drift = abs(got["phi"].sum() - w.phi0.sum()) / np.abs(w.phi0).sum()
+    print("%s %dx%d steps=%d rel_l2=%.3e max=%.3e drift=%.3e" % (
+        w.name, w.nx, w.ny, steps, err, np.abs(got["phi"] - phi).max(), drift))
+    assert err <= REL_L2
+    assert np.abs(got["phi"] - phi).max() <= MAX_ABS
+    assert drift <= DRIFT
+    if check_fields:
+        scale_mu = max(np.abs(mu).max(), 1e-30)
+        assert np.abs(got["mu"] - mu).max() <= 1e-3 * scale_mu
+        scale_u = max(np.abs(u).max(), np.abs(v).max(), 1e-30)
+        assert np.abs(got["u"] - u).max() <= 1e-3 * scale_u
+        assert np.abs(got["v"] - v).max() <= 1e-3 * scale_u
+        if ns:
+            assert np.abs(got["p"] - p).max() <= 1e-3 * max(np.abs(p).max(), 1e-30)
+    s.close()
+    return err
+
+
+def test_ragged_periodic_vortex_model2(lbm):
+    """Several tiles in x and y with ragged tails (200 = 128 + 72 columns, 136 = 4*32 + 8
+    rows), time-dependent vortex, Model-II."""
+    w = workloads.vortex(200, period=400, steps=300)
+    w.ny = 136
+    w.phi0 = w.phi0[:136].copy()
+    w.velocity["ay"] = w.velocity["ay"][:136]
+    w.velocity["by"] = w.velocity["by"][:136]
+    _compare(lbm, w, 300, check_fields=True)
+
+
+def test_translation_128_model1_and_model2(lbm):
+    for model in (1, 2):
+        _compare(lbm, workloads.translation(128, 1000, model=model), 1000)
+
+
+def test_vortex_512_1000_steps(lbm):
+    _compare(lbm, workloads.vortex(512, period=20000, steps=1000), 1000)
+
+
+@pytest.mark.parametrize("tau", [0.7, 1.3])
+def test_general_tau(lbm, tau):
+    _compare(lbm, workloads.vortex(96, period=300, steps=200), 200, tau_g=tau)
+
+
+def test_stored_velocity_field(lbm):
+    n = 128
+    U, V = workloads.random_stream_function(n, 8, seed=1, umax=0.05)
+    w = workloads.Workload("field128", n, n, 300, dict(workloads.PRESCRIBED),
+                           workloads.random_blobs(n, 5, 4.0), field=(U, V))
+    _compare(lbm, w, 300, check_fields=True)
+
+
+def test_walls_prescribed(lbm):
+    w = workloads.vortex(96, period=300, steps=200)
+    _compare(lbm, w, 200, walls=1)
+
+
+def test_rayleigh_taylor_coupled_ns(lbm):
+    w = workloads.rayleigh_taylor_case(nx=64, ny=256, steps=600, reynolds=300.0)
+    _compare(lbm, w, 600, walls=1, ns=True, check_fields=True)
+
+
+def test_small_and_degenerate_grids(lbm):
+    for n in (4, 5, 8, 70):
+        w = workloads.Workload("noise%d" % n, n, n + 3, 40, dict(workloads.PRESCRIBED),
+                               workloads.perturbed_uniform(n, n + 3, 0.2, 0.5, seed=n),
+                               workloads.uniform_velocity(n, n + 3, 0.03, -0.02, 40))
+        _compare(lbm, w, 40)
+
+
+def test_zero_steps_returns_initial_field(lbm):
+    w = workloads.translation(64, 0)
+    s = lbm.Solver(64, 64, w.phi0, velocity=w.velocity, **w.phys)
+    phi = s.phi().double().cpu().numpy()
+    assert np.abs(phi - w.phi0).max() < 1e-6
+    s.close()
+
+
+def test_deterministic_and_resumable(lbm):
+    w = workloads.vortex(160, period=300, steps=100)
+    a = lbm.Solver(160, 160, w.phi0, velocity=w.velocity, **w.phys).step(60)
+    ckpt, n = a.save_state()
+    a.step(40)
+    b = lbm.Solver(160, 160, w.phi0, velocity=w.velocity, **w.phys).step(100)
+    c = lbm.Solver(160, 160, w.phi0, velocity=w.velocity, **w.phys).load_state(ckpt, n).step(40)
+    pa, pb, pc = a.phi(), b.phi(), c.phi()
+    torch.cuda.synchronize()
+    assert torch.equal(pa, pb) and torch.equal(pa, pc)
+    assert a.step_count == b.step_count == c.step_count == 100
+
+
+def test_diagnostics_match_oracle(lbm):
+    w = workloads.vortex(128, period=400, steps=100)
+    s = lbm.Solver(128, 128, w.phi0, velocity=w.velocity, **w.phys).step(100)
+    d = s.diagnostics(phi_ref=w.phi0)
+    phi = s.phi().double().cpu().numpy()
+    ref = oracle.diag(oracle.Params(nx=128, ny=128, **w.phys), phi, w.phi0)
+    for k in ("mass", "abs_mass", "err2", "ref2", "max", "min"):
+        assert d[k] == pytest.approx(ref[k], rel=1e-9, abs=1e-9), k
+    # the GPU forms the isotropic gradient of the energy in float32
+    assert d["energy"] == pytest.approx(ref["energy"], rel=1e-5)
+    assert d["nonfinite"] == 0
+    assert s.check_finite() == lbm.OK
+
+
+def _golden(name):
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    if not os.path.exists(path):
+        pytest.skip("stored oracle samples missing: run tests/golden/make_golden.py")
+    return np.load(path)
+
+
+@pytest.mark.parametrize("case,make", [
+    ("vortex2048_oracle_1000.npz", lambda: workloads.metric2048(steps=1000)),
+    ("vortex512_oracle_20000.npz", lambda: workloads.vortex(512, period=20000)),
+])
+def test_full_size_against_stored_oracle_samples(lbm, case, make):
+    """Full-size workloads in the launch configuration the benchmark times, compared at
+    4096 stored FP64 oracle samples (2048^2 after 1000 steps; 512^2 after the full period
+    T = 20000 of the reversing vortex), plus mass drift and E_phi against phi(0)."""
+    g = _golden(case)
+    w = make()
+    s = lbm.solver_for(w).step(int(g["steps"]))
+    d = s.diagnostics(phi_ref=w.phi0)
+    phi = s.phi().double().cpu().numpy().ravel()
+    s.close()
+    idx, ref = g["index"], g["phi"]
+    rel = float(np.sqrt(((phi[idx] - ref) ** 2).sum() / (ref ** 2).sum()))
+    drift = abs(d["mass"] - float(g["mass0"])) / float(g["abs_mass0"])
+    e_phi = np.sqrt(d["err2"] / d["ref2"])
+    print("%s: sampled rel_l2=%.3e max=%.3e drift=%.3e E_phi gpu=%.5e oracle=%.5e" % (
+        case, rel, np.abs(phi[idx] - ref).max(), drift, e_phi, float(g["e_phi"])))
+    assert rel <= REL_L2
+    assert np.abs(phi[idx] - ref).max() <= MAX_ABS
+    assert drift <= DRIFT
+    assert abs(e_phi - float(g["e_phi"])) <= 1e-4 * max(float(g["e_phi"]), 1e-3)
+    assert d["max"] == pytest.approx(float(g["max"]), abs=1e-4)
+    assert d["min"] == pytest.approx(float(g["min"]), abs=1e-4)
