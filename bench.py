@@ -104,7 +104,25 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=25,
                     help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain device copy of 1 GiB x 10 (counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        dst.copy_(src)
+        e0.record()
+        for _ in range(10):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        print(json.dumps({"copy_probe_bytes_read_per_launch": src.numel() * 4,
+                          "launches": 11, "copy_GBps_read_plus_write":
+                          round(2 * src.numel() * 4 / (ms * 1e-3) / 1e9, 1)}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only; the multi-GPU domain "
               "decomposition is a design, not a runnable path (--gpus must be 1)",

@@ -115,7 +115,8 @@ static void choose_tiles(lbm_ch_ctx* c) {
   const char* env = getenv("LBM_CH_TILE");
   if (env) {
     int a = 0, b = 0;
-    if (sscanf(env, "%dx%d", &a, &b) == 2 && (a == 64 || a == 128 || a == 256) && b >= 1) {
+    if (sscanf(env, "%dx%d", &a, &b) == 2 && (a == 64 || a == 128 || a == 256 || a == 512) &&
+        b >= 1) {
       tx = a;
       ty = b;
     }

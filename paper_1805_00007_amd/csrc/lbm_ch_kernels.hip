@@ -65,34 +65,36 @@ __device__ __forceinline__ void stb(rsrc_t r, float v, uint32_t voff, uint32_t s
 
 // Pull of the nine populations arriving at (x, y): g_i(x, y) = g_i*(x - c_i, y - c_i).
 // With walls, a population whose source lies beyond a wall is the opposite one that
-// left (x, y) (half-way bounce-back).  y is a lattice row; xm/xp are x-1, x+1 wrapped;
-// pb is the plane stride in bytes.
+// left (x, y) (half-way bounce-back).  y is a lattice row (block-uniform); vc, vm, vp
+// are the byte offsets of columns x, x-1, x+1 (wrapped) within a row; rb is the row
+// pitch and pb the plane stride in bytes.  Plane and row offsets travel in the
+// instruction's scalar offset, so a load costs no vector ALU work.
 template <bool WALLS>
-__device__ __forceinline__ void pull9(rsrc_t s, uint32_t pb, int nx, int ny, int y, int xc,
-                                      int xm, int xp, float g[9]) {
+__device__ __forceinline__ void pull9(rsrc_t s, uint32_t pb, uint32_t rb, int ny, int y,
+                                      uint32_t vc, uint32_t vm, uint32_t vp, float g[9]) {
   const int ym = y == 0 ? ny - 1 : y - 1;
   const int yp = y == ny - 1 ? 0 : y + 1;
-  const uint32_t rc = (uint32_t)y * nx, rm = (uint32_t)ym * nx, rp = (uint32_t)yp * nx;
-  g[0] = ldb(s, (rc + xc) * 4u, 0);
-  g[1] = ldb(s, (rc + xm) * 4u, pb);
-  g[3] = ldb(s, (rc + xp) * 4u, 3 * pb);
+  const uint32_t rc = (uint32_t)y * rb, rm = (uint32_t)ym * rb, rp = (uint32_t)yp * rb;
+  g[0] = ldb(s, vc, rc);
+  g[1] = ldb(s, vm, pb + rc);
+  g[3] = ldb(s, vp, 3 * pb + rc);
   if (WALLS && y == 0) {
-    g[2] = ldb(s, (rc + xc) * 4u, 4 * pb);
-    g[5] = ldb(s, (rc + xc) * 4u, 7 * pb);
-    g[6] = ldb(s, (rc + xc) * 4u, 8 * pb);
+    g[2] = ldb(s, vc, 4 * pb + rc);
+    g[5] = ldb(s, vc, 7 * pb + rc);
+    g[6] = ldb(s, vc, 8 * pb + rc);
   } else {
-    g[2] = ldb(s, (rm + xc) * 4u, 2 * pb);
-    g[5] = ldb(s, (rm + xm) * 4u, 5 * pb);
-    g[6] = ldb(s, (rm + xp) * 4u, 6 * pb);
+    g[2] = ldb(s, vc, 2 * pb + rm);
+    g[5] = ldb(s, vm, 5 * pb + rm);
+    g[6] = ldb(s, vp, 6 * pb + rm);
   }
   if (WALLS && y == ny - 1) {
-    g[4] = ldb(s, (rc + xc) * 4u, 2 * pb);
-    g[7] = ldb(s, (rc + xc) * 4u, 5 * pb);
-    g[8] = ldb(s, (rc + xc) * 4u, 6 * pb);
+    g[4] = ldb(s, vc, 2 * pb + rc);
+    g[7] = ldb(s, vc, 5 * pb + rc);
+    g[8] = ldb(s, vc, 6 * pb + rc);
   } else {
-    g[4] = ldb(s, (rp + xc) * 4u, 4 * pb);
-    g[7] = ldb(s, (rp + xp) * 4u, 7 * pb);
-    g[8] = ldb(s, (rp + xm) * 4u, 8 * pb);
+    g[4] = ldb(s, vc, 4 * pb + rp);
+    g[7] = ldb(s, vp, 7 * pb + rp);
+    g[8] = ldb(s, vm, 8 * pb + rp);
   }
 }
 
@@ -174,16 +176,21 @@ __device__ __forceinline__ void collide_g(const Coef& c, float phi, float phi_lo
 // Fused phase-field step.
 //   VMODE VEL_SEP: u = tf ax[x] ay[y]; VEL_FIELD: u = tf ux[y][x];
 //   VEL_NSFIELD: u, p from the NS step, F1 = (phi/rho)(F_s + F_b - grad p).
-template <int TX, bool WALLS, int VMODE>
-struct Pull {
-  static constexpr bool VF = VMODE != VEL_SEP;
-  static constexpr bool NSC = VMODE == VEL_NSFIELD;
+// One row record of the register pipeline: the pulled populations (plus velocity and
+// pressure in the field modes) and the order parameter and velocity of the row.
+struct RowRec {
   float g[9];
-  float u, v, p;
+  float lu, lv, lp;       // loaded velocity / pressure (field modes)
+  float phi, lo, u, v;    // stage-1 results (u, v in the field modes)
+  float fy_u, fy_v;       // separable mode: ay[y], by[y] as loaded, then times tf
 };
 
+#ifndef WPE_PHI
+#define WPE_PHI 4
+#endif
 template <int TX, bool WALLS, int VMODE, bool MODEL2>
-__global__ void __launch_bounds__(TX) k_phi_step(const StepArgs a) {
+__global__ void __launch_bounds__(TX) __attribute__((amdgpu_waves_per_eu(WPE_PHI, 8)))
+k_phi_step(const StepArgs a) {
   constexpr bool NSC = VMODE == VEL_NSFIELD;
   constexpr bool VFIELD = VMODE != VEL_SEP;
   constexpr int LW = TX + 4;
@@ -195,12 +202,12 @@ __global__ void __launch_bounds__(TX) k_phi_step(const StepArgs a) {
   __shared__ float s_qy[QR][LW];
   __shared__ float s_d[QR][LW];
   __shared__ float s_p[PR][LW];
-  using P = Pull<TX, WALLS, VMODE>;
 
   const Coef& c = a.c;
   const int nx = a.nx, ny = a.ny;
   const uint32_t nodes = (uint32_t)nx * ny;
   const uint32_t pb = a.plane * 4u;
+  const uint32_t rb = (uint32_t)nx * 4u;
   const rsrc_t rsrc = make_rsrc(a.src, 9u * pb);
   const rsrc_t rdst = make_rsrc(a.dst, 9u * pb);
   rsrc_t ru, rv, rp;
@@ -217,21 +224,32 @@ __global__ void __launch_bounds__(TX) k_phi_step(const StepArgs a) {
     L = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   }
   const int x0 = (L % a.nstrips) * TX;
-  const int y0 = (L / a.nstrips) * a.ty;
-  const int rows = min(a.ty, ny - y0);
+  const int chunk = L / a.nstrips;
+  const int rows = min(a.ty, ny - chunk * a.ty);
+  // Vertically adjacent chunks march in opposite directions, so the two blocks that
+  // share a chunk boundary pass it at the same moment (both at their start or both
+  // at their end) and the halo rows one re-reads are still in L2.
+  const int dir = (chunk & 1) ? -1 : 1;
+  const int y0 = dir > 0 ? chunk * a.ty : chunk * a.ty + rows - 1;  // first row marched
 
-  // Own column (wrapped) and its neighbours.
+  // Own column (wrapped) and its neighbours, as byte offsets within a row.
   const int xl = x0 + t;
   const bool active = xl < nx;
   const int xc = xl % nx;
-  const int xm = xc == 0 ? nx - 1 : xc - 1;
-  const int xp = xc == nx - 1 ? 0 : xc + 1;
+  const uint32_t vc = xc * 4u;
+  const uint32_t vm = (xc == 0 ? nx - 1 : xc - 1) * 4u;
+  const uint32_t vp = (xc == nx - 1 ? 0 : xc + 1) * 4u;
   // Halo lanes t < 4: logical columns x0-2, x0-1, x0+TX, x0+TX+1 -> LDS 0, 1, TX+2, TX+3.
   const bool hl = t < 4;
   const int hlog = t < 2 ? x0 - 2 + t : x0 + TX - 2 + t;
   const int hc = ((hlog % nx) + nx) % nx;
-  const int hm = hc == 0 ? nx - 1 : hc - 1;
-  const int hp = hc == nx - 1 ? 0 : hc + 1;
+  // Every lane issues the halo pull, so that the wait-count bookkeeping does not depend
+  // on a branch; lanes other than the four halo lanes use an offset beyond the buffer,
+  // for which a raw buffer load returns 0 without accessing memory.
+  constexpr uint32_t OOB = 0xFFFFFF00u;
+  const uint32_t hvc = hl ? hc * 4u : OOB;
+  const uint32_t hvm = hl ? (hc == 0 ? nx - 1 : hc - 1) * 4u : OOB;
+  const uint32_t hvp = hl ? (hc == nx - 1 ? 0 : hc + 1) * 4u : OOB;
   const int hj = t < 2 ? t : TX + t;
   const int j = t + 2;
   const int j2 = t == 0 ? 1 : TX + 2;  // stage-2 halo column of lanes 0 and 1
@@ -246,38 +264,46 @@ __global__ void __launch_bounds__(TX) k_phi_step(const StepArgs a) {
     }
   }
 
-  // Issue the pull of logical row r at column col (plus velocity and pressure in the
+  // Issue the pull of logical row r at one column (plus velocity and pressure in the
   // field modes) so that one wait covers all of it.
-  auto issue = [&](int r, int col, int cm, int cq, P& Q) {
+  auto issue = [&](int r, uint32_t cc, uint32_t cm, uint32_t cp, RowRec& R) {
     float sg;
     const int sr = row_of<WALLS>(r, ny, sg);
-    pull9<WALLS>(rsrc, pb, nx, ny, sr, col, cm, cq, Q.g);
+    pull9<WALLS>(rsrc, pb, rb, ny, sr, cc, cm, cp, R.g);
+    if (VMODE == VEL_SEP) {
+      // row factors of the separable velocity, fetched with the pull so that one wait
+      // covers both (a later load would make the wait cover the whole prefetch)
+      R.fy_u = a.ay[sr];
+      R.fy_v = a.by[sr];
+    }
     if (VFIELD) {
-      const uint32_t off = ((uint32_t)sr * nx + col) * 4u;
-      Q.u = ldb(ru, off, 0);
-      Q.v = ldb(rv, off, 0);
-      if (NSC) Q.p = ldb(rp, off, 0);
+      R.lu = ldb(ru, cc, (uint32_t)sr * rb);
+      R.lv = ldb(rv, cc, (uint32_t)sr * rb);
+      if (NSC) R.lp = ldb(rp, cc, (uint32_t)sr * rb);
     }
   };
   // Stage 1 for logical row r: phi (and q = phi u, p) into the rings at column jj.
-  auto stage1 = [&](int r, const P& Q, int jj, float axv, float bxv, float& phi, float& lo,
-                    float& u, float& v) {
+  auto stage1 = [&](int r, RowRec& R, int jj, float axv, float bxv, bool wr = true) {
     float sg;
     const int sr = row_of<WALLS>(r, ny, sg);
-    phi = sum9(Q.g, lo);
+    R.phi = sum9(R.g, R.lo);
+    float u, v;
     if (VMODE == VEL_SEP) {
-      u = a.tf * axv * a.ay[sr] * sg;
-      v = a.tf * bxv * a.by[sr] * sg;
+      R.fy_u *= a.tf * sg;
+      R.fy_v *= a.tf * sg;
+      u = axv * R.fy_u;
+      v = bxv * R.fy_v;
     } else {
-      u = a.tf * Q.u * sg;
-      v = a.tf * Q.v * sg;
+      u = R.u = a.tf * R.lu * sg;
+      v = R.v = a.tf * R.lv * sg;
     }
-    s_phi[r & 3][jj] = phi;
+    if (!wr) return;
+    s_phi[r & 3][jj] = R.phi;
     if (MODEL2) {
-      s_qx[r & 3][jj] = phi * u;
-      s_qy[r & 3][jj] = phi * v;
+      s_qx[r & 3][jj] = R.phi * u;
+      s_qy[r & 3][jj] = R.phi * v;
     }
-    if (NSC) s_p[r & 7][jj] = Q.p;
+    if (NSC) s_p[r & 7][jj] = R.lp;
   };
   // Stage 2 for logical row r at LDS column jj: mu (Eq. mu) and D = div(phi u).
   auto stage2 = [&](int r, int jj) {
@@ -290,97 +316,117 @@ __global__ void __launch_bounds__(TX) k_phi_step(const StepArgs a) {
                        ddy(s_qy[(r - 1) & 3], s_qy[r & 3], s_qy[(r + 1) & 3], jj);
     }
   };
-
-  // Prologue: rows y0-2 .. y0+1 through stage 1, rows y0-1 and y0 through stage 2,
-  // and the pull of row y0+2 in flight.
-  P P0, P1, P2, H;
-  float phi0, l0, u0, v0, phi1, l1, u1, v1, phi2, l2, u2, v2, dphi, dl, du, dv;
-  {
-    P A, B;
-    issue(y0 - 2, xc, xm, xp, A);
-    issue(y0 - 1, xc, xm, xp, B);
-    issue(y0, xc, xm, xp, P0);
-    issue(y0 + 1, xc, xm, xp, P1);
-    stage1(y0 - 2, A, j, axc, bxc, dphi, dl, du, dv);
-    stage1(y0 - 1, B, j, axc, bxc, dphi, dl, du, dv);
-    if (hl) {
-      issue(y0 - 2, hc, hm, hp, A);
-      issue(y0 - 1, hc, hm, hp, B);
+  // Stage 3 for lattice row y: F = F1 (+ F2), collision, store.
+  auto stage3 = [&](int y, RowRec& R) {
+    if (!active) return;
+    const float* mm = s_mu[(y - 1) & 3];
+    const float* m0 = s_mu[y & 3];
+    const float* mp = s_mu[(y + 1) & 3];
+    const float mux = ddx(mm, m0, mp, j), muy = ddy(mm, m0, mp, j);
+    const float rho = c.a * R.phi + c.b;
+    float tx = -R.phi * mux, ty = -R.phi * muy;
+    if (NSC) {
+      const float* qm = s_p[(y - 1) & 7];
+      const float* q0 = s_p[y & 7];
+      const float* qp = s_p[(y + 1) & 7];
+      tx += rho * c.accel_x - ddx(qm, q0, qp, j);
+      ty += -(rho - c.rho_mean) * c.gravity - ddy(qm, q0, qp, j);
     }
-    stage1(y0, P0, j, axc, bxc, phi0, l0, u0, v0);
-    stage1(y0 + 1, P1, j, axc, bxc, phi1, l1, u1, v1);
+    const float s1 = R.phi * rcp(rho);
+    float fx = s1 * tx, fy = s1 * ty;
+    if (MODEL2) {
+      const float* dm = s_d[(y - 1) & 3];
+      const float* d0 = s_d[y & 3];
+      const float* dp = s_d[(y + 1) & 3];
+      fx += c.k2 * ddx(dm, d0, dp, j);
+      fy += c.k2 * ddy(dm, d0, dp, j);
+    }
+    const float u = VMODE == VEL_SEP ? axc * R.fy_u : R.u;
+    const float v = VMODE == VEL_SEP ? bxc * R.fy_v : R.v;
+    collide_g(c, R.phi, R.lo, m0[j], u, v, fx, fy, R.g);
+    const uint32_t ro = (uint32_t)y * rb;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) stb(rdst, R.g[i], vc, i * pb + ro);
+  };
+
+  // Prologue: rows y0-2d .. y0+d through stage 1, rows y0-d and y0 through stage 2,
+  // and the pull of row y0+2d in flight (d = dir).
+  //
+  // Register pipeline.  A holds row y (collided in stage 3), B row y+d; the pull of
+  // the next row lands in one of two slots, X0 or X1, which alternate, so registers
+  // with a load in flight are never copied (copying them would make the wave wait for
+  // every outstanding memory operation).  Completed rows move down A <- B <- X by copy.
+  const int d = dir;
+  RowRec A, B, X0, X1, H0;
+  {
+    RowRec T0, T1;
+    issue(y0 - 2 * d, vc, vm, vp, T0);
+    issue(y0 - d, vc, vm, vp, T1);
+    issue(y0, vc, vm, vp, A);
+    issue(y0 + d, vc, vm, vp, B);
+    stage1(y0 - 2 * d, T0, j, axc, bxc);
+    stage1(y0 - d, T1, j, axc, bxc);
     if (hl) {
-      stage1(y0 - 2, A, hj, axh, bxh, dphi, dl, du, dv);
-      stage1(y0 - 1, B, hj, axh, bxh, dphi, dl, du, dv);
-      issue(y0, hc, hm, hp, A);
-      issue(y0 + 1, hc, hm, hp, B);
-      stage1(y0, A, hj, axh, bxh, dphi, dl, du, dv);
-      stage1(y0 + 1, B, hj, axh, bxh, dphi, dl, du, dv);
+      issue(y0 - 2 * d, hvc, hvm, hvp, T0);
+      issue(y0 - d, hvc, hvm, hvp, T1);
+    }
+    stage1(y0, A, j, axc, bxc);
+    stage1(y0 + d, B, j, axc, bxc);
+    if (hl) {
+      stage1(y0 - 2 * d, T0, hj, axh, bxh);
+      stage1(y0 - d, T1, hj, axh, bxh);
+      issue(y0, hvc, hvm, hvp, T0);
+      issue(y0 + d, hvc, hvm, hvp, T1);
+      stage1(y0, T0, hj, axh, bxh);
+      stage1(y0 + d, T1, hj, axh, bxh);
     }
   }
-  issue(y0 + 2, xc, xm, xp, P2);
-  if (hl) issue(y0 + 2, hc, hm, hp, H);
+  issue(y0 + 2 * d, hvc, hvm, hvp, H0);
+  __builtin_amdgcn_sched_barrier(0);
+  issue(y0 + 2 * d, vc, vm, vp, X0);
+  __builtin_amdgcn_sched_barrier(0);
   __syncthreads();
-  stage2(y0 - 1, j);
+  stage2(y0 - d, j);
   stage2(y0, j);
   if (t < 2) {
-    stage2(y0 - 1, j2);
+    stage2(y0 - d, j2);
     stage2(y0, j2);
   }
   __syncthreads();
 
+  // One marching row: issue row y+3d into slot N, stage 1 of row y+2d from slot C
+  // (pulled one row earlier), stage 2 of row y+d, stage 3 of row y.  On a block's last
+  // row the pull of y+3d is not needed; it is clamped to the last row the block does
+  // need (already in cache), so the pipeline has no branch and fetches nothing extra.
+  const int last_needed = y0 + (rows + 1) * d;
+  auto row = [&](int k, RowRec& C, RowRec& N) {
+    const int y = y0 + k * d;
+    const int ynext = k + 1 < rows ? y + 3 * d : last_needed;
+    // Halo first: its pull was issued before C's, so waiting for it leaves C in flight.
+    // The scheduling barriers keep the compiler from interleaving the two pulls, which
+    // would make each wait cover the other pull as well.
+    __builtin_amdgcn_sched_barrier(0);
+    stage1(y + 2 * d, H0, hj, axh, bxh, hl);
+    issue(ynext, hvc, hvm, hvp, H0);
+    __builtin_amdgcn_sched_barrier(0);
+    issue(ynext, vc, vm, vp, N);
+    __builtin_amdgcn_sched_barrier(0);
+    stage1(y + 2 * d, C, j, axc, bxc);
+    __syncthreads();
+    stage2(y + d, j);
+    if (t < 2) stage2(y + d, j2);
+    __syncthreads();
+    stage3(y, A);
+    A = B;
+    B = C;
+  };
+  int k = 0;
 #pragma unroll 1
-  for (int k = 0; k < rows; ++k) {
-    const int y = y0 + k;
-    // issue row y+3, then stage 1 of row y+2 (pulled one iteration ago)
-    P PN;
-    if (k + 1 < rows) issue(y + 3, xc, xm, xp, PN);
-    stage1(y + 2, P2, j, axc, bxc, phi2, l2, u2, v2);
-    if (hl) {
-      stage1(y + 2, H, hj, axh, bxh, dphi, dl, du, dv);
-      if (k + 1 < rows) issue(y + 3, hc, hm, hp, H);
-    }
-    __syncthreads();
-    // stage 2, row y+1
-    stage2(y + 1, j);
-    if (t < 2) stage2(y + 1, j2);
-    __syncthreads();
-    // stage 3, row y
-    if (active) {
-      const float* mm = s_mu[(y - 1) & 3];
-      const float* m0 = s_mu[y & 3];
-      const float* mp = s_mu[(y + 1) & 3];
-      const float mux = ddx(mm, m0, mp, j), muy = ddy(mm, m0, mp, j);
-      const float rho = c.a * phi0 + c.b;
-      float tx = -phi0 * mux, ty = -phi0 * muy;
-      if (NSC) {
-        const float* qm = s_p[(y - 1) & 7];
-        const float* q0 = s_p[y & 7];
-        const float* qp = s_p[(y + 1) & 7];
-        tx += rho * c.accel_x - ddx(qm, q0, qp, j);
-        ty += -(rho - c.rho_mean) * c.gravity - ddy(qm, q0, qp, j);
-      }
-      const float s1 = phi0 * rcp(rho);
-      float fx = s1 * tx, fy = s1 * ty;
-      if (MODEL2) {
-        const float* dm = s_d[(y - 1) & 3];
-        const float* d0 = s_d[y & 3];
-        const float* dp = s_d[(y + 1) & 3];
-        fx += c.k2 * ddx(dm, d0, dp, j);
-        fy += c.k2 * ddy(dm, d0, dp, j);
-      }
-      collide_g(c, phi0, l0, m0[j], u0, v0, fx, fy, P0.g);
-      const uint32_t off = ((uint32_t)y * nx + xc) * 4u;
-#pragma unroll
-      for (int i = 0; i < 9; ++i) stb(rdst, P0.g[i], off, i * pb);
-    }
-    // rotate the register pipeline
-    P0 = P1;
-    phi0 = phi1; l0 = l1; u0 = u1; v0 = v1;
-    P1 = P2;
-    phi1 = phi2; l1 = l2; u1 = u2; v1 = v2;
-    P2 = PN;
+  for (; k + 2 <= rows; k += 2) {
+    row(k, X0, X1);
+    row(k + 1, X1, X0);
   }
+  if (k < rows) row(k, X0, X1);
 }
 
 // ---------------------------------------------------------------------------------
@@ -426,10 +472,11 @@ __global__ void __launch_bounds__(TX) k_ns_step(const NsArgs a) {
   const int j = t + 2;
   const int j2 = t == 0 ? 1 : TX + 2;
 
+  const uint32_t rb = (uint32_t)nx * 4u;
   auto phi_at = [&](int r, int col, int cm, int cq) {
     float sg, g[9];
     const int sr = row_of<WALLS>(r, ny, sg);
-    pull9<WALLS>(rg, pb, nx, ny, sr, col, cm, cq, g);
+    pull9<WALLS>(rg, pb, rb, ny, sr, col * 4u, cm * 4u, cq * 4u, g);
     return sum9(g);
   };
   auto stage2 = [&](int r, int jj) {
@@ -452,14 +499,14 @@ __global__ void __launch_bounds__(TX) k_ns_step(const NsArgs a) {
     stage2(y0, j2);
   }
   float fpop[9];
-  pull9<WALLS>(rf, pb, nx, ny, y0, xc, xm, xp, fpop);
+  pull9<WALLS>(rf, pb, rb, ny, y0, xc * 4u, xm * 4u, xp * 4u, fpop);
   __syncthreads();
 
 #pragma unroll 1
   for (int k = 0; k < rows; ++k) {
     const int y = y0 + k;
     float fnext[9];
-    if (k + 1 < rows) pull9<WALLS>(rf, pb, nx, ny, y + 1, xc, xm, xp, fnext);
+    if (k + 1 < rows) pull9<WALLS>(rf, pb, rb, ny, y + 1, xc * 4u, xm * 4u, xp * 4u, fnext);
     s_phi[(y + 2) & 7][j] = phi_at(y + 2, xc, xm, xp);
     if (hl) s_phi[(y + 2) & 7][hj] = phi_at(y + 2, hc, hm, hp);
     __syncthreads();
@@ -493,10 +540,10 @@ __global__ void __launch_bounds__(TX) k_ns_step(const NsArgs a) {
       const float usq15 = 1.5f * (u * u + v * v);
       // p = cs^2/(1 - w0) [sum_{i>0} f_i + u.grad rho / 2 + rho w0 s_0(u)], cs^2/(1-w0) = 3/5
       const float pr = 0.6f * (s + 0.5f * (u * drx + v * dry) - WT[0] * rho * usq15);
-      const uint32_t off = ((uint32_t)y * nx + xc) * 4u;
-      stb(ru, u, off, 0);
-      stb(rv, v, off, 0);
-      stb(rpr, pr, off, 0);
+      const uint32_t off = xc * 4u, ro = (uint32_t)y * rb;
+      stb(ru, u, off, ro);
+      stb(rv, v, off, ro);
+      stb(rpr, pr, off, ro);
       if (a.fdst) {
         const float om = c.omega_f, om1 = 1.0f - om;
         const float p3 = 3.0f * pr;  // p / cs^2
@@ -509,7 +556,7 @@ __global__ void __launch_bounds__(TX) k_ns_step(const NsArgs a) {
           const float su = cu * (3.0f + 4.5f * cu) - usq15;
           const float feq = WT[i] * (p3 + rho * su) - (i == 0 ? p3 : 0.0f);
           const float G = WT[i] * (3.0f * (cF - uF) + 9.0f * cu * cF + 3.0f * cu * cr);
-          stb(rfd, om1 * fpop[i] + om * feq + c.srcf * G, off, i * pb);
+          stb(rfd, om1 * fpop[i] + om * feq + c.srcf * G, off, i * pb + ro);
         }
       }
     }
@@ -607,8 +654,8 @@ __global__ void __launch_bounds__(256) k_phi_field(const float* __restrict__ g, 
   const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
   if (x >= nx) return;
   float p[9];
-  pull9<WALLS>(make_rsrc(g, 9u * plane * 4u), plane * 4u, nx, ny, y, x, x == 0 ? nx - 1 : x - 1,
-               x == nx - 1 ? 0 : x + 1, p);
+  pull9<WALLS>(make_rsrc(g, 9u * plane * 4u), plane * 4u, (uint32_t)nx * 4u, ny, y, x * 4u,
+               (x == 0 ? nx - 1 : x - 1) * 4u, (x == nx - 1 ? 0 : x + 1) * 4u, p);
   phi[(uint32_t)y * nx + x] = sum9(p);
 }
 
@@ -763,6 +810,7 @@ hipError_t launch_phi_step(int tx, bool walls, int vmode, bool model2, const Ste
     case 64: return phi_step_w<64>(walls, vmode, model2, a, nblocks, s);
     case 128: return phi_step_w<128>(walls, vmode, model2, a, nblocks, s);
     case 256: return phi_step_w<256>(walls, vmode, model2, a, nblocks, s);
+    case 512: return phi_step_w<512>(walls, vmode, model2, a, nblocks, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -780,6 +828,10 @@ hipError_t launch_ns_step(int tx, bool walls, const NsArgs& a, int nblocks, hipS
     case 256:
       if (walls) hipLaunchKernelGGL((k_ns_step<256, true>), dim3(nblocks), dim3(256), 0, s, a);
       else hipLaunchKernelGGL((k_ns_step<256, false>), dim3(nblocks), dim3(256), 0, s, a);
+      break;
+    case 512:
+      if (walls) hipLaunchKernelGGL((k_ns_step<512, true>), dim3(nblocks), dim3(512), 0, s, a);
+      else hipLaunchKernelGGL((k_ns_step<512, false>), dim3(nblocks), dim3(512), 0, s, a);
       break;
     default: return hipErrorInvalidValue;
   }
