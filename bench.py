@@ -96,6 +96,38 @@ def accuracy(lbm, w, torch):
             "max_abs_err": float(np.abs(phi[idx] - ref).max()), "mass_drift": drift}
 
 
+def storage_variant(lbm, torch, storage, steps):
+    """Same workload with 16-bit population storage (20 B per node update instead of 36
+    read and 36 written): throughput and phi at the stored 1000-step oracle samples."""
+    import numpy as np
+    import workloads
+    w = workloads.metric2048(steps=steps + 1100)
+    s = lbm.solver_for(w, storage=storage)
+    s.step(50)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s.stream)
+    s.step(steps)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    s.close()
+    out = {"MLUPS": round(w.nx * w.ny / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 5),
+           "bytes_per_lu": 40, "effective_GBps": round(w.nx * w.ny * 40 / (ms * 1e-3) / 1e9, 1)}
+    if os.path.exists(GOLDEN):
+        g = np.load(GOLDEN)
+        s = lbm.solver_for(workloads.metric2048(steps=1000), storage=storage)
+        s.step(int(g["steps"]))
+        d = s.diagnostics()
+        phi = s.phi().double().cpu().numpy().ravel()
+        s.close()
+        ref = g["phi"]
+        out["rel_l2_phi_sampled_1000"] = float(np.sqrt(((phi[g["index"]] - ref) ** 2).sum()
+                                                       / (ref ** 2).sum()))
+        out["mass_drift_1000"] = abs(d["mass"] - float(g["mass0"])) / float(g["abs_mass0"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,6 +232,8 @@ def main():
     }
     if not args.no_accuracy:
         out["accuracy"] = accuracy(lbm, workloads.metric2048(steps=1000), torch)
+        out["storage_variants"] = {name: storage_variant(lbm, torch, st, args.steps)
+                                   for name, st in (("f16", 1), ("bf16", 2))}
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(workloads.metric2048(steps=args.cpu_steps),
                                            args.cpu_steps)

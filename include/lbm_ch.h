@@ -85,15 +85,21 @@ enum {
 };
 
 enum {
-  LBM_CH_STORE_F32 = 0      /* populations stored as float32                         */
+  LBM_CH_STORE_F32 = 0,     /* g stored as nine float32 planes (36 B per node)       */
+  LBM_CH_STORE_F16 = 1,     /* g_0 float32; g_1..g_8 as IEEE half codes of g_i / w_i */
+  LBM_CH_STORE_BF16 = 2     /* g_0 float32; g_1..g_8 as bfloat16 codes of g_i / w_i  */
 };
+/* In the 16-bit modes (20 B per node) all arithmetic stays float32; only the stored
+ * moving populations are rounded.  g_0 is written as phi minus the decoded others, so
+ * phi mass is conserved to float32 rounding whatever the 16-bit rounding.  The f
+ * populations of the Navier-Stokes coupling are always float32. */
 
 typedef struct {
   int32_t nx, ny;         /* lattice nodes; 4 <= nx, ny and 9*nx*ny < 2^31          */
   int32_t walls;          /* 0: periodic in y; 1: no-slip walls (see above)         */
   int32_t model;          /* 1: F = F1 (Model-I); 2: F = F1 + F2 (Model-II), Eq. reFi */
   int32_t velocity_mode;  /* LBM_CH_VEL_*                                           */
-  int32_t storage;        /* LBM_CH_STORE_*                                         */
+  int32_t storage;        /* LBM_CH_STORE_* (population storage of g)                */
   double tau_g;           /* relaxation time of g, > 1/2 (Eq. LB)                   */
   double mobility;        /* M = cs^2 eta (tau_g - 1/2)                             */
   double sigma, width;    /* surface tension and interface width W (Eq. betakappa)  */
@@ -127,7 +133,7 @@ size_t lbm_ch_workspace_bytes(const lbm_ch_params* p);
  * context.  Errors: LBM_CH_EINVAL for tau_g <= 1/2, tau_f <= 1/2 (NS), sizes out of
  * range, phi_a == phi_b, rho_a or rho_b <= 0, model not 1 or 2, a NULL or unaligned
  * (4-byte) array the mode needs, a workspace smaller than lbm_ch_workspace_bytes or
- * not 256-byte aligned; LBM_CH_EUNSUPPORTED for a storage mode not built. */
+ * not 256-byte aligned, or a storage mode outside LBM_CH_STORE_*. */
 int lbm_ch_init(lbm_ch_ctx** out, const lbm_ch_params* p, const lbm_ch_velocity* vel,
                 void* workspace, size_t workspace_bytes, const float* phi0,
                 hipStream_t stream);
@@ -157,7 +163,8 @@ int lbm_ch_check_finite(lbm_ch_ctx* ctx, hipStream_t stream);
 /* Current step counter n. */
 int64_t lbm_ch_step_count(const lbm_ch_ctx* ctx);
 
-/* Bytes of the solver state (populations g, and f with NS). */
+/* Bytes of the solver state: the g populations in their storage layout (followed
+ * by the float32 f populations with NS). */
 size_t lbm_ch_state_bytes(const lbm_ch_ctx* ctx);
 
 /* Enqueue a device-to-device copy of the state into dst (checkpoint), or from src

@@ -22,7 +22,7 @@ LIB_PATH = os.environ.get("LBM_CH_LIB") or os.path.join(HERE, "liblbm_ch.so")
 # Status codes and modes (include/lbm_ch.h).
 OK, EINVAL, EUNSUPPORTED, EHIP, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5
 VEL_NONE, VEL_SEPARABLE, VEL_FIELD, VEL_NS = 0, 1, 2, 3
-STORE_F32 = 0
+STORE_F32, STORE_F16, STORE_BF16 = 0, 1, 2
 
 # Every symbol include/lbm_ch.h declares.
 EXPORTS = ("lbm_ch_workspace_bytes", "lbm_ch_init", "lbm_ch_step", "lbm_ch_moments",

@@ -28,8 +28,10 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  uint32_t plane;  // floats between population planes
-  size_t g_bytes;  // one population buffer (9 planes)
+  uint32_t plane;  // nodes per population plane
+  size_t g_state;  // bytes of the g populations (storage mode), f is 9 float planes
+  size_t g_bytes;  // one g population buffer, 256-byte aligned
+  size_t f_bytes;  // one f population buffer, 256-byte aligned
   size_t off_ga, off_gb, off_fa, off_fb, off_u, off_v, off_p, off_phi, off_ztab, off_part,
       off_diag, total;
 };
@@ -41,6 +43,7 @@ bool valid_params(const lbm_ch_params* p) {
   if (p->walls != 0 && p->walls != 1) return false;
   if (p->model != 1 && p->model != 2) return false;
   if (p->velocity_mode < LBM_CH_VEL_NONE || p->velocity_mode > LBM_CH_VEL_NS) return false;
+  if (p->storage < LBM_CH_STORE_F32 || p->storage > LBM_CH_STORE_BF16) return false;
   if (!(p->tau_g > 0.5) || !isfinite(p->tau_g)) return false;
   if (!(p->phi_a != p->phi_b)) return false;
   if (!(p->rho_a > 0.0) || !(p->rho_b > 0.0)) return false;
@@ -57,14 +60,16 @@ Layout layout_of(const lbm_ch_params* p) {
   Layout L{};
   const size_t nodes = (size_t)p->nx * p->ny;
   L.plane = (uint32_t)((nodes + 63) / 64 * 64);
-  L.g_bytes = align_up((size_t)9 * L.plane * sizeof(float));
+  L.g_state = population_bytes(p->storage, L.plane);
+  L.g_bytes = align_up(L.g_state);
+  L.f_bytes = align_up((size_t)9 * L.plane * sizeof(float));
   const bool ns = p->velocity_mode == LBM_CH_VEL_NS;
   const size_t field = align_up(nodes * sizeof(float));
   size_t o = 0;
   L.off_ga = o; o += L.g_bytes;
   L.off_gb = o; o += L.g_bytes;
-  L.off_fa = o; if (ns) o += L.g_bytes;
-  L.off_fb = o; if (ns) o += L.g_bytes;
+  L.off_fa = o; if (ns) o += L.f_bytes;
+  L.off_fb = o; if (ns) o += L.f_bytes;
   L.off_u = o; o += field;
   L.off_v = o; o += field;
   L.off_p = o; o += field;
@@ -85,7 +90,8 @@ struct lbm_ch_ctx {
   Coef c;
   Layout L;
   char* ws;
-  float *g[2], *f[2], *u, *v, *pr, *phi, *ztab;
+  void* g[2];
+  float *f[2], *u, *v, *pr, *phi, *ztab;
   double *part, *diag;
   int cur;  // index of the buffer holding the current state
   int64_t step;
@@ -110,13 +116,12 @@ static float time_factor(const lbm_ch_ctx* c, int64_t n) {
 // defaults aim at several blocks per CU on 256 CUs; LBM_CH_TILE=TXxTY overrides.
 static void choose_tiles(lbm_ch_ctx* c) {
   const int nx = c->p.nx, ny = c->p.ny;
-  int tx = nx >= 256 ? 256 : (nx >= 128 ? 128 : 64);
+  int tx = nx >= 256 ? 256 : 128;
   int ty = 16;
   const char* env = getenv("LBM_CH_TILE");
   if (env) {
     int a = 0, b = 0;
-    if (sscanf(env, "%dx%d", &a, &b) == 2 && (a == 64 || a == 128 || a == 256 || a == 512) &&
-        b >= 1) {
+    if (sscanf(env, "%dx%d", &a, &b) == 2 && (a == 128 || a == 256 || a == 512) && b >= 1) {
       tx = a;
       ty = b;
     }
@@ -143,7 +148,6 @@ int lbm_ch_init(lbm_ch_ctx** out, const lbm_ch_params* p, const lbm_ch_velocity*
   if (!out) return LBM_CH_EINVAL;
   *out = nullptr;
   if (!valid_params(p)) return LBM_CH_EINVAL;
-  if (p->storage != LBM_CH_STORE_F32) return LBM_CH_EUNSUPPORTED;
   const Layout L = layout_of(p);
   if (!workspace || ((uintptr_t)workspace % ALIGN) != 0 || workspace_bytes < L.total)
     return LBM_CH_EINVAL;
@@ -167,8 +171,8 @@ int lbm_ch_init(lbm_ch_ctx** out, const lbm_ch_params* p, const lbm_ch_velocity*
   c->p = *p;
   c->L = L;
   c->ws = (char*)workspace;
-  c->g[0] = (float*)(c->ws + L.off_ga);
-  c->g[1] = (float*)(c->ws + L.off_gb);
+  c->g[0] = c->ws + L.off_ga;
+  c->g[1] = c->ws + L.off_gb;
   const bool ns = vm == LBM_CH_VEL_NS;
   c->f[0] = ns ? (float*)(c->ws + L.off_fa) : nullptr;
   c->f[1] = ns ? (float*)(c->ws + L.off_fb) : nullptr;
@@ -237,8 +241,9 @@ int lbm_ch_init(lbm_ch_ctx** out, const lbm_ch_params* p, const lbm_ch_velocity*
 
   hipError_t e = launch_fill(z, 0.0f, 2 * (int64_t)(p->nx + p->ny), stream);
   if (e == hipSuccess)
-    e = launch_init(p->walls != 0, c->vmode, c->c, p->nx, p->ny, L.plane, phi0, c->ax, c->ay,
-                    c->bx, c->by, c->ux, c->uy, time_factor(c, 0), c->g[0], c->f[0], stream);
+    e = launch_init(p->walls != 0, c->vmode, p->storage, c->c, p->nx, p->ny, L.plane, phi0,
+                    c->ax, c->ay, c->bx, c->by, c->ux, c->uy, time_factor(c, 0), c->g[0],
+                    c->f[0], stream);
   if (e != hipSuccess) {
     c->magic = 0;
     delete c;
@@ -287,7 +292,7 @@ int lbm_ch_step(lbm_ch_ctx* c, int64_t nsteps, hipStream_t stream) {
       n.gsrc = c->g[src];
       n.fsrc = c->f[src];
       n.fdst = c->f[dst];
-      e = launch_ns_step(c->tx, walls, n, c->nblocks, stream);
+      e = launch_ns_step(c->tx, walls, c->p.storage, n, c->nblocks, stream);
       if (e != hipSuccess) return hip_fail(e);
       a.tf = 1.0f;
     } else {
@@ -295,7 +300,8 @@ int lbm_ch_step(lbm_ch_ctx* c, int64_t nsteps, hipStream_t stream) {
     }
     a.src = c->g[src];
     a.dst = c->g[dst];
-    e = launch_phi_step(c->tx, walls, vmode, c->p.model == 2, a, c->nblocks, stream);
+    e = launch_phi_step(c->tx, walls, vmode, c->p.model == 2, c->p.storage, a, c->nblocks,
+                        stream);
     if (e != hipSuccess) return hip_fail(e);
     c->cur = dst;
     c->step += 1;
@@ -315,7 +321,8 @@ int lbm_ch_moments(lbm_ch_ctx* c, float* phi, float* mu, float* ux, float* uy, f
   const bool ns = c->p.velocity_mode == LBM_CH_VEL_NS;
   float* ph = phi ? phi : c->phi;
   hipError_t e = hipSuccess;
-  if (phi || mu || ns) e = launch_phi_field(walls, c->g[c->cur], c->L.plane, nx, ny, ph, stream);
+  if (phi || mu || ns)
+    e = launch_phi_field(walls, c->p.storage, c->g[c->cur], c->L.plane, nx, ny, ph, stream);
   if (e == hipSuccess && mu) e = launch_mu_field(walls, c->c, ph, nx, ny, mu, stream);
   if (e != hipSuccess) return hip_fail(e);
   if (ns) {
@@ -329,7 +336,7 @@ int lbm_ch_moments(lbm_ch_ctx* c, float* phi, float* mu, float* ux, float* uy, f
       n.nx = nx; n.ny = ny;
       n.ty = c->ty; n.nstrips = c->nstrips; n.xcd_remap = c->xcd_remap;
       n.c = c->c;
-      e = launch_ns_step(c->tx, walls, n, c->nblocks, stream);
+      e = launch_ns_step(c->tx, walls, c->p.storage, n, c->nblocks, stream);
       if (e == hipSuccess && ux) e = hipMemcpyAsync(ux, c->u, fb, hipMemcpyDeviceToDevice, stream);
       if (e == hipSuccess && uy) e = hipMemcpyAsync(uy, c->v, fb, hipMemcpyDeviceToDevice, stream);
       if (e == hipSuccess && p) e = hipMemcpyAsync(p, c->pr, fb, hipMemcpyDeviceToDevice, stream);
@@ -348,7 +355,8 @@ int lbm_ch_diagnostics(lbm_ch_ctx* c, const float* phi_ref, double* out, hipStre
   if (!out || ((uintptr_t)out & 7u) != 0) return LBM_CH_EINVAL;
   if (phi_ref && !aligned4(phi_ref)) return LBM_CH_EINVAL;
   const bool walls = c->p.walls != 0;
-  hipError_t e = launch_phi_field(walls, c->g[c->cur], c->L.plane, c->p.nx, c->p.ny, c->phi, stream);
+  hipError_t e = launch_phi_field(walls, c->p.storage, c->g[c->cur], c->L.plane, c->p.nx,
+                                  c->p.ny, c->phi, stream);
   if (e == hipSuccess)
     e = launch_diag(walls, c->c, c->phi, phi_ref, c->p.nx, c->p.ny, c->part, out, stream);
   return e == hipSuccess ? LBM_CH_OK : hip_fail(e);
@@ -369,17 +377,17 @@ int64_t lbm_ch_step_count(const lbm_ch_ctx* c) { return live(c) ? c->step : -1; 
 
 size_t lbm_ch_state_bytes(const lbm_ch_ctx* c) {
   if (!live(c)) return 0;
-  const size_t g = (size_t)9 * c->L.plane * sizeof(float);
-  return c->p.velocity_mode == LBM_CH_VEL_NS ? 2 * g : g;
+  const size_t f = (size_t)9 * c->L.plane * sizeof(float);
+  return c->L.g_state + (c->p.velocity_mode == LBM_CH_VEL_NS ? f : 0);
 }
 
 int lbm_ch_save_state(lbm_ch_ctx* c, void* dst, size_t bytes, hipStream_t stream) {
   if (!live(c)) return LBM_CH_ESTATE;
   if (!dst || bytes != lbm_ch_state_bytes(c)) return LBM_CH_EINVAL;
-  const size_t g = (size_t)9 * c->L.plane * sizeof(float);
+  const size_t g = c->L.g_state, f = (size_t)9 * c->L.plane * sizeof(float);
   hipError_t e = hipMemcpyAsync(dst, c->g[c->cur], g, hipMemcpyDeviceToDevice, stream);
   if (e == hipSuccess && c->f[0])
-    e = hipMemcpyAsync((char*)dst + g, c->f[c->cur], g, hipMemcpyDeviceToDevice, stream);
+    e = hipMemcpyAsync((char*)dst + g, c->f[c->cur], f, hipMemcpyDeviceToDevice, stream);
   return e == hipSuccess ? LBM_CH_OK : hip_fail(e);
 }
 
@@ -387,10 +395,10 @@ int lbm_ch_load_state(lbm_ch_ctx* c, const void* src, size_t bytes, int64_t step
                       hipStream_t stream) {
   if (!live(c)) return LBM_CH_ESTATE;
   if (!src || bytes != lbm_ch_state_bytes(c) || step < 0) return LBM_CH_EINVAL;
-  const size_t g = (size_t)9 * c->L.plane * sizeof(float);
+  const size_t g = c->L.g_state, f = (size_t)9 * c->L.plane * sizeof(float);
   hipError_t e = hipMemcpyAsync(c->g[c->cur], src, g, hipMemcpyDeviceToDevice, stream);
   if (e == hipSuccess && c->f[0])
-    e = hipMemcpyAsync(c->f[c->cur], (const char*)src + g, g, hipMemcpyDeviceToDevice, stream);
+    e = hipMemcpyAsync(c->f[c->cur], (const char*)src + g, f, hipMemcpyDeviceToDevice, stream);
   if (e != hipSuccess) return hip_fail(e);
   c->step = step;
   return LBM_CH_OK;

@@ -26,8 +26,8 @@ struct Coef {
 
 // Arguments of the fused phase-field step.
 struct StepArgs {
-  const float* src;   // populations at t_n: 9 planes of `plane` floats
-  float* dst;         // populations at t_{n+1}
+  const void* src;    // populations at t_n (layout of the storage mode)
+  void* dst;          // populations at t_{n+1}
   uint32_t plane;     // floats between planes (>= nx*ny)
   int nx, ny;
   int ty;             // rows per block
@@ -43,7 +43,7 @@ struct StepArgs {
 
 // Arguments of the coupled Navier-Stokes step.
 struct NsArgs {
-  const float* gsrc;  // phase-field populations at t_n
+  const void* gsrc;   // phase-field populations at t_n (storage mode of g)
   const float* fsrc;  // NS populations at t_n
   float* fdst;        // NS populations at t_{n+1} (may be null: moments only)
   float *u, *v, *p;   // velocity and pressure at t_n (written)
@@ -55,17 +55,22 @@ struct NsArgs {
 
 enum VelMode { VEL_SEP = 0, VEL_FIELD = 1, VEL_NSFIELD = 2 };
 
-// Launchers (return hipGetLastError() of the launch).
-hipError_t launch_phi_step(int tx, bool walls, int vmode, bool model2, const StepArgs& a,
-                           int nblocks, hipStream_t s);
-hipError_t launch_ns_step(int tx, bool walls, const NsArgs& a, int nblocks, hipStream_t s);
+// Population storage (LBM_CH_STORE_*): 0 float32; 1 half, 2 bfloat16 (g_0 float32, g_1..8
+// as 16-bit codes of g_i / w_i).  Bytes of one population buffer of `plane` nodes/plane.
+uint32_t population_bytes(int storage, uint32_t plane);
 
-hipError_t launch_init(bool walls, int vmode, const Coef& c, int nx, int ny, uint32_t plane,
-                       const float* phi0, const float* ax, const float* ay, const float* bx,
-                       const float* by, const float* ux, const float* uy, float tf, float* g,
-                       float* f, hipStream_t s);
-hipError_t launch_phi_field(bool walls, const float* g, uint32_t plane, int nx, int ny,
-                            float* phi, hipStream_t s);
+// Launchers (return hipGetLastError() of the launch).
+hipError_t launch_phi_step(int tx, bool walls, int vmode, bool model2, int storage,
+                           const StepArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_ns_step(int tx, bool walls, int storage, const NsArgs& a, int nblocks,
+                          hipStream_t s);
+
+hipError_t launch_init(bool walls, int vmode, int storage, const Coef& c, int nx, int ny,
+                       uint32_t plane, const float* phi0, const float* ax, const float* ay,
+                       const float* bx, const float* by, const float* ux, const float* uy,
+                       float tf, void* g, float* f, hipStream_t s);
+hipError_t launch_phi_field(bool walls, int storage, const void* g, uint32_t plane, int nx,
+                            int ny, float* phi, hipStream_t s);
 hipError_t launch_mu_field(bool walls, const Coef& c, const float* phi, int nx, int ny,
                            float* mu, hipStream_t s);
 hipError_t launch_velocity_field(int vmode, int nx, int ny, const float* ax, const float* ay,

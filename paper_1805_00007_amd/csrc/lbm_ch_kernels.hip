@@ -63,38 +63,71 @@ __device__ __forceinline__ void stb(rsrc_t r, float v, uint32_t voff, uint32_t s
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
 }
 
+// Population storage.  ST_F32: nine float32 planes.  ST_F16 / ST_BF16: the rest
+// population g_0 as a float32 plane, then eight 16-bit planes holding g_i / w_i
+// (i = 1..8) in IEEE half or bfloat16.  The moving populations of Eq. geq are
+// w_i (eta mu + phi s_i(u)), of order w_i |u|, so their scaled values are small and a
+// 16-bit code keeps them to ~1e-4 of that size; g_0 ~ phi stays in float32 and, through
+// the mass closure below, absorbs the rounding of the others.
+enum Storage { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
+constexpr float INV_W[9] = {9.0f / 4, 9.0f, 9.0f, 9.0f, 9.0f, 36.0f, 36.0f, 36.0f, 36.0f};
+
+__host__ __device__ constexpr uint32_t pop_bytes(int st, uint32_t plane) {
+  return st == ST_F32 ? 36u * plane : 20u * plane;
+}
+template <int ST>
+__device__ __forceinline__ float dec16(uint32_t h) {
+  if (ST == ST_F16) return (float)__builtin_bit_cast(_Float16, (unsigned short)h);
+  return __builtin_bit_cast(float, h << 16);
+}
+template <int ST>
+__device__ __forceinline__ uint32_t enc16(float f) {
+  if (ST == ST_F16) return __builtin_bit_cast(unsigned short, (_Float16)f);
+  const uint32_t u = __builtin_bit_cast(uint32_t, f);  // round to nearest even
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+// Population i at (column col, row) of a buffer in storage ST.
+template <int ST>
+__device__ __forceinline__ float ldpop(rsrc_t s, int i, uint32_t plane, uint32_t nx,
+                                       uint32_t col, uint32_t row) {
+  if (ST == ST_F32 || i == 0) return ldb(s, col * 4u, ((uint32_t)i * plane + row * nx) * 4u);
+  const uint32_t h = __builtin_amdgcn_raw_buffer_load_b16(
+      s, col * 2u, plane * 4u + ((uint32_t)(i - 1) * plane + row * nx) * 2u, 0);
+  return WT[i] * dec16<ST>(h);
+}
+
 // Pull of the nine populations arriving at (x, y): g_i(x, y) = g_i*(x - c_i, y - c_i).
 // With walls, a population whose source lies beyond a wall is the opposite one that
-// left (x, y) (half-way bounce-back).  y is a lattice row (block-uniform); vc, vm, vp
-// are the byte offsets of columns x, x-1, x+1 (wrapped) within a row; rb is the row
-// pitch and pb the plane stride in bytes.  Plane and row offsets travel in the
-// instruction's scalar offset, so a load costs no vector ALU work.
-template <bool WALLS>
-__device__ __forceinline__ void pull9(rsrc_t s, uint32_t pb, uint32_t rb, int ny, int y,
-                                      uint32_t vc, uint32_t vm, uint32_t vp, float g[9]) {
-  const int ym = y == 0 ? ny - 1 : y - 1;
-  const int yp = y == ny - 1 ? 0 : y + 1;
-  const uint32_t rc = (uint32_t)y * rb, rm = (uint32_t)ym * rb, rp = (uint32_t)yp * rb;
-  g[0] = ldb(s, vc, rc);
-  g[1] = ldb(s, vm, pb + rc);
-  g[3] = ldb(s, vp, 3 * pb + rc);
+// left (x, y) (half-way bounce-back).  y is a lattice row (block-uniform); cc, cm, cp
+// are the columns x, x-1, x+1 (wrapped).  Plane and row offsets travel in the
+// instruction's scalar offset, so a load costs no vector ALU work beyond its column.
+template <bool WALLS, int ST>
+__device__ __forceinline__ void pull9(rsrc_t s, uint32_t plane, uint32_t nx, int ny, int y,
+                                      uint32_t cc, uint32_t cm, uint32_t cp, float g[9]) {
+  const uint32_t ym = y == 0 ? ny - 1 : y - 1;
+  const uint32_t yp = y == ny - 1 ? 0 : y + 1;
+  const uint32_t yc = y;
+  g[0] = ldpop<ST>(s, 0, plane, nx, cc, yc);
+  g[1] = ldpop<ST>(s, 1, plane, nx, cm, yc);
+  g[3] = ldpop<ST>(s, 3, plane, nx, cp, yc);
   if (WALLS && y == 0) {
-    g[2] = ldb(s, vc, 4 * pb + rc);
-    g[5] = ldb(s, vc, 7 * pb + rc);
-    g[6] = ldb(s, vc, 8 * pb + rc);
+    g[2] = ldpop<ST>(s, 4, plane, nx, cc, yc);
+    g[5] = ldpop<ST>(s, 7, plane, nx, cc, yc);
+    g[6] = ldpop<ST>(s, 8, plane, nx, cc, yc);
   } else {
-    g[2] = ldb(s, vc, 2 * pb + rm);
-    g[5] = ldb(s, vm, 5 * pb + rm);
-    g[6] = ldb(s, vp, 6 * pb + rm);
+    g[2] = ldpop<ST>(s, 2, plane, nx, cc, ym);
+    g[5] = ldpop<ST>(s, 5, plane, nx, cm, ym);
+    g[6] = ldpop<ST>(s, 6, plane, nx, cp, ym);
   }
   if (WALLS && y == ny - 1) {
-    g[4] = ldb(s, vc, 2 * pb + rc);
-    g[7] = ldb(s, vc, 5 * pb + rc);
-    g[8] = ldb(s, vc, 6 * pb + rc);
+    g[4] = ldpop<ST>(s, 2, plane, nx, cc, yc);
+    g[7] = ldpop<ST>(s, 5, plane, nx, cc, yc);
+    g[8] = ldpop<ST>(s, 6, plane, nx, cc, yc);
   } else {
-    g[4] = ldb(s, vc, 4 * pb + rp);
-    g[7] = ldb(s, vp, 7 * pb + rp);
-    g[8] = ldb(s, vm, 8 * pb + rp);
+    g[4] = ldpop<ST>(s, 4, plane, nx, cc, yp);
+    g[7] = ldpop<ST>(s, 7, plane, nx, cp, yp);
+    g[8] = ldpop<ST>(s, 8, plane, nx, cm, yp);
   }
 }
 
@@ -119,6 +152,33 @@ __device__ __forceinline__ void close_mass(double m, float g[9]) {
   g[0] = (float)e0;
   g[8] = (float)((double)g[8] + (e0 - (double)g[0]));
 }
+// Writes the nine post-collision populations of node (col, row) in storage ST such that
+// the exact sum of the stored values is m (float32: up to the rounding of g_8; 16-bit:
+// up to the float32 rounding of g_0, which takes m minus the decoded others).  Returns
+// the stored values in g.
+template <int ST>
+__device__ __forceinline__ void finish_store(rsrc_t d, uint32_t plane, uint32_t nx,
+                                             uint32_t col, uint32_t row, double m, float g[9]) {
+  if (ST == ST_F32) {
+    close_mass(m, g);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) stb(d, g[i], col * 4u, ((uint32_t)i * plane + row * nx) * 4u);
+    return;
+  }
+  uint32_t h[9];
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    h[i] = enc16<ST>(g[i] * INV_W[i]);
+    g[i] = WT[i] * dec16<ST>(h[i]);
+  }
+  g[0] = (float)(m - sum8_hi(g));
+  stb(d, g[0], col * 4u, row * nx * 4u);
+#pragma unroll
+  for (int i = 1; i < 9; ++i)
+    __builtin_amdgcn_raw_buffer_store_b16((unsigned short)h[i], d, col * 2u,
+                                          plane * 4u + ((uint32_t)(i - 1) * plane + row * nx) * 2u, 0);
+}
+
 __device__ __forceinline__ float sum9(const float g[9], float& lo) {
   const double s = sum8_hi(g) + (double)g[0];
   const float f = (float)s;
@@ -168,8 +228,9 @@ __device__ __forceinline__ void collide_g(const Coef& c, float phi, float phi_lo
     const float eq = A + phi * cu * (3.0f + 4.5f * cu);
     g[i] = om1 * g[i] + WT[i] * (c.omega * eq + c.srcg * cf);
   }
-  // g_0* = (1 - omega) g_0 + omega g_0^eq, written through mass conservation
-  close_mass((double)phi + (double)phi_lo, g);
+  // g_0* = (1 - omega) g_0 + omega g_0^eq is written by finish_store through mass
+  // conservation: sum_i g_i* = phi + phi_lo.
+  (void)phi_lo;
 }
 
 // ---------------------------------------------------------------------------------
@@ -188,7 +249,7 @@ struct RowRec {
 #ifndef WPE_PHI
 #define WPE_PHI 4
 #endif
-template <int TX, bool WALLS, int VMODE, bool MODEL2>
+template <int TX, bool WALLS, int VMODE, bool MODEL2, int ST>
 __global__ void __launch_bounds__(TX) __attribute__((amdgpu_waves_per_eu(WPE_PHI, 8)))
 k_phi_step(const StepArgs a) {
   constexpr bool NSC = VMODE == VEL_NSFIELD;
@@ -206,10 +267,10 @@ k_phi_step(const StepArgs a) {
   const Coef& c = a.c;
   const int nx = a.nx, ny = a.ny;
   const uint32_t nodes = (uint32_t)nx * ny;
-  const uint32_t pb = a.plane * 4u;
+  const uint32_t plane = a.plane;
   const uint32_t rb = (uint32_t)nx * 4u;
-  const rsrc_t rsrc = make_rsrc(a.src, 9u * pb);
-  const rsrc_t rdst = make_rsrc(a.dst, 9u * pb);
+  const rsrc_t rsrc = make_rsrc(a.src, pop_bytes(ST, plane));
+  const rsrc_t rdst = make_rsrc(a.dst, pop_bytes(ST, plane));
   rsrc_t ru, rv, rp;
   if (VFIELD) {
     ru = make_rsrc(a.ux, nodes * 4u);
@@ -232,13 +293,13 @@ k_phi_step(const StepArgs a) {
   const int dir = (chunk & 1) ? -1 : 1;
   const int y0 = dir > 0 ? chunk * a.ty : chunk * a.ty + rows - 1;  // first row marched
 
-  // Own column (wrapped) and its neighbours, as byte offsets within a row.
+  // Own column (wrapped) and its neighbours.
   const int xl = x0 + t;
   const bool active = xl < nx;
   const int xc = xl % nx;
-  const uint32_t vc = xc * 4u;
-  const uint32_t vm = (xc == 0 ? nx - 1 : xc - 1) * 4u;
-  const uint32_t vp = (xc == nx - 1 ? 0 : xc + 1) * 4u;
+  const uint32_t vc = xc;
+  const uint32_t vm = xc == 0 ? nx - 1 : xc - 1;
+  const uint32_t vp = xc == nx - 1 ? 0 : xc + 1;
   // Halo lanes t < 4: logical columns x0-2, x0-1, x0+TX, x0+TX+1 -> LDS 0, 1, TX+2, TX+3.
   const bool hl = t < 4;
   const int hlog = t < 2 ? x0 - 2 + t : x0 + TX - 2 + t;
@@ -246,10 +307,10 @@ k_phi_step(const StepArgs a) {
   // Every lane issues the halo pull, so that the wait-count bookkeeping does not depend
   // on a branch; lanes other than the four halo lanes use an offset beyond the buffer,
   // for which a raw buffer load returns 0 without accessing memory.
-  constexpr uint32_t OOB = 0xFFFFFF00u;
-  const uint32_t hvc = hl ? hc * 4u : OOB;
-  const uint32_t hvm = hl ? (hc == 0 ? nx - 1 : hc - 1) * 4u : OOB;
-  const uint32_t hvp = hl ? (hc == nx - 1 ? 0 : hc + 1) * 4u : OOB;
+  constexpr uint32_t OOB = 0x3FFFFFC0u;  // column index whose byte offset exceeds any buffer
+  const uint32_t hvc = hl ? hc : OOB;
+  const uint32_t hvm = hl ? (hc == 0 ? nx - 1 : hc - 1) : OOB;
+  const uint32_t hvp = hl ? (hc == nx - 1 ? 0 : hc + 1) : OOB;
   const int hj = t < 2 ? t : TX + t;
   const int j = t + 2;
   const int j2 = t == 0 ? 1 : TX + 2;  // stage-2 halo column of lanes 0 and 1
@@ -269,7 +330,7 @@ k_phi_step(const StepArgs a) {
   auto issue = [&](int r, uint32_t cc, uint32_t cm, uint32_t cp, RowRec& R) {
     float sg;
     const int sr = row_of<WALLS>(r, ny, sg);
-    pull9<WALLS>(rsrc, pb, rb, ny, sr, cc, cm, cp, R.g);
+    pull9<WALLS, ST>(rsrc, plane, nx, ny, sr, cc, cm, cp, R.g);
     if (VMODE == VEL_SEP) {
       // row factors of the separable velocity, fetched with the pull so that one wait
       // covers both (a later load would make the wait cover the whole prefetch)
@@ -277,15 +338,15 @@ k_phi_step(const StepArgs a) {
       R.fy_v = a.by[sr];
     }
     if (VFIELD) {
-      R.lu = ldb(ru, cc, (uint32_t)sr * rb);
-      R.lv = ldb(rv, cc, (uint32_t)sr * rb);
-      if (NSC) R.lp = ldb(rp, cc, (uint32_t)sr * rb);
+      R.lu = ldb(ru, cc * 4u, (uint32_t)sr * rb);
+      R.lv = ldb(rv, cc * 4u, (uint32_t)sr * rb);
+      if (NSC) R.lp = ldb(rp, cc * 4u, (uint32_t)sr * rb);
     }
   };
   // Stage 1 for logical row r: phi (and q = phi u, p) into the rings at column jj.
   auto stage1 = [&](int r, RowRec& R, int jj, float axv, float bxv, bool wr = true) {
     float sg;
-    const int sr = row_of<WALLS>(r, ny, sg);
+    row_of<WALLS>(r, ny, sg);
     R.phi = sum9(R.g, R.lo);
     float u, v;
     if (VMODE == VEL_SEP) {
@@ -344,9 +405,7 @@ k_phi_step(const StepArgs a) {
     const float u = VMODE == VEL_SEP ? axc * R.fy_u : R.u;
     const float v = VMODE == VEL_SEP ? bxc * R.fy_v : R.v;
     collide_g(c, R.phi, R.lo, m0[j], u, v, fx, fy, R.g);
-    const uint32_t ro = (uint32_t)y * rb;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) stb(rdst, R.g[i], vc, i * pb + ro);
+    finish_store<ST>(rdst, plane, nx, vc, (uint32_t)y, (double)R.phi + (double)R.lo, R.g);
   };
 
   // Prologue: rows y0-2d .. y0+d through stage 1, rows y0-d and y0 through stage 2,
@@ -434,7 +493,7 @@ k_phi_step(const StepArgs a) {
 // Same marching layout: stage 1 pulls g for phi, stage 2 computes mu, stage 3 pulls
 // f, forms the force, velocity and pressure, writes u, v, p and (if fdst) collides
 // and stores f.
-template <int TX, bool WALLS>
+template <int TX, bool WALLS, int ST>
 __global__ void __launch_bounds__(TX) k_ns_step(const NsArgs a) {
   constexpr int LW = TX + 4;
   __shared__ float s_phi[8][LW];
@@ -443,7 +502,7 @@ __global__ void __launch_bounds__(TX) k_ns_step(const NsArgs a) {
   const int nx = a.nx, ny = a.ny;
   const uint32_t nodes = (uint32_t)nx * ny;
   const uint32_t pb = a.plane * 4u;
-  const rsrc_t rg = make_rsrc(a.gsrc, 9u * pb);
+  const rsrc_t rg = make_rsrc(a.gsrc, pop_bytes(ST, a.plane));
   const rsrc_t rf = make_rsrc(a.fsrc, 9u * pb);
   const rsrc_t rfd = make_rsrc(a.fdst, a.fdst ? 9u * pb : 0u);
   const rsrc_t ru = make_rsrc(a.u, nodes * 4u);
@@ -476,7 +535,7 @@ __global__ void __launch_bounds__(TX) k_ns_step(const NsArgs a) {
   auto phi_at = [&](int r, int col, int cm, int cq) {
     float sg, g[9];
     const int sr = row_of<WALLS>(r, ny, sg);
-    pull9<WALLS>(rg, pb, rb, ny, sr, col * 4u, cm * 4u, cq * 4u, g);
+    pull9<WALLS, ST>(rg, a.plane, nx, ny, sr, col, cm, cq, g);
     return sum9(g);
   };
   auto stage2 = [&](int r, int jj) {
@@ -499,14 +558,14 @@ __global__ void __launch_bounds__(TX) k_ns_step(const NsArgs a) {
     stage2(y0, j2);
   }
   float fpop[9];
-  pull9<WALLS>(rf, pb, rb, ny, y0, xc * 4u, xm * 4u, xp * 4u, fpop);
+  pull9<WALLS, ST_F32>(rf, a.plane, nx, ny, y0, xc, xm, xp, fpop);
   __syncthreads();
 
 #pragma unroll 1
   for (int k = 0; k < rows; ++k) {
     const int y = y0 + k;
     float fnext[9];
-    if (k + 1 < rows) pull9<WALLS>(rf, pb, rb, ny, y + 1, xc * 4u, xm * 4u, xp * 4u, fnext);
+    if (k + 1 < rows) pull9<WALLS, ST_F32>(rf, a.plane, nx, ny, y + 1, xc, xm, xp, fnext);
     s_phi[(y + 2) & 7][j] = phi_at(y + 2, xc, xm, xp);
     if (hl) s_phi[(y + 2) & 7][hj] = phi_at(y + 2, hc, hm, hp);
     __syncthreads();
@@ -593,25 +652,28 @@ __device__ __forceinline__ void stencil_at(const float* f, int nx, int ny, int x
 // The initial state is written in that form, so that the first pull returns
 // g_i = g_i^eq(phi0, mu[phi0], u(t0)) (and f_i = f_i^eq(0, rho(phi0), u0)) at every node.
 template <bool WALLS>
-__device__ __forceinline__ uint32_t push_index(int nx, int ny, uint32_t plane, int x, int y,
-                                               int i) {
+__device__ __forceinline__ void push_target(int nx, int ny, int x, int y, int i, int& plane_i,
+                                            uint32_t& node) {
   int ty = y - CY[i];
   if (WALLS && (ty < 0 || ty >= ny)) {
     constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
-    return (uint32_t)OPP[i] * plane + (uint32_t)y * nx + x;
+    plane_i = OPP[i];
+    node = (uint32_t)y * nx + x;
+    return;
   }
   int tx = x - CX[i];
   tx = tx < 0 ? tx + nx : (tx >= nx ? tx - nx : tx);
   ty = ty < 0 ? ty + ny : (ty >= ny ? ty - ny : ty);
-  return (uint32_t)i * plane + (uint32_t)ty * nx + tx;
+  plane_i = i;
+  node = (uint32_t)ty * nx + tx;
 }
 
-template <bool WALLS, int VMODE>
+template <bool WALLS, int VMODE, int ST>
 __global__ void __launch_bounds__(256) k_init(const Coef c, int nx, int ny, uint32_t plane,
                                               const float* __restrict__ phi0, const float* ax,
                                               const float* ay, const float* bx, const float* by,
                                               const float* ux, const float* uy, float tf,
-                                              float* __restrict__ g, float* __restrict__ f) {
+                                              char* __restrict__ g, float* __restrict__ f) {
   const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
   if (x >= nx) return;
   const uint32_t k = (uint32_t)y * nx + x;
@@ -627,7 +689,7 @@ __global__ void __launch_bounds__(256) k_init(const Coef c, int nx, int ny, uint
     u = tf * ux[k];
     v = tf * uy[k];
   }
-  // g^eq of Eq. geq (no source term); g_0 through sum_i g_i^eq = phi as in collide_g
+  // g^eq of Eq. geq (no source term); g_0 through sum_i g_i^eq = phi as in the step
   const float em = c.eta * mu, usq15 = 1.5f * (u * u + v * v), A = em - phi * usq15;
   float geq[9];
 #pragma unroll
@@ -635,27 +697,49 @@ __global__ void __launch_bounds__(256) k_init(const Coef c, int nx, int ny, uint
     const float cu = CX[i] * u + CY[i] * v;
     geq[i] = WT[i] * (A + phi * cu * (3.0f + 4.5f * cu));
   }
-  close_mass((double)phi, geq);
+  uint32_t h[9];
+  if (ST == ST_F32) {
+    close_mass((double)phi, geq);
+  } else {
 #pragma unroll
-  for (int i = 0; i < 9; ++i) g[push_index<WALLS>(nx, ny, plane, x, y, i)] = geq[i];
+    for (int i = 1; i < 9; ++i) {
+      h[i] = enc16<ST>(geq[i] * INV_W[i]);
+      geq[i] = WT[i] * dec16<ST>(h[i]);
+    }
+    geq[0] = (float)((double)phi - sum8_hi(geq));
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    int pi;
+    uint32_t node;
+    push_target<WALLS>(nx, ny, x, y, i, pi, node);
+    if (ST == ST_F32 || pi == 0)
+      reinterpret_cast<float*>(g)[(uint32_t)pi * plane + node] = geq[i];
+    else
+      reinterpret_cast<unsigned short*>(g + 4u * plane)[(uint32_t)(pi - 1) * plane + node] =
+          (unsigned short)h[i];
+  }
   if (f) {
     const float rho = c.a * phi + c.b;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const float cu = CX[i] * u + CY[i] * v;
-      f[push_index<WALLS>(nx, ny, plane, x, y, i)] = WT[i] * rho * (cu * (3.0f + 4.5f * cu) - usq15);
+      int pi;
+      uint32_t node;
+      push_target<WALLS>(nx, ny, x, y, i, pi, node);
+      f[(uint32_t)pi * plane + node] = WT[i] * rho * (cu * (3.0f + 4.5f * cu) - usq15);
     }
   }
 }
 
-template <bool WALLS>
-__global__ void __launch_bounds__(256) k_phi_field(const float* __restrict__ g, uint32_t plane,
+template <bool WALLS, int ST>
+__global__ void __launch_bounds__(256) k_phi_field(const void* __restrict__ g, uint32_t plane,
                                                    int nx, int ny, float* __restrict__ phi) {
   const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
   if (x >= nx) return;
   float p[9];
-  pull9<WALLS>(make_rsrc(g, 9u * plane * 4u), plane * 4u, (uint32_t)nx * 4u, ny, y, x * 4u,
-               (x == 0 ? nx - 1 : x - 1) * 4u, (x == nx - 1 ? 0 : x + 1) * 4u, p);
+  pull9<WALLS, ST>(make_rsrc(g, pop_bytes(ST, plane)), plane, nx, ny, y, x,
+                   x == 0 ? nx - 1 : x - 1, x == nx - 1 ? 0 : x + 1, p);
   phi[(uint32_t)y * nx + x] = sum9(p);
 }
 
@@ -777,89 +861,131 @@ __global__ void __launch_bounds__(DIAG_THREADS) k_diag_final(const double* __res
   if (threadIdx.x < NDIAG) out[threadIdx.x] = sh[threadIdx.x][0];
 }
 
-template <int TX, bool WALLS, int VMODE>
+template <int TX, bool WALLS, int VMODE, int ST>
 hipError_t phi_step_m(bool model2, const StepArgs& a, int nb, hipStream_t s) {
   if (model2)
-    hipLaunchKernelGGL((k_phi_step<TX, WALLS, VMODE, true>), dim3(nb), dim3(TX), 0, s, a);
+    hipLaunchKernelGGL((k_phi_step<TX, WALLS, VMODE, true, ST>), dim3(nb), dim3(TX), 0, s, a);
   else
-    hipLaunchKernelGGL((k_phi_step<TX, WALLS, VMODE, false>), dim3(nb), dim3(TX), 0, s, a);
+    hipLaunchKernelGGL((k_phi_step<TX, WALLS, VMODE, false, ST>), dim3(nb), dim3(TX), 0, s, a);
   return hipGetLastError();
 }
 
-template <int TX, bool WALLS>
+template <int TX, bool WALLS, int ST>
 hipError_t phi_step_v(int vmode, bool model2, const StepArgs& a, int nb, hipStream_t s) {
   switch (vmode) {
-    case VEL_SEP: return phi_step_m<TX, WALLS, VEL_SEP>(model2, a, nb, s);
-    case VEL_FIELD: return phi_step_m<TX, WALLS, VEL_FIELD>(model2, a, nb, s);
-    default: return phi_step_m<TX, WALLS, VEL_NSFIELD>(model2, a, nb, s);
+    case VEL_SEP: return phi_step_m<TX, WALLS, VEL_SEP, ST>(model2, a, nb, s);
+    case VEL_FIELD: return phi_step_m<TX, WALLS, VEL_FIELD, ST>(model2, a, nb, s);
+    default: return phi_step_m<TX, WALLS, VEL_NSFIELD, ST>(model2, a, nb, s);
   }
 }
 
-template <int TX>
-hipError_t phi_step_w(bool walls, int vmode, bool model2, const StepArgs& a, int nb,
+template <int ST>
+hipError_t phi_step_t(int tx, bool walls, int vmode, bool model2, const StepArgs& a, int nb,
                       hipStream_t s) {
-  return walls ? phi_step_v<TX, true>(vmode, model2, a, nb, s)
-               : phi_step_v<TX, false>(vmode, model2, a, nb, s);
+  switch (tx) {
+    case 128:
+      return walls ? phi_step_v<128, true, ST>(vmode, model2, a, nb, s)
+                   : phi_step_v<128, false, ST>(vmode, model2, a, nb, s);
+    case 256:
+      return walls ? phi_step_v<256, true, ST>(vmode, model2, a, nb, s)
+                   : phi_step_v<256, false, ST>(vmode, model2, a, nb, s);
+    case 512:
+      return walls ? phi_step_v<512, true, ST>(vmode, model2, a, nb, s)
+                   : phi_step_v<512, false, ST>(vmode, model2, a, nb, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int TX, int ST>
+void ns_step_l(bool walls, const NsArgs& a, int nb, hipStream_t s) {
+  if (walls) hipLaunchKernelGGL((k_ns_step<TX, true, ST>), dim3(nb), dim3(TX), 0, s, a);
+  else hipLaunchKernelGGL((k_ns_step<TX, false, ST>), dim3(nb), dim3(TX), 0, s, a);
+}
+
+template <int ST>
+hipError_t ns_step_t(int tx, bool walls, const NsArgs& a, int nb, hipStream_t s) {
+  switch (tx) {
+    case 128: ns_step_l<128, ST>(walls, a, nb, s); break;
+    case 256: ns_step_l<256, ST>(walls, a, nb, s); break;
+    case 512: ns_step_l<512, ST>(walls, a, nb, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int ST>
+void init_l(bool walls, int vmode, dim3 grid, hipStream_t s, const Coef& c, int nx, int ny,
+            uint32_t plane, const float* phi0, const float* ax, const float* ay,
+            const float* bx, const float* by, const float* ux, const float* uy, float tf,
+            char* g, float* f) {
+  const bool sep = vmode == VEL_SEP;
+  if (walls && sep)
+    hipLaunchKernelGGL((k_init<true, VEL_SEP, ST>), grid, dim3(256), 0, s, c, nx, ny, plane, phi0, ax, ay, bx, by, ux, uy, tf, g, f);
+  else if (walls)
+    hipLaunchKernelGGL((k_init<true, VEL_FIELD, ST>), grid, dim3(256), 0, s, c, nx, ny, plane, phi0, ax, ay, bx, by, ux, uy, tf, g, f);
+  else if (sep)
+    hipLaunchKernelGGL((k_init<false, VEL_SEP, ST>), grid, dim3(256), 0, s, c, nx, ny, plane, phi0, ax, ay, bx, by, ux, uy, tf, g, f);
+  else
+    hipLaunchKernelGGL((k_init<false, VEL_FIELD, ST>), grid, dim3(256), 0, s, c, nx, ny, plane, phi0, ax, ay, bx, by, ux, uy, tf, g, f);
 }
 
 }  // namespace
 
-hipError_t launch_phi_step(int tx, bool walls, int vmode, bool model2, const StepArgs& a,
-                           int nblocks, hipStream_t s) {
-  switch (tx) {
-    case 64: return phi_step_w<64>(walls, vmode, model2, a, nblocks, s);
-    case 128: return phi_step_w<128>(walls, vmode, model2, a, nblocks, s);
-    case 256: return phi_step_w<256>(walls, vmode, model2, a, nblocks, s);
-    case 512: return phi_step_w<512>(walls, vmode, model2, a, nblocks, s);
+uint32_t population_bytes(int storage, uint32_t plane) { return pop_bytes(storage, plane); }
+
+hipError_t launch_phi_step(int tx, bool walls, int vmode, bool model2, int storage,
+                           const StepArgs& a, int nblocks, hipStream_t s) {
+  switch (storage) {
+    case ST_F32: return phi_step_t<ST_F32>(tx, walls, vmode, model2, a, nblocks, s);
+    case ST_F16: return phi_step_t<ST_F16>(tx, walls, vmode, model2, a, nblocks, s);
+    case ST_BF16: return phi_step_t<ST_BF16>(tx, walls, vmode, model2, a, nblocks, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_ns_step(int tx, bool walls, const NsArgs& a, int nblocks, hipStream_t s) {
-  switch (tx) {
-    case 64:
-      if (walls) hipLaunchKernelGGL((k_ns_step<64, true>), dim3(nblocks), dim3(64), 0, s, a);
-      else hipLaunchKernelGGL((k_ns_step<64, false>), dim3(nblocks), dim3(64), 0, s, a);
-      break;
-    case 128:
-      if (walls) hipLaunchKernelGGL((k_ns_step<128, true>), dim3(nblocks), dim3(128), 0, s, a);
-      else hipLaunchKernelGGL((k_ns_step<128, false>), dim3(nblocks), dim3(128), 0, s, a);
-      break;
-    case 256:
-      if (walls) hipLaunchKernelGGL((k_ns_step<256, true>), dim3(nblocks), dim3(256), 0, s, a);
-      else hipLaunchKernelGGL((k_ns_step<256, false>), dim3(nblocks), dim3(256), 0, s, a);
-      break;
-    case 512:
-      if (walls) hipLaunchKernelGGL((k_ns_step<512, true>), dim3(nblocks), dim3(512), 0, s, a);
-      else hipLaunchKernelGGL((k_ns_step<512, false>), dim3(nblocks), dim3(512), 0, s, a);
-      break;
+hipError_t launch_ns_step(int tx, bool walls, int storage, const NsArgs& a, int nblocks,
+                          hipStream_t s) {
+  switch (storage) {
+    case ST_F32: return ns_step_t<ST_F32>(tx, walls, a, nblocks, s);
+    case ST_F16: return ns_step_t<ST_F16>(tx, walls, a, nblocks, s);
+    case ST_BF16: return ns_step_t<ST_BF16>(tx, walls, a, nblocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_init(bool walls, int vmode, int storage, const Coef& c, int nx, int ny,
+                       uint32_t plane, const float* phi0, const float* ax, const float* ay,
+                       const float* bx, const float* by, const float* ux, const float* uy,
+                       float tf, void* g, float* f, hipStream_t s) {
+  const dim3 grid((nx + 255) / 256, ny);
+  char* gb = static_cast<char*>(g);
+  switch (storage) {
+    case ST_F32: init_l<ST_F32>(walls, vmode, grid, s, c, nx, ny, plane, phi0, ax, ay, bx, by, ux, uy, tf, gb, f); break;
+    case ST_F16: init_l<ST_F16>(walls, vmode, grid, s, c, nx, ny, plane, phi0, ax, ay, bx, by, ux, uy, tf, gb, f); break;
+    case ST_BF16: init_l<ST_BF16>(walls, vmode, grid, s, c, nx, ny, plane, phi0, ax, ay, bx, by, ux, uy, tf, gb, f); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_init(bool walls, int vmode, const Coef& c, int nx, int ny, uint32_t plane,
-                       const float* phi0, const float* ax, const float* ay, const float* bx,
-                       const float* by, const float* ux, const float* uy, float tf, float* g,
-                       float* f, hipStream_t s) {
+hipError_t launch_phi_field(bool walls, int storage, const void* g, uint32_t plane, int nx,
+                            int ny, float* phi, hipStream_t s) {
   const dim3 grid((nx + 255) / 256, ny);
-  const bool sep = vmode == VEL_SEP;
-  if (walls && sep)
-    hipLaunchKernelGGL((k_init<true, VEL_SEP>), grid, dim3(256), 0, s, c, nx, ny, plane, phi0, ax, ay, bx, by, ux, uy, tf, g, f);
-  else if (walls)
-    hipLaunchKernelGGL((k_init<true, VEL_FIELD>), grid, dim3(256), 0, s, c, nx, ny, plane, phi0, ax, ay, bx, by, ux, uy, tf, g, f);
-  else if (sep)
-    hipLaunchKernelGGL((k_init<false, VEL_SEP>), grid, dim3(256), 0, s, c, nx, ny, plane, phi0, ax, ay, bx, by, ux, uy, tf, g, f);
-  else
-    hipLaunchKernelGGL((k_init<false, VEL_FIELD>), grid, dim3(256), 0, s, c, nx, ny, plane, phi0, ax, ay, bx, by, ux, uy, tf, g, f);
-  return hipGetLastError();
-}
-
-hipError_t launch_phi_field(bool walls, const float* g, uint32_t plane, int nx, int ny,
-                            float* phi, hipStream_t s) {
-  const dim3 grid((nx + 255) / 256, ny);
-  if (walls) hipLaunchKernelGGL((k_phi_field<true>), grid, dim3(256), 0, s, g, plane, nx, ny, phi);
-  else hipLaunchKernelGGL((k_phi_field<false>), grid, dim3(256), 0, s, g, plane, nx, ny, phi);
+  switch (storage) {
+    case ST_F32:
+      if (walls) hipLaunchKernelGGL((k_phi_field<true, ST_F32>), grid, dim3(256), 0, s, g, plane, nx, ny, phi);
+      else hipLaunchKernelGGL((k_phi_field<false, ST_F32>), grid, dim3(256), 0, s, g, plane, nx, ny, phi);
+      break;
+    case ST_F16:
+      if (walls) hipLaunchKernelGGL((k_phi_field<true, ST_F16>), grid, dim3(256), 0, s, g, plane, nx, ny, phi);
+      else hipLaunchKernelGGL((k_phi_field<false, ST_F16>), grid, dim3(256), 0, s, g, plane, nx, ny, phi);
+      break;
+    case ST_BF16:
+      if (walls) hipLaunchKernelGGL((k_phi_field<true, ST_BF16>), grid, dim3(256), 0, s, g, plane, nx, ny, phi);
+      else hipLaunchKernelGGL((k_phi_field<false, ST_BF16>), grid, dim3(256), 0, s, g, plane, nx, ny, phi);
+      break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -70,10 +70,22 @@ def test_workspace_and_alignment_checks():
     # separable mode without tables
     p.velocity_mode = lbm.VEL_SEPARABLE
     assert args(4096, need, 4096) == lbm.EINVAL
-    # a storage mode that is not built
+    # a storage mode outside LBM_CH_STORE_*
     p.velocity_mode = lbm.VEL_NONE
     p.storage = 9
-    assert args(4096, need, 4096) == lbm.EUNSUPPORTED
+    assert L.lbm_ch_workspace_bytes(ctypes.byref(p)) == 0
+    assert args(4096, need, 4096) == lbm.EINVAL
+
+
+def test_storage_modes_shrink_the_workspace():
+    L = lbm.lib()
+    sizes = {}
+    for st in (lbm.STORE_F32, lbm.STORE_F16, lbm.STORE_BF16):
+        p = lbm.make_params(256, 256, storage=st)
+        sizes[st] = L.lbm_ch_workspace_bytes(ctypes.byref(p))
+    # two population buffers: 36 B per node in float32, 20 B per node in 16-bit modes
+    assert sizes[lbm.STORE_F32] - sizes[lbm.STORE_F16] == 2 * 16 * 256 * 256
+    assert sizes[lbm.STORE_F16] == sizes[lbm.STORE_BF16]
 
 
 def test_context_calls_reject_null_and_strerror():
