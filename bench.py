@@ -35,6 +35,7 @@ BYTES_PER_LU = 72.0
 KERNEL_SRC = os.path.join(ROOT, "paper_1805_00007_amd", "csrc", "lbm_ch_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "phi_step_vortex2048_traffic.txt")
 GOLDEN = os.path.join(ROOT, "tests", "golden", "vortex2048_oracle_1000.npz")
+ADJ_GOLDEN = os.path.join(ROOT, "tests", "golden", "adjoint256_oracle_2000.npz")
 
 
 def kernel_sha():
@@ -126,6 +127,66 @@ def storage_variant(lbm, torch, storage, steps):
                                                        / (ref ** 2).sum()))
         out["mass_drift_1000"] = abs(d["mass"] - float(g["mass0"])) / float(g["abs_mass0"])
     return out
+
+
+def adjoint_leg(lbm, torch, reps=3):
+    """One forward plus backward pass of the 256^2, 2000-step interface-matching problem
+    (16 stream-function coefficients, sqrt(N) checkpointing), against the plain forward
+    run of the same workload, and its gradients against stored FP64 central differences."""
+    import numpy as np
+    import workloads
+    from paper_1805_00007_amd.adjoint import evolve
+    if not os.path.exists(ADJ_GOLDEN):
+        return None
+    g = np.load(ADJ_GOLDEN)
+    steps = int(g["steps"])
+    case = workloads.adjoint_case(256, steps)
+    dev = torch.device("cuda:0")
+    target = torch.tensor(g["phi_target"], dtype=torch.float32, device=dev)
+    basis = torch.tensor(case.basis, dtype=torch.float32, device=dev)
+    U, V = case.field()
+
+    def plain():
+        s = lbm.Solver(case.n, case.n, case.phi0, field=(U, V), device=dev, **case.phys)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s.close()
+        return dt
+
+    def fwd_bwd():
+        phi0 = torch.tensor(case.phi0, dtype=torch.float32, device=dev, requires_grad=True)
+        theta = torch.tensor(case.theta, dtype=torch.float32, device=dev, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        uv = case.scale * torch.tensordot(theta, basis, dims=1)
+        phi = evolve(phi0, uv[0], uv[1], steps, **case.phys)
+        loss = ((phi - target) ** 2).sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return dt, float(loss.detach()), theta.grad.double().cpu().numpy(), \
+            phi0.grad.double().cpu().numpy()
+
+    plain()
+    fwd_bwd()
+    t_plain = min(plain() for _ in range(reps))
+    runs = [fwd_bwd() for _ in range(reps)]
+    t_adj = min(r[0] for r in runs)
+    _, loss, gt, gp = runs[0]
+    ref_t, ref_p = g["grad_theta"], g["grad_phi0"]
+    return {"workload": "adjoint256: 256^2, %d steps, 16 stream-function coefficients" % steps,
+            "adjoint_ms": round(t_adj * 1e3, 2),
+            "forward_ms_plain": round(t_plain * 1e3, 2),
+            "ratio_to_plain_forward": round(t_adj / t_plain, 2),
+            "checkpoints": -(-steps // (int(np.ceil(np.sqrt(steps))))),
+            "loss_rel_err": abs(loss - float(g["loss"])) / float(g["loss"]),
+            "grad_theta_rel_err": float(np.linalg.norm(gt - ref_t) / np.linalg.norm(ref_t)),
+            "grad_phi0_rel_err": float(np.linalg.norm(gp.ravel()[g["phi0_index"]] - ref_p)
+                                       / np.linalg.norm(ref_p)),
+            "reference": "FP64 oracle central differences, h = %g" % float(g["h"])}
 
 
 def main():
@@ -234,6 +295,7 @@ def main():
         out["accuracy"] = accuracy(lbm, workloads.metric2048(steps=1000), torch)
         out["storage_variants"] = {name: storage_variant(lbm, torch, st, args.steps)
                                    for name, st in (("f16", 1), ("bf16", 2))}
+        out["adjoint"] = adjoint_leg(lbm, torch)
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(workloads.metric2048(steps=args.cpu_steps),
                                            args.cpu_steps)

@@ -174,6 +174,44 @@ int lbm_ch_save_state(lbm_ch_ctx* ctx, void* dst, size_t bytes, hipStream_t stre
 int lbm_ch_load_state(lbm_ch_ctx* ctx, const void* src, size_t bytes, int64_t step,
                       hipStream_t stream);
 
+/* Discrete adjoint of the step at tau_g = 1
+ * -----------------------------------------
+ * With tau_g = 1 the collision of Eq. LB keeps nothing of the incoming populations
+ * (g* = g^eq + S/2 with Eqs. geq and liangFi), so one step is a map of the order
+ * parameter alone:
+ *   phi^{n+1} = phi^n + M lap(mu^n) + sum_i w_i T_{-c_i}[phi^n s_i(u^n)] - div(F^n)/2,
+ * where (T_c psi)(x) = psi(x + c), s_i as above and F = F1 (+ F2 for Model-II) with
+ * grad p = 0.  The calls below propagate a derivative dL/dphi^{n+1} back through this
+ * map, using that lap is symmetric, grad and div are antisymmetric and T_c^T = T_{-c}
+ * on the periodic lattice.  With 16-bit storage the forward map differs from this one
+ * by the storage rounding. */
+
+/* Bytes of device scratch lbm_ch_adjoint needs (8 nx ny floats), 0 if p is invalid. */
+size_t lbm_ch_adjoint_scratch_bytes(const lbm_ch_params* p);
+
+/* Enqueue nsteps steps exactly as lbm_ch_step does, and before each step n write the
+ * order parameter phi^n into phi_traj + (n - n0) nx ny (n0: the step counter at the
+ * call; phi_traj holds nsteps * nx * ny floats): the forward trajectory that
+ * lbm_ch_adjoint reads.  Any mode.  Errors: LBM_CH_EINVAL for nsteps < 0 or a NULL or
+ * unaligned phi_traj when nsteps > 0. */
+int lbm_ch_record(lbm_ch_ctx* ctx, int64_t nsteps, float* phi_traj, hipStream_t stream);
+
+/* Enqueue the reverse steps n = n_end - 1 down to n_end - nsteps.  phi_traj holds
+ * phi^n for n = n_end - nsteps .. n_end - 1 in that order (as lbm_ch_record writes it).
+ * lam (nx*ny floats) holds dL/dphi^{n_end} on entry and dL/dphi^{n_end - nsteps} when
+ * the work has run (updated in place).  grad_u and grad_v are both NULL or both device
+ * arrays of nx*ny floats; they accumulate (+=) sum_n tf[n] dL/du^n and
+ * sum_n tf[n] dL/dv^n, the derivative with respect to the base velocity field (ux, uy
+ * with LBM_CH_VEL_FIELD; the products ax[x] ay[y] and bx[x] by[y] with
+ * LBM_CH_VEL_SEPARABLE).  scratch: at least lbm_ch_adjoint_scratch_bytes device bytes,
+ * 4-byte aligned, contents undefined afterwards.  The context's state and step counter
+ * are not changed.  Errors: LBM_CH_EUNSUPPORTED unless tau_g == 1, walls == 0 and the
+ * velocity is prescribed; LBM_CH_EINVAL for nsteps < 0, n_end < nsteps, NULL or
+ * unaligned arrays, or too little scratch. */
+int lbm_ch_adjoint(lbm_ch_ctx* ctx, int64_t n_end, int64_t nsteps, const float* phi_traj,
+                   float* lam, float* grad_u, float* grad_v, void* scratch,
+                   size_t scratch_bytes, hipStream_t stream);
+
 /* Release the context (host memory only).  NULL is accepted. */
 int lbm_ch_destroy(lbm_ch_ctx* ctx);
 

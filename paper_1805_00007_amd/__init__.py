@@ -27,7 +27,8 @@ STORE_F32, STORE_F16, STORE_BF16 = 0, 1, 2
 # Every symbol include/lbm_ch.h declares.
 EXPORTS = ("lbm_ch_workspace_bytes", "lbm_ch_init", "lbm_ch_step", "lbm_ch_moments",
            "lbm_ch_diagnostics", "lbm_ch_check_finite", "lbm_ch_step_count",
-           "lbm_ch_state_bytes", "lbm_ch_save_state", "lbm_ch_load_state", "lbm_ch_destroy",
+           "lbm_ch_state_bytes", "lbm_ch_save_state", "lbm_ch_load_state",
+           "lbm_ch_adjoint_scratch_bytes", "lbm_ch_record", "lbm_ch_adjoint", "lbm_ch_destroy",
            "lbm_ch_strerror", "lbm_ch_last_hip_error")
 
 
@@ -85,6 +86,10 @@ def lib():
         L.lbm_ch_state_bytes.restype = ctypes.c_size_t
         L.lbm_ch_save_state.argtypes = [vp, vp, ctypes.c_size_t, vp]
         L.lbm_ch_load_state.argtypes = [vp, vp, ctypes.c_size_t, i64, vp]
+        L.lbm_ch_adjoint_scratch_bytes.argtypes = [PP]
+        L.lbm_ch_adjoint_scratch_bytes.restype = ctypes.c_size_t
+        L.lbm_ch_record.argtypes = [vp, i64, vp, vp]
+        L.lbm_ch_adjoint.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.lbm_ch_destroy.argtypes = [vp]
         L.lbm_ch_strerror.argtypes = [i32]
         L.lbm_ch_strerror.restype = ctypes.c_char_p
@@ -115,6 +120,13 @@ def workspace_bytes(params: Params) -> int:
 
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _device_f32(torch, a, device):
+    """A contiguous float32 copy (or view) of an array or tensor on the device."""
+    if isinstance(a, torch.Tensor):
+        return a.detach().to(device=device, dtype=torch.float32).contiguous()
+    return torch.as_tensor(np.asarray(a), dtype=torch.float32, device=device).contiguous()
 
 
 class Solver:
@@ -158,11 +170,11 @@ class Solver:
             if tf is None:
                 tf = velocity.get("tf")
         elif mode == VEL_FIELD:
-            U, V = [torch.as_tensor(np.asarray(a), **f32).contiguous() for a in field]
+            U, V = [_device_f32(torch, a, self.device) for a in field]
             self._keep += [U, V]
             vel.ux, vel.uy = U.data_ptr(), V.data_ptr()
         elif mode == VEL_NS and u0 is not None:
-            U, V = [torch.as_tensor(np.asarray(a), **f32).contiguous() for a in u0]
+            U, V = [_device_f32(torch, a, self.device) for a in u0]
             self._keep += [U, V]
             vel.ux, vel.uy = U.data_ptr(), V.data_ptr()
         tfa = None
@@ -170,7 +182,7 @@ class Solver:
             tfa = np.ascontiguousarray(tf, dtype=np.float64)
             vel.time_factor = tfa.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             vel.n_time_factor = len(tfa)
-        phi0 = torch.as_tensor(phi0, **f32).contiguous()
+        phi0 = _device_f32(torch, phi0, self.device)
         assert phi0.shape == (ny, nx)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         ctx = ctypes.c_void_p()
@@ -230,6 +242,35 @@ class Solver:
         _check(lib().lbm_ch_load_state(self.ctx, _ptr(buf), buf.numel(), int(step), self._s()),
                "lbm_ch_load_state")
         return self
+
+    def adjoint_scratch_bytes(self):
+        return lib().lbm_ch_adjoint_scratch_bytes(ctypes.byref(self.params))
+
+    def record(self, nsteps, phi_traj):
+        """Advance ``nsteps`` steps, writing phi^n before each step into
+        ``phi_traj[n - n0]`` (a (nsteps, ny, nx) float32 device tensor)."""
+        assert phi_traj.is_contiguous() and phi_traj.dtype == self.torch.float32
+        assert phi_traj.numel() >= nsteps * self.nx * self.ny
+        _check(lib().lbm_ch_record(self.ctx, int(nsteps), _ptr(phi_traj), self._s()),
+               "lbm_ch_record")
+        return self
+
+    def adjoint(self, n_end, nsteps, phi_traj, lam, grad_u=None, grad_v=None, scratch=None):
+        """Reverse steps n_end-1 .. n_end-nsteps of the tau_g = 1 map: ``lam`` holds
+        dL/dphi^{n_end} and becomes dL/dphi^{n_end-nsteps}; ``grad_u``/``grad_v``
+        accumulate the derivative with respect to the base velocity field."""
+        t = self.torch
+        for a in (phi_traj, lam, grad_u, grad_v):
+            assert a is None or (a.is_contiguous() and a.dtype == t.float32)
+        assert phi_traj.numel() >= nsteps * self.nx * self.ny
+        nbytes = self.adjoint_scratch_bytes()
+        if scratch is None:
+            scratch = t.empty(nbytes, dtype=t.uint8, device=self.device)
+        _check(lib().lbm_ch_adjoint(self.ctx, int(n_end), int(nsteps), _ptr(phi_traj), _ptr(lam),
+                                    _ptr(grad_u), _ptr(grad_v), _ptr(scratch),
+                                    scratch.numel() * scratch.element_size(), self._s()),
+               "lbm_ch_adjoint")
+        return lam
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -1,0 +1,72 @@
+"""Reverse-mode derivatives of a phase-field run at tau_g = 1, as a torch.autograd.Function.
+
+``evolve(phi0, U, V, steps, **params)`` returns phi^N of the solver started from phi0 in
+the prescribed velocity field u^n = tf[n] (U, V), and is differentiable with respect to
+phi0 and (U, V).  A parameterised velocity (for instance stream-function coefficients
+times fixed mode fields) reaches its parameters through ordinary torch operations on U
+and V before the call.
+
+Forward: the solver runs N steps on the GPU and keeps its state every S = ceil(sqrt(N))
+steps (``lbm_ch_save_state``).  Backward: for each segment from the last, the state is
+reloaded, the segment re-run with ``lbm_ch_record`` (phi^n of every step), and
+``lbm_ch_adjoint`` carries dL/dphi back over it while accumulating dL/d(U, V).  Memory:
+ceil(N/S) states plus S phi fields.  All derivative arithmetic runs in the library's
+kernels; this module only orders the calls.
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+from . import Solver
+
+
+class _Evolve(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, phi0, U, V, steps, segment, tf, params):
+        ny, nx = phi0.shape
+        s = Solver(nx, ny, phi0.detach(), field=(U.detach(), V.detach()), tf=tf,
+                   device=phi0.device, **params)
+        s.stream.wait_stream(torch.cuda.current_stream(phi0.device))
+        seg = int(segment) if segment else max(1, math.isqrt(max(steps - 1, 0)) + 1)
+        ckpts = []
+        n = 0
+        while n < steps:
+            k = min(seg, steps - n)
+            buf, _ = s.save_state()
+            ckpts.append((n, k, buf))
+            s.step(k)
+            n += k
+        phi = s.phi()
+        torch.cuda.current_stream(phi0.device).wait_stream(s.stream)
+        ctx.solver, ctx.ckpts, ctx.seg = s, ckpts, seg
+        return phi
+
+    @staticmethod
+    def backward(ctx, gphi):
+        s = ctx.solver
+        dev = s.device
+        s.stream.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(s.stream):
+            lam = gphi.detach().to(torch.float32).contiguous().clone()
+            want_u = ctx.needs_input_grad[1] or ctx.needs_input_grad[2]
+            gu = torch.zeros_like(lam) if want_u else None
+            gv = torch.zeros_like(lam) if want_u else None
+            traj = torch.empty((ctx.seg, s.ny, s.nx), dtype=torch.float32, device=dev)
+            scratch = torch.empty(s.adjoint_scratch_bytes(), dtype=torch.uint8, device=dev)
+            for n0, k, buf in reversed(ctx.ckpts):
+                s.load_state(buf, n0)
+                s.record(k, traj)
+                s.adjoint(n0 + k, k, traj, lam, gu, gv, scratch)
+        torch.cuda.current_stream(dev).wait_stream(s.stream)
+        return lam, gu, gv, None, None, None, None
+
+
+def evolve(phi0, U, V, steps, *, tf=None, segment=None, **params):
+    """phi after ``steps`` steps from ``phi0`` (ny, nx) in the velocity field tf[n] (U, V),
+    differentiable in phi0, U and V.  ``params`` are those of ``lbm_ch_params``; the
+    derivative needs tau_g = 1, periodic boundaries and a prescribed velocity."""
+    if float(params.get("tau_g", 1.0)) != 1.0 or params.get("walls", 0):
+        raise ValueError("the discrete adjoint covers tau_g = 1 on a periodic lattice")
+    return _Evolve.apply(phi0, U, V, int(steps), segment, tf, dict(params))

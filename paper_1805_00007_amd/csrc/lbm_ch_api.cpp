@@ -404,6 +404,52 @@ int lbm_ch_load_state(lbm_ch_ctx* c, const void* src, size_t bytes, int64_t step
   return LBM_CH_OK;
 }
 
+size_t lbm_ch_adjoint_scratch_bytes(const lbm_ch_params* p) {
+  if (!valid_params(p)) return 0;
+  return (size_t)8 * p->nx * p->ny * sizeof(float);
+}
+
+int lbm_ch_record(lbm_ch_ctx* c, int64_t nsteps, float* phi_traj, hipStream_t stream) {
+  if (!live(c)) return LBM_CH_ESTATE;
+  if (nsteps < 0) return LBM_CH_EINVAL;
+  if (nsteps == 0) return LBM_CH_OK;
+  if (!phi_traj || !aligned4(phi_traj)) return LBM_CH_EINVAL;
+  const size_t nodes = (size_t)c->p.nx * c->p.ny;
+  for (int64_t k = 0; k < nsteps; ++k) {
+    hipError_t e = launch_phi_field(c->p.walls != 0, c->p.storage, c->g[c->cur], c->L.plane,
+                                    c->p.nx, c->p.ny, phi_traj + (size_t)k * nodes, stream);
+    if (e != hipSuccess) return hip_fail(e);
+    const int r = lbm_ch_step(c, 1, stream);
+    if (r != LBM_CH_OK) return r;
+  }
+  return LBM_CH_OK;
+}
+
+int lbm_ch_adjoint(lbm_ch_ctx* c, int64_t n_end, int64_t nsteps, const float* phi_traj,
+                   float* lam, float* grad_u, float* grad_v, void* scratch,
+                   size_t scratch_bytes, hipStream_t stream) {
+  if (!live(c)) return LBM_CH_ESTATE;
+  if (c->p.tau_g != 1.0 || c->p.walls != 0 || c->p.velocity_mode == LBM_CH_VEL_NS)
+    return LBM_CH_EUNSUPPORTED;
+  if (nsteps < 0 || n_end < nsteps) return LBM_CH_EINVAL;
+  if (nsteps == 0) return LBM_CH_OK;
+  if (!phi_traj || !lam || !aligned4(phi_traj) || !aligned4(lam)) return LBM_CH_EINVAL;
+  if ((grad_u == nullptr) != (grad_v == nullptr)) return LBM_CH_EINVAL;
+  if (grad_u && (!aligned4(grad_u) || !aligned4(grad_v))) return LBM_CH_EINVAL;
+  if (!scratch || !aligned4(scratch) || scratch_bytes < lbm_ch_adjoint_scratch_bytes(&c->p))
+    return LBM_CH_EINVAL;
+  const size_t nodes = (size_t)c->p.nx * c->p.ny;
+  for (int64_t k = nsteps - 1; k >= 0; --k) {
+    const int64_t n = n_end - nsteps + k;
+    hipError_t e = launch_adjoint_step(
+        c->c, (float)c->p.mobility, c->p.nx, c->p.ny, c->vmode, c->ax, c->ay, c->bx, c->by,
+        c->ux, c->uy, time_factor(c, n), phi_traj + (size_t)k * nodes, lam, lam, grad_u,
+        grad_v, (float*)scratch, stream);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return LBM_CH_OK;
+}
+
 int lbm_ch_destroy(lbm_ch_ctx* c) {
   if (!c) return LBM_CH_OK;
   if (!live(c)) return LBM_CH_ESTATE;

@@ -861,6 +861,154 @@ __global__ void __launch_bounds__(DIAG_THREADS) k_diag_final(const double* __res
   if (threadIdx.x < NDIAG) out[threadIdx.x] = sh[threadIdx.x][0];
 }
 
+// ---------------------------------------------------------------------------------
+// Discrete adjoint of one step at tau_g = 1 (periodic lattice).  With tau_g = 1 the
+// collision of Eq. LB keeps nothing of the incoming populations (g* = g^eq + S/2), so
+// one step is a map of phi alone:
+//   phi' = phi + M L(mu) + A(phi, u) - Div(F)/2,
+//   mu = f'(phi) - kappa L(phi),  A = sum_i w_i T_{-c_i}[phi s_i(u)],
+//   F = -h(phi) grad mu + K grad(Div(phi u)),  h = phi^2 / rho(phi),
+// with L, grad, Div the isotropic stencils (L symmetric, grad antisymmetric) and
+// (T_c psi)(x) = psi(x + c).  Given lam' = dL/dphi' the passes below form
+//   lam = dL/dphi = lam' + sum_i w_i s_i(u) T_{c_i} lam' - h'(phi) grad mu . lamF
+//         + f''(phi) lamMu - kappa L(lamMu) + u . lamQ,
+//   lamF = grad(lam')/2,  lamMu = M L(lam') + Div(h lamF),
+//   lamD = -K Div(lamF),  lamQ = -grad(lamD),
+//   dL/du = sum_i w_i phi ds_i/du T_{c_i} lam' + phi lamQ,
+// and add tf * dL/du to the caller's gradient of the base velocity field.
+struct AdjArgs {
+  const float* phi;   // forward phi at the start of the step
+  const float* lam1;  // dL/dphi' (after the step)
+  float* lam0;        // dL/dphi (output)
+  float* gu;          // += tf dL/du (base field); may be null
+  float* gv;
+  float* s;           // scratch: 8 fields of nx*ny floats
+  int nx, ny;
+  Coef c;
+  float mob;          // M
+  int vmode;          // VEL_SEP or VEL_FIELD
+  const float *ax, *ay, *bx, *by, *ux, *uy;
+  float tf;
+};
+
+__device__ __forceinline__ float adj_h(const Coef& c, float phi, float& dh) {
+  const float rho = c.a * phi + c.b;
+  const float ir = 1.0f / rho;
+  dh = phi * (c.a * phi + 2.0f * c.b) * ir * ir;
+  return phi * phi * ir;
+}
+__device__ __forceinline__ float d2bulk(const Coef& c, float p) {
+  const float a = p - c.phia, b = p - c.phib, s = 2.0f * p - c.phia - c.phib;
+  return c.beta2 * (b * s + a * s + 2.0f * a * b);
+}
+__device__ __forceinline__ void adj_vel(const AdjArgs& a, int x, int y, float& u, float& v) {
+  if (a.vmode == VEL_SEP) {
+    u = a.tf * a.ax[x] * a.ay[y];
+    v = a.tf * a.bx[x] * a.by[y];
+  } else {
+    u = a.ux ? a.tf * a.ux[(uint32_t)y * a.nx + x] : 0.f;
+    v = a.uy ? a.tf * a.uy[(uint32_t)y * a.nx + x] : 0.f;
+  }
+}
+// 3x3 neighbourhood of a periodic field
+__device__ __forceinline__ void nb3(const float* f, int nx, int ny, int x, int y, float v[3][3]) {
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) v[dy + 1][dx + 1] = field_at<false>(f, nx, ny, x + dx, y + dy);
+}
+
+// scratch fields
+enum { AS_MU = 0, AS_LFX, AS_LFY, AS_WFX, AS_WFY, AS_P1, AS_LMU, AS_LD };
+
+__global__ void __launch_bounds__(256) k_adj_a(const AdjArgs a) {  // mu
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+  if (x >= a.nx) return;
+  float v[3][3];
+  nb3(a.phi, a.nx, a.ny, x, y, v);
+  const uint32_t n = (uint32_t)a.nx * a.ny, k = (uint32_t)y * a.nx + x;
+  a.s[AS_MU * n + k] = mu_bulk(a.c, v[1][1]) - a.c.kappa * lap9(v[0], v[1], v[2], 1);
+}
+
+__global__ void __launch_bounds__(256) k_adj_b(const AdjArgs a) {
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+  if (x >= a.nx) return;
+  const uint32_t n = (uint32_t)a.nx * a.ny, k = (uint32_t)y * a.nx + x;
+  float L[3][3], M[3][3];
+  nb3(a.lam1, a.nx, a.ny, x, y, L);
+  nb3(a.s + AS_MU * n, a.nx, a.ny, x, y, M);
+  const float phi = a.phi[k];
+  float u, v;
+  adj_vel(a, x, y, u, v);
+  const float lfx = 0.5f * ddx(L[0], L[1], L[2], 1), lfy = 0.5f * ddy(L[0], L[1], L[2], 1);
+  float dh;
+  const float h = adj_h(a.c, phi, dh);
+  const float usq = u * u + v * v;
+  float p1 = L[1][1], lu = 0.f, lv = 0.f;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const float cu = CX[i] * u + CY[i] * v;
+    const float si = 3.0f * cu + 4.5f * cu * cu - 1.5f * usq;
+    const float lam = L[1 + CY[i]][1 + CX[i]];  // lam'(x + c_i)
+    p1 += WT[i] * si * lam;
+    // d s_i / du = 3 c_i + 9 (c_i.u) c_i - 3 u
+    lu += WT[i] * phi * (3.0f * CX[i] + 9.0f * cu * CX[i] - 3.0f * u) * lam;
+    lv += WT[i] * phi * (3.0f * CY[i] + 9.0f * cu * CY[i] - 3.0f * v) * lam;
+  }
+  p1 -= dh * (lfx * ddx(M[0], M[1], M[2], 1) + lfy * ddy(M[0], M[1], M[2], 1));
+  a.s[AS_LFX * n + k] = lfx;
+  a.s[AS_LFY * n + k] = lfy;
+  a.s[AS_WFX * n + k] = h * lfx;
+  a.s[AS_WFY * n + k] = h * lfy;
+  a.s[AS_P1 * n + k] = p1;
+  if (a.gu) {  // partial dL/du from A; the lamQ part is added in pass D
+    a.gu[k] += a.tf * lu;
+    a.gv[k] += a.tf * lv;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_adj_c(const AdjArgs a) {
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+  if (x >= a.nx) return;
+  const uint32_t n = (uint32_t)a.nx * a.ny, k = (uint32_t)y * a.nx + x;
+  float L[3][3], WX[3][3], WY[3][3];
+  nb3(a.lam1, a.nx, a.ny, x, y, L);
+  nb3(a.s + AS_WFX * n, a.nx, a.ny, x, y, WX);
+  nb3(a.s + AS_WFY * n, a.nx, a.ny, x, y, WY);
+  a.s[AS_LMU * n + k] = a.mob * lap9(L[0], L[1], L[2], 1) + ddx(WX[0], WX[1], WX[2], 1) +
+                        ddy(WY[0], WY[1], WY[2], 1);
+  if (a.c.k2 != 0.0f) {
+    float FX[3][3], FY[3][3];
+    nb3(a.s + AS_LFX * n, a.nx, a.ny, x, y, FX);
+    nb3(a.s + AS_LFY * n, a.nx, a.ny, x, y, FY);
+    a.s[AS_LD * n + k] = -a.c.k2 * (ddx(FX[0], FX[1], FX[2], 1) + ddy(FY[0], FY[1], FY[2], 1));
+  }
+}
+
+__global__ void __launch_bounds__(256) k_adj_d(const AdjArgs a) {
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+  if (x >= a.nx) return;
+  const uint32_t n = (uint32_t)a.nx * a.ny, k = (uint32_t)y * a.nx + x;
+  float LM[3][3];
+  nb3(a.s + AS_LMU * n, a.nx, a.ny, x, y, LM);
+  const float phi = a.phi[k];
+  float lam = a.s[AS_P1 * n + k] + d2bulk(a.c, phi) * LM[1][1] -
+              a.c.kappa * lap9(LM[0], LM[1], LM[2], 1);
+  if (a.c.k2 != 0.0f) {
+    float LD[3][3];
+    nb3(a.s + AS_LD * n, a.nx, a.ny, x, y, LD);
+    const float lqx = -ddx(LD[0], LD[1], LD[2], 1), lqy = -ddy(LD[0], LD[1], LD[2], 1);
+    float u, v;
+    adj_vel(a, x, y, u, v);
+    lam += u * lqx + v * lqy;
+    if (a.gu) {
+      a.gu[k] += a.tf * phi * lqx;
+      a.gv[k] += a.tf * phi * lqy;
+    }
+  }
+  a.lam0[k] = lam;
+}
+
 template <int TX, bool WALLS, int VMODE, int ST>
 hipError_t phi_step_m(bool model2, const StepArgs& a, int nb, hipStream_t s) {
   if (model2)
@@ -986,6 +1134,23 @@ hipError_t launch_phi_field(bool walls, int storage, const void* g, uint32_t pla
       break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_step(const Coef& c, float mobility, int nx, int ny, int vmode,
+                                const float* ax, const float* ay, const float* bx,
+                                const float* by, const float* ux, const float* uy, float tf,
+                                const float* phi, const float* lam1, float* lam0, float* gu,
+                                float* gv, float* scratch, hipStream_t s) {
+  AdjArgs a{};
+  a.phi = phi; a.lam1 = lam1; a.lam0 = lam0; a.gu = gu; a.gv = gv; a.s = scratch;
+  a.nx = nx; a.ny = ny; a.c = c; a.mob = mobility; a.vmode = vmode;
+  a.ax = ax; a.ay = ay; a.bx = bx; a.by = by; a.ux = ux; a.uy = uy; a.tf = tf;
+  const dim3 grid((nx + 255) / 256, ny);
+  hipLaunchKernelGGL(k_adj_a, grid, dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_b, grid, dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_c, grid, dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_d, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

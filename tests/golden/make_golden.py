@@ -8,6 +8,12 @@ the final extrema.
     python tests/golden/make_golden.py vortex2048     # 2048^2, 1000 steps
     python tests/golden/make_golden.py vortex512      # 512^2, one period T = 20000
     python tests/golden/make_golden.py rt256          # 256x1024 Rayleigh-Taylor, 1000 steps
+    python tests/golden/make_golden.py adjoint256     # 256^2, 2000 steps: target + FD gradients
+
+The adjoint case stores the target field phi_target (the oracle run with the held-out
+coefficients) and FP64 central finite differences (h = 1e-6) of the loss
+||phi(N) - phi_target||^2 with respect to all 16 stream-function coefficients and phi0
+at 8 seeded nodes.
 """
 import os
 import sys
@@ -54,6 +60,58 @@ def make(name):
         np.sqrt(d["err2"] / d["ref2"]), d["max"], d["min"], time.time() - t0))
 
 
+def adjoint_run(case, p, phi0, theta, scale):
+    U, V = case.field(theta, scale)
+    return oracle.State(p, phi0, U, V).run(case.steps).phi
+
+
+def adjoint_fd(case, h=1e-6, nodes=8, seed=20240602):
+    """Central differences of L = sum (phi(N) - phi_target)^2, each as
+    sum (phi+ - phi-)(phi+ + phi- - 2 phi_target) / (2 h) to avoid cancelling L."""
+    p = oracle.Params(nx=case.n, ny=case.n, **case.phys)
+    target = adjoint_run(case, p, case.phi0, case.theta_target, case.scale_target)
+    base = adjoint_run(case, p, case.phi0, case.theta, case.scale)
+
+    def fd(plus, minus):
+        return float(((plus - minus) * (plus + minus - 2.0 * target)).sum() / (2.0 * h))
+
+    g_theta = np.zeros(len(case.theta))
+    for k in range(len(case.theta)):
+        e = np.zeros_like(case.theta)
+        e[k] = h
+        g_theta[k] = fd(adjoint_run(case, p, case.phi0, case.theta + e, case.scale),
+                        adjoint_run(case, p, case.phi0, case.theta - e, case.scale))
+        print("theta", k, g_theta[k], flush=True)
+    rng = np.random.default_rng(seed)
+    near = np.flatnonzero(np.abs(case.phi0.ravel()) < 0.9)
+    idx = np.sort(np.concatenate([rng.choice(near, nodes - 1, replace=False),
+                                  [case.n // 2 * case.n + case.n // 2]]))
+    g_phi = np.zeros(len(idx))
+    for j, i in enumerate(idx):
+        d = np.zeros(case.n * case.n)
+        d[i] = h
+        d = d.reshape(case.n, case.n)
+        g_phi[j] = fd(adjoint_run(case, p, case.phi0 + d, case.theta, case.scale),
+                      adjoint_run(case, p, case.phi0 - d, case.theta, case.scale))
+        print("phi0", i, g_phi[j], flush=True)
+    return target, base, g_theta, idx, g_phi
+
+
+def make_adjoint(n=256, steps=2000):
+    case = workloads.adjoint_case(n, steps)
+    t0 = time.time()
+    target, base, g_theta, idx, g_phi = adjoint_fd(case)
+    out = os.path.join(HERE, "adjoint%d_oracle_%d.npz" % (n, steps))
+    np.savez_compressed(out, steps=steps, h=1e-6, phi_target=target.astype(np.float32),
+                        loss=float(((base - target) ** 2).sum()), grad_theta=g_theta,
+                        phi0_index=idx, grad_phi0=g_phi, threads=oracle.num_threads(),
+                        seconds=time.time() - t0)
+    print(out, "loss=%.6e %.0fs" % (((base - target) ** 2).sum(), time.time() - t0))
+
+
 if __name__ == "__main__":
     for n in sys.argv[1:] or ["vortex2048"]:
-        make(n)
+        if n == "adjoint256":
+            make_adjoint()
+        else:
+            make(n)

@@ -94,7 +94,17 @@ def test_context_calls_reject_null_and_strerror():
     assert L.lbm_ch_moments(None, None, None, None, None, None, None) == lbm.ESTATE
     assert L.lbm_ch_diagnostics(None, None, None, None) == lbm.ESTATE
     assert L.lbm_ch_step_count(None) == -1
+    assert L.lbm_ch_record(None, 1, None, None) == lbm.ESTATE
+    assert L.lbm_ch_adjoint(None, 1, 1, None, None, None, None, None, 0, None) == lbm.ESTATE
     assert L.lbm_ch_destroy(None) == lbm.OK
     for st in (lbm.OK, lbm.EINVAL, lbm.EUNSUPPORTED, lbm.EHIP, lbm.ENONFINITE, lbm.ESTATE):
         assert L.lbm_ch_strerror(st)
     assert L.lbm_ch_strerror(12345) == b"unknown status"
+
+
+def test_adjoint_scratch_size():
+    L = lbm.lib()
+    p = lbm.make_params(96, 40)
+    assert L.lbm_ch_adjoint_scratch_bytes(ctypes.byref(p)) == 8 * 96 * 40 * 4
+    p.tau_g = 0.4
+    assert L.lbm_ch_adjoint_scratch_bytes(ctypes.byref(p)) == 0

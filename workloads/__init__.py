@@ -222,3 +222,66 @@ def rayleigh_taylor_case(nx=256, ny=1024, steps=40000, **kw):
     phys = rt_params(nx=nx, **kw)
     return Workload("rayleigh_taylor%dx%d" % (nx, ny), nx, ny, steps, phys,
                     rayleigh_taylor(nx, ny, phys["width"]))
+
+
+def stream_basis(n, modes):
+    """Velocity of each unit stream-function mode: (modes*modes, 2, n, n) with entry
+    [k*modes + l] = (u, v) of psi = sin(2 pi (k+1) x/n) sin(2 pi (l+1) y/n)."""
+    out = np.zeros((modes * modes, 2, n, n))
+    for k in range(modes):
+        for l in range(modes):
+            c = np.zeros((modes, modes))
+            c[k, l] = 1.0
+            out[k * modes + l] = stream_function_field(n, c)
+    return out
+
+
+def stream_coefficients(modes, seed):
+    """a_kl ~ N(0, 1) / (k^2 + l^2), k, l = 1..modes, flattened row-major."""
+    rng = np.random.default_rng(seed)
+    k = np.arange(1, modes + 1)
+    return (rng.standard_normal((modes, modes)) / (k[:, None] ** 2 + k[None, :] ** 2)).ravel()
+
+
+@dataclasses.dataclass
+class AdjointCase:
+    """Interface-matching problem: phi0 advected for `steps` steps by
+    u = scale * sum_k theta_k B_k (B = stream_basis), loss ||phi(N) - phi_target||^2 with
+    phi_target produced from held-out coefficients.  `scale` is fixed from the initial
+    coefficients (max |u| = umax) and is not a parameter of the loss."""
+    name: str
+    n: int
+    steps: int
+    phys: dict
+    phi0: np.ndarray
+    basis: np.ndarray
+    theta: np.ndarray
+    scale: float
+    theta_target: np.ndarray
+    scale_target: float
+
+    def field(self, theta=None, scale=None):
+        th = self.theta if theta is None else theta
+        sc = self.scale if scale is None else scale
+        uv = sc * np.tensordot(th, self.basis, axes=1)
+        return uv[0], uv[1]
+
+
+def adjoint_case(n=256, steps=2000, modes=4, seed=5, target_seed=6, umax=0.05,
+                 radius_frac=0.25, model=2):
+    """Differentiation workload: 256^2, 2000 steps, 16 seeded Fourier coefficients of the
+    stream function (k, l = 1..4), a circle of radius n/4 at the centre, Model-II at
+    tau_g = 1 with the prescribed-flow parameters of Sec. III."""
+    basis = stream_basis(n, modes)
+
+    def scaled(seed_):
+        th = stream_coefficients(modes, seed_)
+        uv = np.tensordot(th, basis, axes=1)
+        return th, umax / np.abs(uv).max()
+
+    theta, scale = scaled(seed)
+    theta_t, scale_t = scaled(target_seed)
+    phys = dict(PRESCRIBED, model=model)
+    phi0 = circle(n, n, n / 2.0, n / 2.0, radius_frac * n, phys["width"])
+    return AdjointCase("adjoint%d" % n, n, steps, phys, phi0, basis, theta, scale, theta_t,
+                       scale_t)
