@@ -174,6 +174,22 @@ int lbm_ch_save_state(lbm_ch_ctx* ctx, void* dst, size_t bytes, hipStream_t stre
 int lbm_ch_load_state(lbm_ch_ctx* ctx, const void* src, size_t bytes, int64_t step,
                       hipStream_t stream);
 
+/* Tile shape of the step kernels: tx columns (one lane each; 64, 128 or 256) by ty >= 1
+ * rows per thread block (ty is clipped to ny).  The default is chosen at init from the
+ * lattice size (the tallest, then widest, shape that gives at least 1024 blocks); it
+ * changes speed only, never results.  Errors: LBM_CH_EINVAL for other shapes. */
+int lbm_ch_set_tiles(lbm_ch_ctx* ctx, int32_t tx, int32_t ty);
+int lbm_ch_get_tiles(const lbm_ch_ctx* ctx, int32_t* tx, int32_t* ty);
+
+/* Autotuner: time trial_steps >= 1 steps (after one untimed step) for each tile shape
+ * tx in {64, 128, 256} (skipping widths with more than half the lanes idle) and ty in
+ * {2, 4, 8, 16, 32}, keep the fastest, and restore the state and step counter from
+ * `backup`, a caller device buffer of exactly lbm_ch_state_bytes(ctx) bytes.
+ * Synchronises `stream`.  *best_us (may be NULL) receives the chosen shape's time per
+ * step in microseconds. */
+int lbm_ch_autotune(lbm_ch_ctx* ctx, void* backup, size_t backup_bytes, int32_t trial_steps,
+                    hipStream_t stream, float* best_us);
+
 /* Discrete adjoint of the step at tau_g = 1
  * -----------------------------------------
  * With tau_g = 1 the collision of Eq. LB keeps nothing of the incoming populations
@@ -186,7 +202,7 @@ int lbm_ch_load_state(lbm_ch_ctx* ctx, const void* src, size_t bytes, int64_t st
  * on the periodic lattice.  With 16-bit storage the forward map differs from this one
  * by the storage rounding. */
 
-/* Bytes of device scratch lbm_ch_adjoint needs (8 nx ny floats), 0 if p is invalid. */
+/* Bytes of device scratch lbm_ch_adjoint needs (nx*ny floats), 0 if p is invalid. */
 size_t lbm_ch_adjoint_scratch_bytes(const lbm_ch_params* p);
 
 /* Enqueue nsteps steps exactly as lbm_ch_step does, and before each step n write the

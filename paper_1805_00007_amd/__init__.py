@@ -28,6 +28,7 @@ STORE_F32, STORE_F16, STORE_BF16 = 0, 1, 2
 EXPORTS = ("lbm_ch_workspace_bytes", "lbm_ch_init", "lbm_ch_step", "lbm_ch_moments",
            "lbm_ch_diagnostics", "lbm_ch_check_finite", "lbm_ch_step_count",
            "lbm_ch_state_bytes", "lbm_ch_save_state", "lbm_ch_load_state",
+           "lbm_ch_set_tiles", "lbm_ch_get_tiles", "lbm_ch_autotune",
            "lbm_ch_adjoint_scratch_bytes", "lbm_ch_record", "lbm_ch_adjoint", "lbm_ch_destroy",
            "lbm_ch_strerror", "lbm_ch_last_hip_error")
 
@@ -86,6 +87,11 @@ def lib():
         L.lbm_ch_state_bytes.restype = ctypes.c_size_t
         L.lbm_ch_save_state.argtypes = [vp, vp, ctypes.c_size_t, vp]
         L.lbm_ch_load_state.argtypes = [vp, vp, ctypes.c_size_t, i64, vp]
+        L.lbm_ch_set_tiles.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+        L.lbm_ch_get_tiles.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32)]
+        L.lbm_ch_autotune.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int32, vp,
+                                      ctypes.POINTER(ctypes.c_float)]
         L.lbm_ch_adjoint_scratch_bytes.argtypes = [PP]
         L.lbm_ch_adjoint_scratch_bytes.restype = ctypes.c_size_t
         L.lbm_ch_record.argtypes = [vp, i64, vp, vp]
@@ -242,6 +248,28 @@ class Solver:
         _check(lib().lbm_ch_load_state(self.ctx, _ptr(buf), buf.numel(), int(step), self._s()),
                "lbm_ch_load_state")
         return self
+
+    @property
+    def tiles(self):
+        tx, ty = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().lbm_ch_get_tiles(self.ctx, ctypes.byref(tx), ctypes.byref(ty)),
+               "lbm_ch_get_tiles")
+        return tx.value, ty.value
+
+    def set_tiles(self, tx, ty):
+        _check(lib().lbm_ch_set_tiles(self.ctx, int(tx), int(ty)), "lbm_ch_set_tiles")
+        return self
+
+    def autotune(self, trial_steps=20):
+        """Pick the fastest tile shape by timing trial steps; the state is restored.
+        Returns ((tx, ty), microseconds per step)."""
+        t = self.torch
+        n = lib().lbm_ch_state_bytes(self.ctx)
+        backup = t.empty(n, dtype=t.uint8, device=self.device)
+        us = ctypes.c_float()
+        _check(lib().lbm_ch_autotune(self.ctx, _ptr(backup), n, int(trial_steps), self._s(),
+                                     ctypes.byref(us)), "lbm_ch_autotune")
+        return self.tiles, us.value
 
     def adjoint_scratch_bytes(self):
         return lib().lbm_ch_adjoint_scratch_bytes(ctypes.byref(self.params))

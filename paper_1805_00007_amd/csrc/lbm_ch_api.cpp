@@ -112,20 +112,11 @@ static float time_factor(const lbm_ch_ctx* c, int64_t n) {
   return (float)c->tf.back();
 }
 
-// Tile choice: TX columns per block (one lane per column), TY rows per block.  The
-// defaults aim at several blocks per CU on 256 CUs; LBM_CH_TILE=TXxTY overrides.
-static void choose_tiles(lbm_ch_ctx* c) {
+// Tile shape: TX columns per block (one lane per column), TY rows per block.
+static bool valid_tile(int tx, int ty) { return (tx == 64 || tx == 128 || tx == 256) && ty >= 1; }
+
+static void apply_tiles(lbm_ch_ctx* c, int tx, int ty) {
   const int nx = c->p.nx, ny = c->p.ny;
-  int tx = nx >= 256 ? 256 : 128;
-  int ty = 16;
-  const char* env = getenv("LBM_CH_TILE");
-  if (env) {
-    int a = 0, b = 0;
-    if (sscanf(env, "%dx%d", &a, &b) == 2 && (a == 128 || a == 256 || a == 512) && b >= 1) {
-      tx = a;
-      ty = b;
-    }
-  }
   if (ty > ny) ty = ny;
   c->tx = tx;
   c->ty = ty;
@@ -133,6 +124,37 @@ static void choose_tiles(lbm_ch_ctx* c) {
   const int nchunks = (ny + ty - 1) / ty;
   c->nblocks = c->nstrips * nchunks;
   c->xcd_remap = (c->nblocks % 8 == 0) ? 1 : 0;
+}
+
+// Default: the tallest tile (fewest halo rows per row), then the widest, that still
+// gives at least 4 blocks per CU on 256 CUs; small lattices get the most blocks.
+// LBM_CH_TILE=TXxTY overrides; lbm_ch_autotune measures.
+static void choose_tiles(lbm_ch_ctx* c) {
+  const int nx = c->p.nx, ny = c->p.ny;
+  int tx = 64, ty = 4;
+  bool found = false;
+  for (int yy : {16, 8, 4}) {
+    for (int xx : {256, 128, 64}) {
+      if (xx > nx && xx > 64) continue;
+      const long nb = (long)((nx + xx - 1) / xx) * ((ny + yy - 1) / yy);
+      if (nb >= 1024) {
+        tx = xx;
+        ty = yy;
+        found = true;
+        break;
+      }
+    }
+    if (found) break;
+  }
+  const char* env = getenv("LBM_CH_TILE");
+  if (env) {
+    int a = 0, b = 0;
+    if (sscanf(env, "%dx%d", &a, &b) == 2 && valid_tile(a, b)) {
+      tx = a;
+      ty = b;
+    }
+  }
+  apply_tiles(c, tx, ty);
 }
 
 extern "C" {
@@ -257,9 +279,8 @@ int lbm_ch_init(lbm_ch_ctx** out, const lbm_ch_params* p, const lbm_ch_velocity*
   return LBM_CH_OK;
 }
 
-int lbm_ch_step(lbm_ch_ctx* c, int64_t nsteps, hipStream_t stream) {
-  if (!live(c)) return LBM_CH_ESTATE;
-  if (nsteps < 0) return LBM_CH_EINVAL;
+// nsteps steps; with phi_out, phi^n of step n is also written to phi_out + (n - n0) nx ny.
+static int run_steps(lbm_ch_ctx* c, int64_t nsteps, float* phi_out, hipStream_t stream) {
   const bool ns = c->p.velocity_mode == LBM_CH_VEL_NS;
   const bool walls = c->p.walls != 0;
   StepArgs a{};
@@ -300,6 +321,11 @@ int lbm_ch_step(lbm_ch_ctx* c, int64_t nsteps, hipStream_t stream) {
     }
     a.src = c->g[src];
     a.dst = c->g[dst];
+    if (phi_out) {
+      e = launch_phi_field(walls, c->p.storage, c->g[src], c->L.plane, c->p.nx, c->p.ny,
+                           phi_out + (size_t)s * c->p.nx * c->p.ny, stream);
+      if (e != hipSuccess) return hip_fail(e);
+    }
     e = launch_phi_step(c->tx, walls, vmode, c->p.model == 2, c->p.storage, a, c->nblocks,
                         stream);
     if (e != hipSuccess) return hip_fail(e);
@@ -307,6 +333,12 @@ int lbm_ch_step(lbm_ch_ctx* c, int64_t nsteps, hipStream_t stream) {
     c->step += 1;
   }
   return LBM_CH_OK;
+}
+
+int lbm_ch_step(lbm_ch_ctx* c, int64_t nsteps, hipStream_t stream) {
+  if (!live(c)) return LBM_CH_ESTATE;
+  if (nsteps < 0) return LBM_CH_EINVAL;
+  return run_steps(c, nsteps, nullptr, stream);
 }
 
 int lbm_ch_moments(lbm_ch_ctx* c, float* phi, float* mu, float* ux, float* uy, float* p,
@@ -404,9 +436,75 @@ int lbm_ch_load_state(lbm_ch_ctx* c, const void* src, size_t bytes, int64_t step
   return LBM_CH_OK;
 }
 
+int lbm_ch_set_tiles(lbm_ch_ctx* c, int32_t tx, int32_t ty) {
+  if (!live(c)) return LBM_CH_ESTATE;
+  if (!valid_tile(tx, ty)) return LBM_CH_EINVAL;
+  apply_tiles(c, tx, ty);
+  return LBM_CH_OK;
+}
+
+int lbm_ch_get_tiles(const lbm_ch_ctx* c, int32_t* tx, int32_t* ty) {
+  if (!live(c)) return LBM_CH_ESTATE;
+  if (!tx || !ty) return LBM_CH_EINVAL;
+  *tx = c->tx;
+  *ty = c->ty;
+  return LBM_CH_OK;
+}
+
+int lbm_ch_autotune(lbm_ch_ctx* c, void* backup, size_t backup_bytes, int32_t trial_steps,
+                    hipStream_t stream, float* best_us) {
+  if (!live(c)) return LBM_CH_ESTATE;
+  if (!backup || backup_bytes != lbm_ch_state_bytes(c) || trial_steps < 1)
+    return LBM_CH_EINVAL;
+  const int64_t step0 = c->step;
+  const int tx0 = c->tx, ty0 = c->ty;
+  int r = lbm_ch_save_state(c, backup, backup_bytes, stream);
+  if (r != LBM_CH_OK) return r;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  float best = -1.0f;
+  int btx = tx0, bty = ty0;
+  const int nx = c->p.nx, ny = c->p.ny;
+  for (int xx : {64, 128, 256}) {
+    if (e != hipSuccess) break;
+    if (xx > 64 && xx / 2 >= nx) continue;  // more than half the lanes idle
+    for (int yy : {2, 4, 8, 16, 32}) {
+      if (yy > ny && yy > 2) continue;
+      apply_tiles(c, xx, yy);
+      r = lbm_ch_step(c, 1, stream);  // untimed: first launch of this kernel shape
+      if (r == LBM_CH_OK) {
+        e = hipEventRecord(e0, stream);
+        if (e == hipSuccess) r = lbm_ch_step(c, trial_steps, stream);
+        if (e == hipSuccess && r == LBM_CH_OK) e = hipEventRecord(e1, stream);
+        if (e == hipSuccess && r == LBM_CH_OK) e = hipEventSynchronize(e1);
+      }
+      float ms = 0.0f;
+      if (e == hipSuccess && r == LBM_CH_OK) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess || r != LBM_CH_OK) break;
+      if (best < 0.0f || ms < best) {
+        best = ms;
+        btx = xx;
+        bty = yy;
+      }
+    }
+    if (r != LBM_CH_OK) break;
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  // restore the state and the step counter whatever happened above
+  apply_tiles(c, (e == hipSuccess && r == LBM_CH_OK) ? btx : tx0,
+              (e == hipSuccess && r == LBM_CH_OK) ? bty : ty0);
+  const int r2 = lbm_ch_load_state(c, backup, backup_bytes, step0, stream);
+  if (e != hipSuccess) return hip_fail(e);
+  if (r != LBM_CH_OK) return r;
+  if (best_us) *best_us = best * 1000.0f / (float)trial_steps;
+  return r2;
+}
+
 size_t lbm_ch_adjoint_scratch_bytes(const lbm_ch_params* p) {
   if (!valid_params(p)) return 0;
-  return (size_t)8 * p->nx * p->ny * sizeof(float);
+  return (size_t)p->nx * p->ny * sizeof(float);
 }
 
 int lbm_ch_record(lbm_ch_ctx* c, int64_t nsteps, float* phi_traj, hipStream_t stream) {
@@ -414,15 +512,7 @@ int lbm_ch_record(lbm_ch_ctx* c, int64_t nsteps, float* phi_traj, hipStream_t st
   if (nsteps < 0) return LBM_CH_EINVAL;
   if (nsteps == 0) return LBM_CH_OK;
   if (!phi_traj || !aligned4(phi_traj)) return LBM_CH_EINVAL;
-  const size_t nodes = (size_t)c->p.nx * c->p.ny;
-  for (int64_t k = 0; k < nsteps; ++k) {
-    hipError_t e = launch_phi_field(c->p.walls != 0, c->p.storage, c->g[c->cur], c->L.plane,
-                                    c->p.nx, c->p.ny, phi_traj + (size_t)k * nodes, stream);
-    if (e != hipSuccess) return hip_fail(e);
-    const int r = lbm_ch_step(c, 1, stream);
-    if (r != LBM_CH_OK) return r;
-  }
-  return LBM_CH_OK;
+  return run_steps(c, nsteps, phi_traj, stream);
 }
 
 int lbm_ch_adjoint(lbm_ch_ctx* c, int64_t n_end, int64_t nsteps, const float* phi_traj,
@@ -439,12 +529,21 @@ int lbm_ch_adjoint(lbm_ch_ctx* c, int64_t n_end, int64_t nsteps, const float* ph
   if (!scratch || !aligned4(scratch) || scratch_bytes < lbm_ch_adjoint_scratch_bytes(&c->p))
     return LBM_CH_EINVAL;
   const size_t nodes = (size_t)c->p.nx * c->p.ny;
+  // lam and the scratch field alternate as source and destination
+  float* buf[2] = {lam, (float*)scratch};
+  int cur = 0;
   for (int64_t k = nsteps - 1; k >= 0; --k) {
     const int64_t n = n_end - nsteps + k;
     hipError_t e = launch_adjoint_step(
         c->c, (float)c->p.mobility, c->p.nx, c->p.ny, c->vmode, c->ax, c->ay, c->bx, c->by,
-        c->ux, c->uy, time_factor(c, n), phi_traj + (size_t)k * nodes, lam, lam, grad_u,
-        grad_v, (float*)scratch, stream);
+        c->ux, c->uy, time_factor(c, n), phi_traj + (size_t)k * nodes, buf[cur], buf[cur ^ 1],
+        grad_u, grad_v, stream);
+    if (e != hipSuccess) return hip_fail(e);
+    cur ^= 1;
+  }
+  if (cur != 0) {
+    hipError_t e = hipMemcpyAsync(lam, scratch, nodes * sizeof(float), hipMemcpyDeviceToDevice,
+                                  stream);
     if (e != hipSuccess) return hip_fail(e);
   }
   return LBM_CH_OK;

@@ -73,12 +73,12 @@ hipError_t launch_phi_field(bool walls, int storage, const void* g, uint32_t pla
                             int ny, float* phi, hipStream_t s);
 hipError_t launch_mu_field(bool walls, const Coef& c, const float* phi, int nx, int ny,
                            float* mu, hipStream_t s);
-// One reverse step of the tau_g = 1 phi map (periodic); scratch holds 8 fields.
+// One reverse step of the tau_g = 1 phi map (periodic); lam0 must not alias lam1.
 hipError_t launch_adjoint_step(const Coef& c, float mobility, int nx, int ny, int vmode,
                                 const float* ax, const float* ay, const float* bx,
                                 const float* by, const float* ux, const float* uy, float tf,
                                 const float* phi, const float* lam1, float* lam0, float* gu,
-                                float* gv, float* scratch, hipStream_t s);
+                                float* gv, hipStream_t s);
 hipError_t launch_velocity_field(int vmode, int nx, int ny, const float* ax, const float* ay,
                                  const float* bx, const float* by, const float* ux,
                                  const float* uy, float tf, float* u, float* v,

@@ -869,7 +869,7 @@ __global__ void __launch_bounds__(DIAG_THREADS) k_diag_final(const double* __res
 //   mu = f'(phi) - kappa L(phi),  A = sum_i w_i T_{-c_i}[phi s_i(u)],
 //   F = -h(phi) grad mu + K grad(Div(phi u)),  h = phi^2 / rho(phi),
 // with L, grad, Div the isotropic stencils (L symmetric, grad antisymmetric) and
-// (T_c psi)(x) = psi(x + c).  Given lam' = dL/dphi' the passes below form
+// (T_c psi)(x) = psi(x + c).  Given lam' = dL/dphi' the kernel below forms
 //   lam = dL/dphi = lam' + sum_i w_i s_i(u) T_{c_i} lam' - h'(phi) grad mu . lamF
 //         + f''(phi) lamMu - kappa L(lamMu) + u . lamQ,
 //   lamF = grad(lam')/2,  lamMu = M L(lam') + Div(h lamF),
@@ -879,10 +879,9 @@ __global__ void __launch_bounds__(DIAG_THREADS) k_diag_final(const double* __res
 struct AdjArgs {
   const float* phi;   // forward phi at the start of the step
   const float* lam1;  // dL/dphi' (after the step)
-  float* lam0;        // dL/dphi (output)
+  float* lam0;        // dL/dphi (output; must not alias lam1)
   float* gu;          // += tf dL/du (base field); may be null
   float* gv;
-  float* s;           // scratch: 8 fields of nx*ny floats
   int nx, ny;
   Coef c;
   float mob;          // M
@@ -901,112 +900,111 @@ __device__ __forceinline__ float d2bulk(const Coef& c, float p) {
   const float a = p - c.phia, b = p - c.phib, s = 2.0f * p - c.phia - c.phib;
   return c.beta2 * (b * s + a * s + 2.0f * a * b);
 }
-__device__ __forceinline__ void adj_vel(const AdjArgs& a, int x, int y, float& u, float& v) {
+__device__ __forceinline__ int wrap(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+// One block per ATW x ATH output tile.  Every quantity is formed in LDS on the region
+// its consumers need: lam' with a halo of 3, phi, lamF and h lamF with 2, mu, lamMu and
+// lamD with 1, so one launch does a whole reverse step.
+constexpr int ATW = 32, ATH = 8;
+__global__ void __launch_bounds__(ATW * ATH) k_adjoint(const AdjArgs a) {
+  constexpr int L3W = ATW + 6, L3H = ATH + 6;
+  constexpr int P2W = ATW + 4, P2H = ATH + 4;
+  constexpr int Q1W = ATW + 2, Q1H = ATH + 2;
+  constexpr int NT = ATW * ATH;
+  __shared__ float sl[L3H][L3W];
+  __shared__ float sp[P2H][P2W];
+  __shared__ float slfx[P2H][P2W], slfy[P2H][P2W], swfx[P2H][P2W], swfy[P2H][P2W];
+  __shared__ float smu[Q1H][Q1W], slmu[Q1H][Q1W], sld[Q1H][Q1W];
+  const Coef& c = a.c;
+  const int nx = a.nx, ny = a.ny;
+  const int t = threadIdx.x;
+  const int x0 = blockIdx.x * ATW, y0 = blockIdx.y * ATH;
+  for (int i = t; i < L3H * L3W; i += NT) {
+    const int r = i / L3W, cc = i - r * L3W;
+    sl[r][cc] = a.lam1[(uint32_t)wrap(y0 - 3 + r, ny) * nx + wrap(x0 - 3 + cc, nx)];
+  }
+  for (int i = t; i < P2H * P2W; i += NT) {
+    const int r = i / P2W, cc = i - r * P2W;
+    sp[r][cc] = a.phi[(uint32_t)wrap(y0 - 2 + r, ny) * nx + wrap(x0 - 2 + cc, nx)];
+  }
+  __syncthreads();
+  // lamF = grad(lam')/2 and h lamF on the halo-2 region (sl is offset by one more)
+  for (int i = t; i < P2H * P2W; i += NT) {
+    const int r = i / P2W, cc = i - r * P2W;
+    const float lfx = 0.5f * ddx(sl[r], sl[r + 1], sl[r + 2], cc + 1);
+    const float lfy = 0.5f * ddy(sl[r], sl[r + 1], sl[r + 2], cc + 1);
+    float dh;
+    const float h = adj_h(c, sp[r][cc], dh);
+    slfx[r][cc] = lfx;
+    slfy[r][cc] = lfy;
+    swfx[r][cc] = h * lfx;
+    swfy[r][cc] = h * lfy;
+  }
+  // mu (Eq. mu) on the halo-1 region
+  for (int i = t; i < Q1H * Q1W; i += NT) {
+    const int r = i / Q1W, cc = i - r * Q1W;
+    smu[r][cc] = mu_bulk(c, sp[r + 1][cc + 1]) - c.kappa * lap9(sp[r], sp[r + 1], sp[r + 2], cc + 1);
+  }
+  __syncthreads();
+  // lamMu = M lap(lam') + div(h lamF), lamD = -K div(lamF) on the halo-1 region
+  for (int i = t; i < Q1H * Q1W; i += NT) {
+    const int r = i / Q1W, cc = i - r * Q1W;
+    slmu[r][cc] = a.mob * lap9(sl[r + 1], sl[r + 2], sl[r + 3], cc + 2) +
+                  ddx(swfx[r], swfx[r + 1], swfx[r + 2], cc + 1) +
+                  ddy(swfy[r], swfy[r + 1], swfy[r + 2], cc + 1);
+    if (c.k2 != 0.0f)
+      sld[r][cc] = -c.k2 * (ddx(slfx[r], slfx[r + 1], slfx[r + 2], cc + 1) +
+                            ddy(slfy[r], slfy[r + 1], slfy[r + 2], cc + 1));
+  }
+  __syncthreads();
+  const int ty = t / ATW, tx = t - ty * ATW;
+  const int x = x0 + tx, y = y0 + ty;
+  if (x >= nx || y >= ny) return;
+  const uint32_t k = (uint32_t)y * nx + x;
+  const float phi = sp[ty + 2][tx + 2];
+  float u, v;
   if (a.vmode == VEL_SEP) {
     u = a.tf * a.ax[x] * a.ay[y];
     v = a.tf * a.bx[x] * a.by[y];
   } else {
-    u = a.ux ? a.tf * a.ux[(uint32_t)y * a.nx + x] : 0.f;
-    v = a.uy ? a.tf * a.uy[(uint32_t)y * a.nx + x] : 0.f;
+    u = a.tf * a.ux[k];
+    v = a.tf * a.uy[k];
   }
-}
-// 3x3 neighbourhood of a periodic field
-__device__ __forceinline__ void nb3(const float* f, int nx, int ny, int x, int y, float v[3][3]) {
-#pragma unroll
-  for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-    for (int dx = -1; dx <= 1; ++dx) v[dy + 1][dx + 1] = field_at<false>(f, nx, ny, x + dx, y + dy);
-}
-
-// scratch fields
-enum { AS_MU = 0, AS_LFX, AS_LFY, AS_WFX, AS_WFY, AS_P1, AS_LMU, AS_LD };
-
-__global__ void __launch_bounds__(256) k_adj_a(const AdjArgs a) {  // mu
-  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
-  if (x >= a.nx) return;
-  float v[3][3];
-  nb3(a.phi, a.nx, a.ny, x, y, v);
-  const uint32_t n = (uint32_t)a.nx * a.ny, k = (uint32_t)y * a.nx + x;
-  a.s[AS_MU * n + k] = mu_bulk(a.c, v[1][1]) - a.c.kappa * lap9(v[0], v[1], v[2], 1);
-}
-
-__global__ void __launch_bounds__(256) k_adj_b(const AdjArgs a) {
-  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
-  if (x >= a.nx) return;
-  const uint32_t n = (uint32_t)a.nx * a.ny, k = (uint32_t)y * a.nx + x;
-  float L[3][3], M[3][3];
-  nb3(a.lam1, a.nx, a.ny, x, y, L);
-  nb3(a.s + AS_MU * n, a.nx, a.ny, x, y, M);
-  const float phi = a.phi[k];
-  float u, v;
-  adj_vel(a, x, y, u, v);
-  const float lfx = 0.5f * ddx(L[0], L[1], L[2], 1), lfy = 0.5f * ddy(L[0], L[1], L[2], 1);
-  float dh;
-  const float h = adj_h(a.c, phi, dh);
   const float usq = u * u + v * v;
-  float p1 = L[1][1], lu = 0.f, lv = 0.f;
+  // advection part: sum_i w_i s_i(u) lam'(x + c_i), and its u-derivative times phi
+  float lam = sl[ty + 3][tx + 3], lu = 0.f, lv = 0.f;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const float cu = CX[i] * u + CY[i] * v;
     const float si = 3.0f * cu + 4.5f * cu * cu - 1.5f * usq;
-    const float lam = L[1 + CY[i]][1 + CX[i]];  // lam'(x + c_i)
-    p1 += WT[i] * si * lam;
-    // d s_i / du = 3 c_i + 9 (c_i.u) c_i - 3 u
-    lu += WT[i] * phi * (3.0f * CX[i] + 9.0f * cu * CX[i] - 3.0f * u) * lam;
-    lv += WT[i] * phi * (3.0f * CY[i] + 9.0f * cu * CY[i] - 3.0f * v) * lam;
+    const float l = sl[ty + 3 + (int)CY[i]][tx + 3 + (int)CX[i]];
+    lam += WT[i] * si * l;
+    lu += WT[i] * (3.0f * CX[i] + 9.0f * cu * CX[i] - 3.0f * u) * l;
+    lv += WT[i] * (3.0f * CY[i] + 9.0f * cu * CY[i] - 3.0f * v) * l;
   }
-  p1 -= dh * (lfx * ddx(M[0], M[1], M[2], 1) + lfy * ddy(M[0], M[1], M[2], 1));
-  a.s[AS_LFX * n + k] = lfx;
-  a.s[AS_LFY * n + k] = lfy;
-  a.s[AS_WFX * n + k] = h * lfx;
-  a.s[AS_WFY * n + k] = h * lfy;
-  a.s[AS_P1 * n + k] = p1;
-  if (a.gu) {  // partial dL/du from A; the lamQ part is added in pass D
-    a.gu[k] += a.tf * lu;
-    a.gv[k] += a.tf * lv;
-  }
-}
-
-__global__ void __launch_bounds__(256) k_adj_c(const AdjArgs a) {
-  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
-  if (x >= a.nx) return;
-  const uint32_t n = (uint32_t)a.nx * a.ny, k = (uint32_t)y * a.nx + x;
-  float L[3][3], WX[3][3], WY[3][3];
-  nb3(a.lam1, a.nx, a.ny, x, y, L);
-  nb3(a.s + AS_WFX * n, a.nx, a.ny, x, y, WX);
-  nb3(a.s + AS_WFY * n, a.nx, a.ny, x, y, WY);
-  a.s[AS_LMU * n + k] = a.mob * lap9(L[0], L[1], L[2], 1) + ddx(WX[0], WX[1], WX[2], 1) +
-                        ddy(WY[0], WY[1], WY[2], 1);
-  if (a.c.k2 != 0.0f) {
-    float FX[3][3], FY[3][3];
-    nb3(a.s + AS_LFX * n, a.nx, a.ny, x, y, FX);
-    nb3(a.s + AS_LFY * n, a.nx, a.ny, x, y, FY);
-    a.s[AS_LD * n + k] = -a.c.k2 * (ddx(FX[0], FX[1], FX[2], 1) + ddy(FY[0], FY[1], FY[2], 1));
-  }
-}
-
-__global__ void __launch_bounds__(256) k_adj_d(const AdjArgs a) {
-  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
-  if (x >= a.nx) return;
-  const uint32_t n = (uint32_t)a.nx * a.ny, k = (uint32_t)y * a.nx + x;
-  float LM[3][3];
-  nb3(a.s + AS_LMU * n, a.nx, a.ny, x, y, LM);
-  const float phi = a.phi[k];
-  float lam = a.s[AS_P1 * n + k] + d2bulk(a.c, phi) * LM[1][1] -
-              a.c.kappa * lap9(LM[0], LM[1], LM[2], 1);
-  if (a.c.k2 != 0.0f) {
-    float LD[3][3];
-    nb3(a.s + AS_LD * n, a.nx, a.ny, x, y, LD);
-    const float lqx = -ddx(LD[0], LD[1], LD[2], 1), lqy = -ddy(LD[0], LD[1], LD[2], 1);
-    float u, v;
-    adj_vel(a, x, y, u, v);
+  float dh;
+  adj_h(c, phi, dh);
+  const float mux = ddx(smu[ty], smu[ty + 1], smu[ty + 2], tx + 1);
+  const float muy = ddy(smu[ty], smu[ty + 1], smu[ty + 2], tx + 1);
+  lam -= dh * (slfx[ty + 2][tx + 2] * mux + slfy[ty + 2][tx + 2] * muy);
+  lam += d2bulk(c, phi) * slmu[ty + 1][tx + 1] -
+         c.kappa * lap9(slmu[ty], slmu[ty + 1], slmu[ty + 2], tx + 1);
+  float gx = lu, gy = lv;
+  if (c.k2 != 0.0f) {  // lamQ = -grad(lamD); q = phi u
+    const float lqx = -ddx(sld[ty], sld[ty + 1], sld[ty + 2], tx + 1);
+    const float lqy = -ddy(sld[ty], sld[ty + 1], sld[ty + 2], tx + 1);
     lam += u * lqx + v * lqy;
-    if (a.gu) {
-      a.gu[k] += a.tf * phi * lqx;
-      a.gv[k] += a.tf * phi * lqy;
-    }
+    gx += lqx;
+    gy += lqy;
   }
   a.lam0[k] = lam;
+  if (a.gu) {
+    a.gu[k] += a.tf * phi * gx;
+    a.gv[k] += a.tf * phi * gy;
+  }
 }
 
 template <int TX, bool WALLS, int VMODE, int ST>
@@ -1031,15 +1029,15 @@ template <int ST>
 hipError_t phi_step_t(int tx, bool walls, int vmode, bool model2, const StepArgs& a, int nb,
                       hipStream_t s) {
   switch (tx) {
+    case 64:
+      return walls ? phi_step_v<64, true, ST>(vmode, model2, a, nb, s)
+                   : phi_step_v<64, false, ST>(vmode, model2, a, nb, s);
     case 128:
       return walls ? phi_step_v<128, true, ST>(vmode, model2, a, nb, s)
                    : phi_step_v<128, false, ST>(vmode, model2, a, nb, s);
     case 256:
       return walls ? phi_step_v<256, true, ST>(vmode, model2, a, nb, s)
                    : phi_step_v<256, false, ST>(vmode, model2, a, nb, s);
-    case 512:
-      return walls ? phi_step_v<512, true, ST>(vmode, model2, a, nb, s)
-                   : phi_step_v<512, false, ST>(vmode, model2, a, nb, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1053,9 +1051,9 @@ void ns_step_l(bool walls, const NsArgs& a, int nb, hipStream_t s) {
 template <int ST>
 hipError_t ns_step_t(int tx, bool walls, const NsArgs& a, int nb, hipStream_t s) {
   switch (tx) {
+    case 64: ns_step_l<64, ST>(walls, a, nb, s); break;
     case 128: ns_step_l<128, ST>(walls, a, nb, s); break;
     case 256: ns_step_l<256, ST>(walls, a, nb, s); break;
-    case 512: ns_step_l<512, ST>(walls, a, nb, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1141,16 +1139,13 @@ hipError_t launch_adjoint_step(const Coef& c, float mobility, int nx, int ny, in
                                 const float* ax, const float* ay, const float* bx,
                                 const float* by, const float* ux, const float* uy, float tf,
                                 const float* phi, const float* lam1, float* lam0, float* gu,
-                                float* gv, float* scratch, hipStream_t s) {
+                                float* gv, hipStream_t s) {
   AdjArgs a{};
-  a.phi = phi; a.lam1 = lam1; a.lam0 = lam0; a.gu = gu; a.gv = gv; a.s = scratch;
+  a.phi = phi; a.lam1 = lam1; a.lam0 = lam0; a.gu = gu; a.gv = gv;
   a.nx = nx; a.ny = ny; a.c = c; a.mob = mobility; a.vmode = vmode;
   a.ax = ax; a.ay = ay; a.bx = bx; a.by = by; a.ux = ux; a.uy = uy; a.tf = tf;
-  const dim3 grid((nx + 255) / 256, ny);
-  hipLaunchKernelGGL(k_adj_a, grid, dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_adj_b, grid, dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_adj_c, grid, dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_adj_d, grid, dim3(256), 0, s, a);
+  const dim3 grid((nx + ATW - 1) / ATW, (ny + ATH - 1) / ATH);
+  hipLaunchKernelGGL(k_adjoint, grid, dim3(ATW * ATH), 0, s, a);
   return hipGetLastError();
 }
 

@@ -105,6 +105,6 @@ def test_context_calls_reject_null_and_strerror():
 def test_adjoint_scratch_size():
     L = lbm.lib()
     p = lbm.make_params(96, 40)
-    assert L.lbm_ch_adjoint_scratch_bytes(ctypes.byref(p)) == 8 * 96 * 40 * 4
+    assert L.lbm_ch_adjoint_scratch_bytes(ctypes.byref(p)) == 96 * 40 * 4
     p.tau_g = 0.4
     assert L.lbm_ch_adjoint_scratch_bytes(ctypes.byref(p)) == 0

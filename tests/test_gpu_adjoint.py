@@ -190,7 +190,7 @@ def test_adjoint_rejects_unsupported(lbm):
     dev = torch.device("cuda:0")
     traj = torch.empty((1, n, n), dtype=torch.float32, device=dev)
     lam = torch.zeros((n, n), dtype=torch.float32, device=dev)
-    scratch = torch.empty(8 * n * n * 4, dtype=torch.uint8, device=dev)
+    scratch = torch.empty(n * n * 4, dtype=torch.uint8, device=dev)
     L = lbm.lib()
     P = ctypes.c_void_p
     for kw in (dict(tau_g=0.8), dict(walls=1), dict(ns=True, tau_f=0.8, gravity=1e-5)):

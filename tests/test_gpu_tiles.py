@@ -1,0 +1,71 @@
+"""Tile shapes and the autotuner: results never depend on the tile shape, and the
+autotuner leaves the state and step counter as it found them."""
+import numpy as np
+import pytest
+
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import paper_1805_00007_amd as lbm
+    lbm.lib()
+    return lbm
+
+
+def _run(lbm, w, steps, tiles=None, walls=0, **kw):
+    s = lbm.solver_for(w, walls=walls, **kw)
+    if tiles is not None:
+        s.set_tiles(*tiles)
+    s.step(steps)
+    phi = s.phi().cpu().numpy()
+    s.close()
+    return phi
+
+
+@pytest.mark.parametrize("walls", [0, 1])
+def test_results_do_not_depend_on_tiles(lbm, walls):
+    w = workloads.vortex(200, period=400, steps=60)
+    w.ny = 136
+    w.phi0 = w.phi0[:136]
+    w.velocity = dict(w.velocity, ay=w.velocity["ay"][:136], by=w.velocity["by"][:136])
+    ref = _run(lbm, w, 60, (256, 16), walls=walls)
+    for tiles in ((64, 1), (64, 2), (128, 5), (128, 32), (256, 3), (64, 200)):
+        print("tiles", tiles, flush=True)
+        assert np.array_equal(_run(lbm, w, 60, tiles, walls=walls), ref), tiles
+
+
+def test_ns_results_do_not_depend_on_tiles(lbm):
+    w = workloads.rayleigh_taylor_case(64, 128, steps=80)
+    ref = _run(lbm, w, 80, (64, 16))
+    for tiles in ((128, 3), (64, 1)):
+        assert np.array_equal(_run(lbm, w, 80, tiles), ref), tiles
+
+
+def test_set_tiles_rejects_invalid(lbm):
+    w = workloads.translation(64, steps=10)
+    s = lbm.solver_for(w)
+    for bad in ((512, 16), (32, 4), (128, 0)):
+        with pytest.raises(lbm.LbmChError):
+            s.set_tiles(*bad)
+    s.set_tiles(64, 1000)
+    assert s.tiles == (64, 64)  # ty clipped to ny
+    s.close()
+
+
+def test_autotune_restores_state(lbm):
+    w = workloads.vortex(256, period=2000, steps=400)
+    s = lbm.solver_for(w)
+    s.step(30)
+    tiles, us = s.autotune(trial_steps=5)
+    print("autotune 256^2 ->", tiles, "%.2f us/step" % us)
+    assert s.step_count == 30
+    assert tiles[0] in (64, 128, 256) and tiles[1] in (2, 4, 8, 16, 32) and us > 0
+    s.step(40)
+    got = s.phi().cpu().numpy()
+    s.close()
+    ref = _run(lbm, w, 70)
+    assert np.array_equal(got, ref)
