@@ -189,6 +189,62 @@ def adjoint_leg(lbm, torch, reps=3):
             "reference": "FP64 oracle central differences, h = %g" % float(g["h"])}
 
 
+def batch_leg(lbm, torch, steps=5000, plain_steps=200, check_steps=100):
+    """64 lattices of uneven sizes (sides 64-512, seeded): the batched persistent kernel
+    with autotuned tiles, `steps` steps captured in one hipGraph and launched once,
+    against the plain form (one lbm_ch_step launch per lattice per step) on the same GPU;
+    both give bitwise the same fields."""
+    import numpy as np
+    import workloads
+    ws = workloads.batch_case(steps=steps)
+    nodes = sum(w.nx * w.ny for w in ws)
+    sol = [lbm.solver_for(w) for w in ws]
+    ref = [lbm.solver_for(w) for w in ws]
+    b = lbm.Batch(sol)
+    tiles, tuned_us = b.autotune(5)
+    b.step(check_steps, graph=True)
+    for s in ref:
+        s.step(check_steps)
+    same = all(np.array_equal(x.phi().cpu().numpy(), y.phi().cpu().numpy())
+               for x, y in zip(sol, ref))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(plain_steps):
+        for s in ref:
+            s.step(1)
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / plain_steps
+    for s in ref:
+        s.close()
+    b.step(steps, graph=True)  # captures and instantiates the graph (untimed)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(b.stream)
+    t0 = time.perf_counter()
+    b.step(steps, graph=True)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_batch = e0.elapsed_time(e1) * 1e-3 / steps
+    nonfinite = sum(s.diagnostics()["nonfinite"] for s in sol)
+    b.close()
+    for s in sol:
+        s.close()
+    return {"workload": "batch64: 64 lattices, sides %s, %d nodes, steady random stream "
+                        "functions, Model-II, FP32" % (sorted({w.nx for w in ws}), nodes),
+            "steps_in_one_graph_launch": steps,
+            "batched_MLUPS": round(nodes / t_batch / 1e6, 1),
+            "batched_us_per_step": round(t_batch * 1e6, 2),
+            "graph_launch_wall_s": round(wall, 4),
+            "plain_MLUPS": round(nodes / t_plain / 1e6, 1),
+            "plain_us_per_step": round(t_plain * 1e6, 2),
+            "speedup_vs_plain": round(t_plain / t_batch, 2),
+            "autotuned_tiles": {"tx": tiles[0], "ty": tiles[1], "trial_us": round(tuned_us, 2)},
+            "bitwise_equal_to_plain_after_%d" % check_steps: bool(same),
+            "nonfinite": int(nonfinite),
+            "bytes_per_lu": 80}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -296,6 +352,7 @@ def main():
         out["storage_variants"] = {name: storage_variant(lbm, torch, st, args.steps)
                                    for name, st in (("f16", 1), ("bf16", 2))}
         out["adjoint"] = adjoint_leg(lbm, torch)
+        out["batched"] = batch_leg(lbm, torch)
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(workloads.metric2048(steps=args.cpu_steps),
                                            args.cpu_steps)

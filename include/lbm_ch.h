@@ -228,6 +228,55 @@ int lbm_ch_adjoint(lbm_ch_ctx* ctx, int64_t n_end, int64_t nsteps, const float* 
                    float* lam, float* grad_u, float* grad_v, void* scratch,
                    size_t scratch_bytes, hipStream_t stream);
 
+/* Batched stepping
+ * ----------------
+ * A batch advances many independent lattices (contexts created by lbm_ch_init) in one
+ * launch per step: the tiles of every lattice form one work list that a persistent
+ * grid of workgroups walks, each XCD taking a contiguous range of it.  Results are
+ * bitwise those of lbm_ch_step on each context.  Lattices with different tile widths
+ * or kernel variants (velocity mode, Model-I/II) form groups of one launch each.
+ * Supported: periodic lattices, LBM_CH_STORE_F32, prescribed velocity without a
+ * time-factor table.  The contexts must outlive the batch; stepping a context on its
+ * own between batch steps is allowed. */
+typedef struct lbm_ch_batch lbm_ch_batch; /* opaque, host-side */
+
+/* Device bytes of the batch's instance tables for n lattices (0 if n < 1). */
+size_t lbm_ch_batch_workspace_bytes(int32_t n);
+
+/* Create a batch over ctxs[0..n) (distinct, live).  workspace: caller device memory of
+ * lbm_ch_batch_workspace_bytes(n) bytes, 256-byte aligned, kept until destroy.  No
+ * device work is enqueued.  Errors: LBM_CH_EINVAL (sizes, NULL, duplicates),
+ * LBM_CH_ESTATE (a dead context), LBM_CH_EUNSUPPORTED (walls, 16-bit storage, NS
+ * velocity or a time-factor table). */
+int lbm_ch_batch_create(lbm_ch_batch** out, lbm_ch_ctx* const* ctxs, int32_t n,
+                        void* workspace, size_t workspace_bytes);
+
+/* Tile shape of the batch: tx in {64, 128, 256} for every lattice, or 0 to give each
+ * lattice the widest of those that leaves the fewest idle lanes; ty >= 1 rows (clipped
+ * to each ny).  Default (64, 16). */
+int lbm_ch_batch_set_tiles(lbm_ch_batch* b, int32_t tx, int32_t ty);
+int lbm_ch_batch_get_tiles(const lbm_ch_batch* b, int32_t* tx, int32_t* ty);
+
+/* Enqueue nsteps steps of every lattice on `stream`.  use_graph != 0: the nsteps
+ * launches are captured once into a hipGraph (cached for this nsteps) and the graph is
+ * launched once.  When the instance tables must be (re)uploaded (first call, new tiles,
+ * a context stepped on its own) the call first synchronises `stream`. */
+int lbm_ch_batch_step(lbm_ch_batch* b, int64_t nsteps, int32_t use_graph, hipStream_t stream);
+
+/* Bytes of a backup of every lattice's state (each rounded to 256 bytes). */
+size_t lbm_ch_batch_state_bytes(const lbm_ch_batch* b);
+
+/* Autotuner: time trial_steps >= 1 batch steps (after one untimed step) for every tile
+ * policy tx in {0, 64, 128, 256} and ty in {4, 8, 16, 32}, keep the fastest, and
+ * restore every lattice's state and step counter from `backup` (device memory of
+ * exactly lbm_ch_batch_state_bytes bytes, 256-byte aligned).  Synchronises `stream`.
+ * *best_us (may be NULL): the chosen shape's time per batch step in microseconds. */
+int lbm_ch_batch_autotune(lbm_ch_batch* b, void* backup, size_t backup_bytes,
+                          int32_t trial_steps, hipStream_t stream, float* best_us);
+
+/* Release the batch (its cached graphs and capture stream); the contexts stay. */
+int lbm_ch_batch_destroy(lbm_ch_batch* b);
+
 /* Release the context (host memory only).  NULL is accepted. */
 int lbm_ch_destroy(lbm_ch_ctx* ctx);
 

@@ -29,7 +29,10 @@ EXPORTS = ("lbm_ch_workspace_bytes", "lbm_ch_init", "lbm_ch_step", "lbm_ch_momen
            "lbm_ch_diagnostics", "lbm_ch_check_finite", "lbm_ch_step_count",
            "lbm_ch_state_bytes", "lbm_ch_save_state", "lbm_ch_load_state",
            "lbm_ch_set_tiles", "lbm_ch_get_tiles", "lbm_ch_autotune",
-           "lbm_ch_adjoint_scratch_bytes", "lbm_ch_record", "lbm_ch_adjoint", "lbm_ch_destroy",
+           "lbm_ch_adjoint_scratch_bytes", "lbm_ch_record", "lbm_ch_adjoint",
+           "lbm_ch_batch_workspace_bytes", "lbm_ch_batch_create", "lbm_ch_batch_set_tiles",
+           "lbm_ch_batch_get_tiles", "lbm_ch_batch_step", "lbm_ch_batch_state_bytes",
+           "lbm_ch_batch_autotune", "lbm_ch_batch_destroy", "lbm_ch_destroy",
            "lbm_ch_strerror", "lbm_ch_last_hip_error")
 
 
@@ -96,6 +99,19 @@ def lib():
         L.lbm_ch_adjoint_scratch_bytes.restype = ctypes.c_size_t
         L.lbm_ch_record.argtypes = [vp, i64, vp, vp]
         L.lbm_ch_adjoint.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.lbm_ch_batch_workspace_bytes.argtypes = [ctypes.c_int32]
+        L.lbm_ch_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.lbm_ch_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int32,
+                                          vp, ctypes.c_size_t]
+        L.lbm_ch_batch_set_tiles.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+        L.lbm_ch_batch_get_tiles.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
+                                             ctypes.POINTER(ctypes.c_int32)]
+        L.lbm_ch_batch_step.argtypes = [vp, i64, ctypes.c_int32, vp]
+        L.lbm_ch_batch_state_bytes.argtypes = [vp]
+        L.lbm_ch_batch_state_bytes.restype = ctypes.c_size_t
+        L.lbm_ch_batch_autotune.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int32, vp,
+                                            ctypes.POINTER(ctypes.c_float)]
+        L.lbm_ch_batch_destroy.argtypes = [vp]
         L.lbm_ch_destroy.argtypes = [vp]
         L.lbm_ch_strerror.argtypes = [i32]
         L.lbm_ch_strerror.restype = ctypes.c_char_p
@@ -305,6 +321,69 @@ class Solver:
             self.stream.synchronize()
             lib().lbm_ch_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many solvers stepped together: ``Batch([solver, ...])``.  The solvers keep
+    working on their own (moments, diagnostics, save/load); ``step`` advances all of
+    them with the batched kernel, optionally through one captured hipGraph."""
+
+    def __init__(self, solvers, stream=None):
+        import torch
+        self.torch = torch
+        self.solvers = list(solvers)
+        n = len(self.solvers)
+        self.device = self.solvers[0].device
+        self.stream = stream if stream is not None else self.solvers[0].stream
+        nbytes = lib().lbm_ch_batch_workspace_bytes(n)
+        self.workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device)
+        arr = (ctypes.c_void_p * n)(*[s.ctx.value for s in self.solvers])
+        b = ctypes.c_void_p()
+        _check(lib().lbm_ch_batch_create(ctypes.byref(b), arr, n,
+                                         ctypes.c_void_p(self.workspace.data_ptr()), nbytes),
+               "lbm_ch_batch_create")
+        self.b = b
+
+    def _s(self):
+        return ctypes.c_void_p(self.stream.cuda_stream)
+
+    def step(self, n=1, graph=False):
+        _check(lib().lbm_ch_batch_step(self.b, int(n), 1 if graph else 0, self._s()),
+               "lbm_ch_batch_step")
+        return self
+
+    @property
+    def tiles(self):
+        tx, ty = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().lbm_ch_batch_get_tiles(self.b, ctypes.byref(tx), ctypes.byref(ty)),
+               "lbm_ch_batch_get_tiles")
+        return tx.value, ty.value
+
+    def set_tiles(self, tx, ty):
+        _check(lib().lbm_ch_batch_set_tiles(self.b, int(tx), int(ty)), "lbm_ch_batch_set_tiles")
+        return self
+
+    def autotune(self, trial_steps=5):
+        t = self.torch
+        n = lib().lbm_ch_batch_state_bytes(self.b)
+        backup = t.empty(n, dtype=t.uint8, device=self.device)
+        us = ctypes.c_float()
+        _check(lib().lbm_ch_batch_autotune(self.b, _ptr(backup), n, int(trial_steps),
+                                           self._s(), ctypes.byref(us)),
+               "lbm_ch_batch_autotune")
+        return self.tiles, us.value
+
+    def close(self):
+        if getattr(self, "b", None):
+            self.stream.synchronize()
+            lib().lbm_ch_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

@@ -8,6 +8,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -490,8 +491,8 @@ int lbm_ch_autotune(lbm_ch_ctx* c, void* backup, size_t backup_bytes, int32_t tr
     }
     if (r != LBM_CH_OK) break;
   }
-  if (e0) hipEventDestroy(e0);
-  if (e1) hipEventDestroy(e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   // restore the state and the step counter whatever happened above
   apply_tiles(c, (e == hipSuccess && r == LBM_CH_OK) ? btx : tx0,
               (e == hipSuccess && r == LBM_CH_OK) ? bty : ty0);
@@ -570,5 +571,363 @@ const char* lbm_ch_strerror(int status) {
 }
 
 int lbm_ch_last_hip_error(void) { return g_last_hip; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------
+// Batched stepping of many lattices.
+namespace {
+
+struct BatchGroup {
+  int tx, vmode;
+  bool model2;
+  int first, count;  // range in the instance order
+  int start_off;     // offset of this group's start[] in the device start array
+  int total, grid;
+};
+
+struct BatchExec {
+  hipGraphExec_t exec;
+  int64_t steps;
+  int phase;
+};
+
+constexpr uint32_t BATCH_MAGIC = 0x4c424d42u;
+
+}  // namespace
+
+struct lbm_ch_batch {
+  std::vector<lbm_ch_ctx*> ctx;
+  StepArgs* dargs;
+  int* dstart;
+  std::vector<StepArgs> hargs;
+  std::vector<int> hstart;
+  std::vector<int> built_cur;  // ctx->cur of each instance when the tables were built
+  std::vector<BatchGroup> groups;
+  int tx_policy;  // 0: per-instance width, else one width for all
+  int ty;
+  int phase;      // steps taken since the tables were built, mod 2
+  bool built;
+  int cus;
+  hipStream_t cap;
+  std::vector<BatchExec> execs;
+  uint32_t magic;
+};
+
+static bool batch_live(const lbm_ch_batch* b) { return b && b->magic == BATCH_MAGIC; }
+
+static size_t batch_table_bytes(int32_t n) {
+  return align_up((size_t)n * sizeof(StepArgs)) + align_up((size_t)(2 * n + 1) * sizeof(int));
+}
+
+// Width of instance tiles: the policy's width, or (policy 0) the widest of 256, 128, 64
+// that leaves the fewest idle lanes in the last strip.
+static int batch_tx(int policy, int nx) {
+  if (policy) return policy;
+  int best = 64, idle = 1 << 30;
+  for (int tx : {256, 128, 64}) {
+    const int w = (nx + tx - 1) / tx * tx - nx;
+    if (w < idle) {
+      idle = w;
+      best = tx;
+    }
+  }
+  return best;
+}
+
+static void batch_drop_graphs(lbm_ch_batch* b) {
+  for (auto& x : b->execs) (void)hipGraphExecDestroy(x.exec);
+  b->execs.clear();
+}
+
+// Rebuild the instance tables (grouped by kernel variant) and upload them on `stream`.
+static int batch_build(lbm_ch_batch* b, hipStream_t stream) {
+  const int n = (int)b->ctx.size();
+  // the host tables may still be read by an earlier upload
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e);
+  batch_drop_graphs(b);
+  std::vector<int> order(n), txs(n);
+  for (int i = 0; i < n; ++i) {
+    order[i] = i;
+    txs[i] = batch_tx(b->tx_policy, b->ctx[i]->p.nx);
+  }
+  auto key = [&](int i) {
+    const lbm_ch_ctx* c = b->ctx[i];
+    return txs[i] * 16 + c->vmode * 2 + (c->p.model == 2 ? 1 : 0);
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return key(x) < key(y); });
+  b->hargs.assign(n, StepArgs{});
+  b->hstart.clear();
+  b->groups.clear();
+  b->built_cur.assign(n, 0);
+  for (int k = 0; k < n; ++k) {
+    const int i = order[k];
+    lbm_ch_ctx* c = b->ctx[i];
+    if (b->groups.empty() || key(order[b->groups.back().first]) != key(i)) {
+      if (!b->groups.empty()) b->hstart.push_back(b->groups.back().total);
+      BatchGroup g{};
+      g.tx = txs[i];
+      g.vmode = c->vmode;
+      g.model2 = c->p.model == 2;
+      g.first = k;
+      g.start_off = (int)b->hstart.size();
+      b->groups.push_back(g);
+    }
+    BatchGroup& g = b->groups.back();
+    const int ty = b->ty < c->p.ny ? b->ty : c->p.ny;
+    StepArgs& a = b->hargs[k];
+    a.src = c->g[c->cur];
+    a.dst = c->g[1 - c->cur];
+    a.plane = c->L.plane;
+    a.nx = c->p.nx;
+    a.ny = c->p.ny;
+    a.ty = ty;
+    a.nstrips = (c->p.nx + g.tx - 1) / g.tx;
+    a.xcd_remap = 0;
+    a.c = c->c;
+    a.ax = c->ax; a.ay = c->ay; a.bx = c->bx; a.by = c->by;
+    a.ux = c->ux; a.uy = c->uy;
+    a.tf = time_factor(c, c->step);
+    b->built_cur[i] = c->cur;
+    b->hstart.push_back(g.total);
+    g.total += a.nstrips * ((c->p.ny + ty - 1) / ty);
+    g.count += 1;
+  }
+  b->hstart.push_back(b->groups.back().total);
+  for (BatchGroup& g : b->groups) {
+    const int per_cu = phi_batch_blocks_per_cu(g.tx, g.vmode, g.model2);
+    const int resident = b->cus * per_cu / 8 * 8;
+    const int want = (g.total + 7) / 8 * 8;
+    g.grid = want < resident ? want : (resident > 8 ? resident : 8);
+  }
+  e = hipMemcpyAsync(b->dargs, b->hargs.data(), n * sizeof(StepArgs), hipMemcpyHostToDevice,
+                     stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->dstart, b->hstart.data(), b->hstart.size() * sizeof(int),
+                       hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e);
+  b->phase = 0;
+  b->built = true;
+  return LBM_CH_OK;
+}
+
+static int batch_prepare(lbm_ch_batch* b, hipStream_t stream) {
+  bool stale = !b->built;
+  for (size_t i = 0; i < b->ctx.size() && !stale; ++i) {
+    if (!live(b->ctx[i])) return LBM_CH_ESTATE;
+    stale = b->ctx[i]->cur != (b->built_cur[i] ^ b->phase);
+  }
+  for (lbm_ch_ctx* c : b->ctx)
+    if (!live(c)) return LBM_CH_ESTATE;
+  return stale ? batch_build(b, stream) : LBM_CH_OK;
+}
+
+static hipError_t batch_enqueue(lbm_ch_batch* b, int64_t nsteps, int phase, hipStream_t s) {
+  for (int64_t k = 0; k < nsteps; ++k) {
+    for (const BatchGroup& g : b->groups) {
+      BatchArgs a{};
+      a.args = b->dargs + g.first;
+      a.start = b->dstart + g.start_off;
+      a.n = g.count;
+      a.total = g.total;
+      a.parity = (int)((phase + k) & 1);
+      hipError_t e = launch_phi_batch(g.tx, g.vmode, g.model2, a, g.grid, s);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+static void batch_advance(lbm_ch_batch* b, int64_t nsteps) {
+  for (lbm_ch_ctx* c : b->ctx) {
+    if (nsteps & 1) c->cur = 1 - c->cur;
+    c->step += nsteps;
+  }
+  b->phase = (int)((b->phase + nsteps) & 1);
+}
+
+extern "C" {
+
+size_t lbm_ch_batch_workspace_bytes(int32_t n) {
+  return n >= 1 ? batch_table_bytes(n) : 0;
+}
+
+int lbm_ch_batch_create(lbm_ch_batch** out, lbm_ch_ctx* const* ctxs, int32_t n,
+                        void* workspace, size_t workspace_bytes) {
+  if (!out) return LBM_CH_EINVAL;
+  *out = nullptr;
+  if (!ctxs || n < 1) return LBM_CH_EINVAL;
+  if (!workspace || ((uintptr_t)workspace % ALIGN) != 0 ||
+      workspace_bytes < batch_table_bytes(n))
+    return LBM_CH_EINVAL;
+  for (int32_t i = 0; i < n; ++i) {
+    const lbm_ch_ctx* c = ctxs[i];
+    if (!live(c)) return LBM_CH_ESTATE;
+    for (int32_t j = 0; j < i; ++j)
+      if (ctxs[j] == c) return LBM_CH_EINVAL;
+    if (c->p.walls != 0 || c->p.storage != LBM_CH_STORE_F32 ||
+        c->p.velocity_mode == LBM_CH_VEL_NS || !c->tf.empty())
+      return LBM_CH_EUNSUPPORTED;
+  }
+  int cus = 0;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(e);
+  lbm_ch_batch* b = new (std::nothrow) lbm_ch_batch();
+  if (!b) return LBM_CH_EINVAL;
+  b->ctx.assign(ctxs, ctxs + n);
+  b->dargs = (StepArgs*)workspace;
+  b->dstart = (int*)((char*)workspace + align_up((size_t)n * sizeof(StepArgs)));
+  b->tx_policy = 64;
+  b->ty = 16;
+  b->phase = 0;
+  b->built = false;
+  b->cus = cus > 0 ? cus : 1;
+  e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(e);
+  }
+  b->magic = BATCH_MAGIC;
+  *out = b;
+  return LBM_CH_OK;
+}
+
+int lbm_ch_batch_set_tiles(lbm_ch_batch* b, int32_t tx, int32_t ty) {
+  if (!batch_live(b)) return LBM_CH_ESTATE;
+  if (!(tx == 0 || valid_tile(tx, 1)) || ty < 1) return LBM_CH_EINVAL;
+  b->tx_policy = tx;
+  b->ty = ty;
+  b->built = false;
+  return LBM_CH_OK;
+}
+
+int lbm_ch_batch_get_tiles(const lbm_ch_batch* b, int32_t* tx, int32_t* ty) {
+  if (!batch_live(b)) return LBM_CH_ESTATE;
+  if (!tx || !ty) return LBM_CH_EINVAL;
+  *tx = b->tx_policy;
+  *ty = b->ty;
+  return LBM_CH_OK;
+}
+
+int lbm_ch_batch_step(lbm_ch_batch* b, int64_t nsteps, int32_t use_graph, hipStream_t stream) {
+  if (!batch_live(b)) return LBM_CH_ESTATE;
+  if (nsteps < 0) return LBM_CH_EINVAL;
+  int r = batch_prepare(b, stream);
+  if (r != LBM_CH_OK || nsteps == 0) return r;
+  if (!use_graph) {
+    hipError_t e = batch_enqueue(b, nsteps, b->phase, stream);
+    if (e != hipSuccess) return hip_fail(e);
+    batch_advance(b, nsteps);
+    return LBM_CH_OK;
+  }
+  hipGraphExec_t exec = nullptr;
+  for (const BatchExec& x : b->execs)
+    if (x.steps == nsteps && x.phase == b->phase) exec = x.exec;
+  if (!exec) {
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e);
+    hipError_t el = batch_enqueue(b, nsteps, b->phase, b->cap);
+    e = hipStreamEndCapture(b->cap, &graph);
+    if (el != hipSuccess) e = el;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e);
+    if (b->execs.size() >= 4) {
+      (void)hipGraphExecDestroy(b->execs.front().exec);
+      b->execs.erase(b->execs.begin());
+    }
+    b->execs.push_back(BatchExec{exec, nsteps, b->phase});
+  }
+  hipError_t e = hipGraphLaunch(exec, stream);
+  if (e != hipSuccess) return hip_fail(e);
+  batch_advance(b, nsteps);
+  return LBM_CH_OK;
+}
+
+size_t lbm_ch_batch_state_bytes(const lbm_ch_batch* b) {
+  if (!batch_live(b)) return 0;
+  size_t total = 0;
+  for (const lbm_ch_ctx* c : b->ctx) total += align_up(lbm_ch_state_bytes(c));
+  return total;
+}
+
+int lbm_ch_batch_autotune(lbm_ch_batch* b, void* backup, size_t backup_bytes,
+                          int32_t trial_steps, hipStream_t stream, float* best_us) {
+  if (!batch_live(b)) return LBM_CH_ESTATE;
+  for (lbm_ch_ctx* c : b->ctx)
+    if (!live(c)) return LBM_CH_ESTATE;
+  if (!backup || ((uintptr_t)backup % ALIGN) != 0 ||
+      backup_bytes != lbm_ch_batch_state_bytes(b) || trial_steps < 1)
+    return LBM_CH_EINVAL;
+  std::vector<int64_t> step0;
+  size_t off = 0;
+  for (lbm_ch_ctx* c : b->ctx) {
+    step0.push_back(c->step);
+    const int r = lbm_ch_save_state(c, (char*)backup + off, lbm_ch_state_bytes(c), stream);
+    if (r != LBM_CH_OK) return r;
+    off += align_up(lbm_ch_state_bytes(c));
+  }
+  const int tx0 = b->tx_policy, ty0 = b->ty;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  int r = LBM_CH_OK;
+  float best = -1.0f;
+  int btx = tx0, bty = ty0;
+  for (int xx : {0, 64, 128, 256}) {
+    for (int yy : {4, 8, 16, 32}) {
+      if (e != hipSuccess || r != LBM_CH_OK) break;
+      b->tx_policy = xx;
+      b->ty = yy;
+      b->built = false;
+      r = lbm_ch_batch_step(b, 1, 0, stream);  // rebuilds the tables; untimed
+      if (r != LBM_CH_OK) break;
+      e = hipEventRecord(e0, stream);
+      if (e == hipSuccess) r = lbm_ch_batch_step(b, trial_steps, 0, stream);
+      if (e == hipSuccess && r == LBM_CH_OK) e = hipEventRecord(e1, stream);
+      if (e == hipSuccess && r == LBM_CH_OK) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess && r == LBM_CH_OK) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && r == LBM_CH_OK && (best < 0.0f || ms < best)) {
+        best = ms;
+        btx = xx;
+        bty = yy;
+      }
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  const bool ok = e == hipSuccess && r == LBM_CH_OK;
+  b->tx_policy = ok ? btx : tx0;
+  b->ty = ok ? bty : ty0;
+  b->built = false;
+  off = 0;
+  int r2 = LBM_CH_OK;
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    lbm_ch_ctx* c = b->ctx[i];
+    const int ri = lbm_ch_load_state(c, (char*)backup + off, lbm_ch_state_bytes(c), step0[i],
+                                     stream);
+    if (ri != LBM_CH_OK) r2 = ri;
+    off += align_up(lbm_ch_state_bytes(c));
+  }
+  if (e != hipSuccess) return hip_fail(e);
+  if (r != LBM_CH_OK) return r;
+  if (best_us && ok) *best_us = best * 1000.0f / (float)trial_steps;
+  return r2;
+}
+
+int lbm_ch_batch_destroy(lbm_ch_batch* b) {
+  if (!b) return LBM_CH_OK;
+  if (!batch_live(b)) return LBM_CH_ESTATE;
+  batch_drop_graphs(b);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  b->magic = 0;
+  delete b;
+  return LBM_CH_OK;
+}
 
 }  // extern "C"

@@ -41,6 +41,16 @@ struct StepArgs {
   float tf;
 };
 
+// Arguments of the batched step: one StepArgs per instance (src/dst as at parity 0),
+// start[i] = first tile of instance i (start[n] = total), periodic float32 lattices.
+struct BatchArgs {
+  const StepArgs* args;
+  const int* start;
+  int n;
+  int total;
+  int parity;         // 1: swap src and dst of every instance
+};
+
 // Arguments of the coupled Navier-Stokes step.
 struct NsArgs {
   const void* gsrc;   // phase-field populations at t_n (storage mode of g)
@@ -62,6 +72,10 @@ uint32_t population_bytes(int storage, uint32_t plane);
 // Launchers (return hipGetLastError() of the launch).
 hipError_t launch_phi_step(int tx, bool walls, int vmode, bool model2, int storage,
                            const StepArgs& a, int nblocks, hipStream_t s);
+// grid: a multiple of 8 workgroups; the kernel strides over the tiles.
+int phi_batch_blocks_per_cu(int tx, int vmode, bool model2);
+hipError_t launch_phi_batch(int tx, int vmode, bool model2, const BatchArgs& b, int grid,
+                            hipStream_t s);
 hipError_t launch_ns_step(int tx, bool walls, int storage, const NsArgs& a, int nblocks,
                           hipStream_t s);
 

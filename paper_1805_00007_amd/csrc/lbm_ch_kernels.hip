@@ -249,9 +249,9 @@ struct RowRec {
 #ifndef WPE_PHI
 #define WPE_PHI 4
 #endif
+// One tile of the step: strip (L % nstrips) of TX columns, row chunk L / nstrips.
 template <int TX, bool WALLS, int VMODE, bool MODEL2, int ST>
-__global__ void __launch_bounds__(TX) __attribute__((amdgpu_waves_per_eu(WPE_PHI, 8)))
-k_phi_step(const StepArgs a) {
+__device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
   constexpr bool NSC = VMODE == VEL_NSFIELD;
   constexpr bool VFIELD = VMODE != VEL_SEP;
   constexpr int LW = TX + 4;
@@ -279,11 +279,6 @@ k_phi_step(const StepArgs a) {
   if (NSC) rp = make_rsrc(a.pf, nodes * 4u);
 
   const int t = threadIdx.x;
-  int L = blockIdx.x;
-  if (a.xcd_remap) {
-    const int per = gridDim.x >> 3;
-    L = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  }
   const int x0 = (L % a.nstrips) * TX;
   const int chunk = L / a.nstrips;
   const int rows = min(a.ty, ny - chunk * a.ty);
@@ -486,6 +481,54 @@ k_phi_step(const StepArgs a) {
     row(k + 1, X1, X0);
   }
   if (k < rows) row(k, X0, X1);
+}
+
+template <int TX, bool WALLS, int VMODE, bool MODEL2, int ST>
+__global__ void __launch_bounds__(TX) __attribute__((amdgpu_waves_per_eu(WPE_PHI, 8)))
+k_phi_step(const StepArgs a) {
+  int L = blockIdx.x;
+  if (a.xcd_remap) {  // workgroup w runs on XCD w % 8: give each XCD a band of chunks
+    const int per = gridDim.x >> 3;
+    L = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  }
+  phi_tile<TX, WALLS, VMODE, MODEL2, ST>(a, L);
+}
+
+// Batched step: the tiles of many lattices (one instance table entry each) in one
+// persistent launch.  The tiles are numbered instance by instance; XCD x (workgroups
+// w with w % 8 == x) owns the contiguous range [x per, (x + 1) per) and its workgroups
+// stride through it, so vertically adjacent tiles of one lattice share that XCD's L2.
+// Every workgroup leaves the loop after at most ceil(per / slots) tiles.
+#ifndef WPE_BATCH
+#define WPE_BATCH 3
+#endif
+template <int TX, int VMODE, bool MODEL2>
+__global__ void __launch_bounds__(TX) __attribute__((amdgpu_waves_per_eu(WPE_BATCH, 8)))
+k_phi_batch(const BatchArgs b) {
+  const int slots = gridDim.x >> 3;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int per = (b.total + 7) >> 3;
+  const int lo = xcd * per, hi = min(b.total, lo + per);
+  int v = lo + slot;
+  if (v >= hi) return;
+  int lo_i = 0, hi_i = b.n;  // instance of tile v: start[inst] <= v < start[inst + 1]
+  while (hi_i - lo_i > 1) {
+    const int mid = (lo_i + hi_i) >> 1;
+    if (b.start[mid] <= v) lo_i = mid; else hi_i = mid;
+  }
+  int inst = lo_i;
+#pragma unroll 1
+  for (; v < hi; v += slots) {
+    while (b.start[inst + 1] <= v) ++inst;
+    StepArgs a = b.args[inst];
+    if (b.parity) {
+      const void* t = a.src;
+      a.src = a.dst;
+      a.dst = const_cast<void*>(t);
+    }
+    phi_tile<TX, false, VMODE, MODEL2, ST_F32>(a, v - b.start[inst]);
+    __syncthreads();  // the LDS rings are reused by the next tile
+  }
 }
 
 // ---------------------------------------------------------------------------------
@@ -1016,6 +1059,18 @@ hipError_t phi_step_m(bool model2, const StepArgs& a, int nb, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int TX>
+hipError_t phi_batch_t(int vmode, bool model2, const BatchArgs& b, int grid, hipStream_t s) {
+  if (vmode == VEL_SEP) {
+    if (model2) hipLaunchKernelGGL((k_phi_batch<TX, VEL_SEP, true>), dim3(grid), dim3(TX), 0, s, b);
+    else hipLaunchKernelGGL((k_phi_batch<TX, VEL_SEP, false>), dim3(grid), dim3(TX), 0, s, b);
+  } else {
+    if (model2) hipLaunchKernelGGL((k_phi_batch<TX, VEL_FIELD, true>), dim3(grid), dim3(TX), 0, s, b);
+    else hipLaunchKernelGGL((k_phi_batch<TX, VEL_FIELD, false>), dim3(grid), dim3(TX), 0, s, b);
+  }
+  return hipGetLastError();
+}
+
 template <int TX, bool WALLS, int ST>
 hipError_t phi_step_v(int vmode, bool model2, const StepArgs& a, int nb, hipStream_t s) {
   switch (vmode) {
@@ -1085,6 +1140,36 @@ hipError_t launch_phi_step(int tx, bool walls, int vmode, bool model2, int stora
     case ST_F32: return phi_step_t<ST_F32>(tx, walls, vmode, model2, a, nblocks, s);
     case ST_F16: return phi_step_t<ST_F16>(tx, walls, vmode, model2, a, nblocks, s);
     case ST_BF16: return phi_step_t<ST_BF16>(tx, walls, vmode, model2, a, nblocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int phi_batch_blocks_per_cu(int tx, int vmode, bool model2) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  const bool sep = vmode == VEL_SEP;
+#define LBM_OCC(T)                                                                          \
+  e = sep ? (model2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phi_batch<T, VEL_SEP, true>, T, 0)    \
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phi_batch<T, VEL_SEP, false>, T, 0))   \
+          : (model2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phi_batch<T, VEL_FIELD, true>, T, 0)  \
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phi_batch<T, VEL_FIELD, false>, T, 0))
+  switch (tx) {
+    case 64: LBM_OCC(64); break;
+    case 128: LBM_OCC(128); break;
+    case 256: LBM_OCC(256); break;
+    default: break;
+  }
+#undef LBM_OCC
+  return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
+hipError_t launch_phi_batch(int tx, int vmode, bool model2, const BatchArgs& b, int grid,
+                            hipStream_t s) {
+  if (grid <= 0 || (grid & 7) != 0 || b.n <= 0) return hipErrorInvalidValue;
+  switch (tx) {
+    case 64: return phi_batch_t<64>(vmode, model2, b, grid, s);
+    case 128: return phi_batch_t<128>(vmode, model2, b, grid, s);
+    case 256: return phi_batch_t<256>(vmode, model2, b, grid, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -97,6 +97,14 @@ def test_context_calls_reject_null_and_strerror():
     assert L.lbm_ch_record(None, 1, None, None) == lbm.ESTATE
     assert L.lbm_ch_adjoint(None, 1, 1, None, None, None, None, None, 0, None) == lbm.ESTATE
     assert L.lbm_ch_destroy(None) == lbm.OK
+    assert L.lbm_ch_batch_step(None, 1, 0, None) == lbm.ESTATE
+    assert L.lbm_ch_batch_autotune(None, None, 0, 1, None, None) == lbm.ESTATE
+    assert L.lbm_ch_batch_state_bytes(None) == 0
+    assert L.lbm_ch_batch_destroy(None) == lbm.OK
+    b = ctypes.c_void_p()
+    assert L.lbm_ch_batch_create(ctypes.byref(b), None, 0, None, 0) == lbm.EINVAL
+    assert L.lbm_ch_batch_workspace_bytes(0) == 0
+    assert L.lbm_ch_batch_workspace_bytes(64) > 0
     for st in (lbm.OK, lbm.EINVAL, lbm.EUNSUPPORTED, lbm.EHIP, lbm.ENONFINITE, lbm.ESTATE):
         assert L.lbm_ch_strerror(st)
     assert L.lbm_ch_strerror(12345) == b"unknown status"

@@ -285,3 +285,20 @@ def adjoint_case(n=256, steps=2000, modes=4, seed=5, target_seed=6, umax=0.05,
     phi0 = circle(n, n, n / 2.0, n / 2.0, radius_frac * n, phys["width"])
     return AdjointCase("adjoint%d" % n, n, steps, phys, phi0, basis, theta, scale, theta_t,
                        scale_t)
+
+
+def batch_case(n_inst=64, seed=4, sides=(64, 128, 192, 256, 384, 512), modes=8, umax=0.05,
+               steps=5000, model=2):
+    """Many independent lattices of uneven sizes: side lengths drawn from `sides` by the
+    seed, each with 1-3 random circles or ellipses (radii 0.1-0.3 of the side) and a
+    steady divergence-free velocity from its own random stream function (modes x modes
+    Fourier modes, scaled to max |u| = umax).  Prescribed-flow parameters of Sec. III."""
+    rng = np.random.default_rng(seed)
+    picks = rng.choice(np.asarray(sides), size=n_inst)
+    phys = dict(PRESCRIBED, model=model)
+    out = []
+    for i, n in enumerate(picks.tolist()):
+        phi0 = random_blobs(n, seed=seed * 1000 + i, width=phys["width"])
+        U, V = random_stream_function(n, modes, seed * 1000 + 500 + i, umax)
+        out.append(Workload("batch%d_%d" % (i, n), n, n, steps, phys, phi0, field=(U, V)))
+    return out
