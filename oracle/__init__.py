@@ -97,7 +97,8 @@ def _load():
         lib.orc_lap.argtypes = [P, _D, ctypes.c_int, _D]
         lib.orc_chemical_potential.argtypes = [P, _D, _D]
         lib.orc_init.argtypes = [P, _D, _D, _D, _D, _D]
-        lib.orc_run.argtypes = [P, _D, _D, _D, _D, _D, ctypes.c_long]
+        lib.orc_run.argtypes = [P, _D, _D, _D, _D, _D, ctypes.c_long, _D,
+                                ctypes.POINTER(ctypes.c_int)]
         lib.orc_fields.argtypes = [P, _D, _D, _D, _D, ctypes.c_double] + [_D] * 5
         lib.orc_diag.argtypes = [P, _D, _D, _D]
         lib.orc_num_threads.restype = ctypes.c_int
@@ -196,6 +197,9 @@ class State:
         v0 = None if self.uy is None else f0 * self.uy
         _load().orc_init(ctypes.byref(p.c()), _ptr(phi0), _ptr(u0), _ptr(v0), _ptr(self.g),
                          _ptr(self.f))
+        # model 3: F1 and grad mu of the previous step (Eq. F2-1 time derivatives)
+        self.hist = np.zeros((4, p.ny, p.nx))
+        self.hist_valid = ctypes.c_int(0)
 
     def run(self, nsteps: int) -> "State":
         tf = None
@@ -203,7 +207,8 @@ class State:
             assert self.n + nsteps <= len(self.tf), "time-factor table too short"
             tf = np.ascontiguousarray(self.tf[self.n:self.n + nsteps])
         _load().orc_run(ctypes.byref(self.p.c()), _ptr(self.g), _ptr(self.f), _ptr(self.ux),
-                        _ptr(self.uy), _ptr(tf), int(nsteps))
+                        _ptr(self.uy), _ptr(tf), int(nsteps), _ptr(self.hist),
+                        ctypes.byref(self.hist_valid))
         self.n += nsteps
         return self
 

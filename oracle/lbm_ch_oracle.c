@@ -306,8 +306,11 @@ static void velocity_fields(const orc_params* p, const orc_coeffs* c, const doub
   }
 }
 
-/* F = F1 (+ F2): Eq. t0-phiu and Eq. mark3. */
-static void ch_force(const orc_params* p, const orc_coeffs* c, orc_work* w) {
+/* F = F1 (+ F2): Eq. t0-phiu and Eq. mark3 (model 2) or Eq. F2-1 (model 3).  For
+ * model 3, hist holds F1 and grad mu of the previous step (planes F1x, F1y, mux, muy)
+ * and *hist_valid says whether there was one. */
+static void ch_force(const orc_params* p, const orc_coeffs* c, orc_work* w, double* hist,
+                     int* hist_valid) {
   size_t n = nn(p);
   int nx = p->nx, ny = p->ny;
   double rho_mean = 0.5 * (p->rho_a + p->rho_b);
@@ -328,11 +331,34 @@ static void ch_force(const orc_params* p, const orc_coeffs* c, orc_work* w) {
       w->fx[k] = phi / rho * tx;
       w->fy[k] = phi / rho * ty;
     }
-  if (p->model != 2) return;
-  /* F2 = 3 cs^2 K grad(div(phi u)): two composed isotropic gradients.  q = phi u
-   * takes the velocity's ghost parity (-1) across walls; div q is evaluated on the
-   * rows -1..ny (stored with a one-row offset) so that its gradient reaches every
-   * fluid row. */
+  if (p->model == 1) return;
+  /* Eq. F2-1, model 3: the time derivatives of F1 and grad mu (taken on the whole time
+   * scale, as Remarks I and II allow) as differences over the last step; zero on the
+   * first step, which has no earlier state. */
+  if (p->model == 3) {
+    double cA = 2.0 * p->tau_g - 1.0 + 3.0 * c->K;
+    double cB = 3.0 * CS2 * c->eta * c->K;
+    int valid = hist_valid ? *hist_valid : 0;
+#pragma omp parallel for schedule(static)
+    for (size_t k = 0; k < n; ++k) {
+      double f1x = w->fx[k], f1y = w->fy[k];
+      double dF1x = valid ? f1x - hist[k] : 0.0;
+      double dF1y = valid ? f1y - hist[n + k] : 0.0;
+      double dmux = valid ? w->mux[k] - hist[2 * n + k] : 0.0;
+      double dmuy = valid ? w->muy[k] - hist[3 * n + k] : 0.0;
+      hist[k] = f1x;
+      hist[n + k] = f1y;
+      hist[2 * n + k] = w->mux[k];
+      hist[3 * n + k] = w->muy[k];
+      w->fx[k] = f1x + cA * dF1x + cB * dmux;
+      w->fy[k] = f1y + cA * dF1y + cB * dmuy;
+    }
+    if (hist_valid) *hist_valid = 1;
+  }
+  /* F2 (models 2 and 3) contains 3 cs^2 K grad(div(phi u)): two composed isotropic
+   * gradients.  q = phi u takes the velocity's ghost parity (-1) across walls; div q
+   * is evaluated on the rows -1..ny (stored with a one-row offset) so that its
+   * gradient reaches every fluid row. */
   for (size_t k = 0; k < n; ++k) {
     w->qx[k] = w->phi[k] * w->u[k];
     w->qy[k] = w->phi[k] * w->v[k];
@@ -417,15 +443,16 @@ void orc_init(const orc_params* p, const double* phi0, const double* ux0, const 
 }
 
 void orc_run(const orc_params* p, double* g, double* f, const double* ux, const double* uy,
-             const double* tf, long nsteps) {
+             const double* tf, long nsteps, double* hist, int* hist_valid) {
   orc_coeffs c;
   if (orc_coeffs_from(p, &c) != 0) return;
+  if (p->model == 3 && (!hist || !hist_valid)) return;
   orc_work w;
   work_alloc(p, &w);
   for (long s = 0; s < nsteps; ++s) {
     phase_fields(p, &c, g, &w);
     velocity_fields(p, &c, f, ux, uy, tf ? tf[s] : 1.0, &w);
-    ch_force(p, &c, &w);
+    ch_force(p, &c, &w, hist, hist_valid);
     collide_stream(p, &c, g, f, &w);
   }
   work_free(&w);

@@ -42,7 +42,9 @@ extern "C" {
 typedef struct {
   int nx, ny;
   int walls;     /* 0: periodic in y; 1: no-slip walls below row 0 and above row ny-1 */
-  int model;     /* 1: F = F1 (Model-I); 2: F = F1 + F2 of Eq. mark3 (Model-II)        */
+  int model;     /* 1: F = F1 (Model-I); 2: F = F1 + F2 of Eq. mark3 (Model-II);
+                    3: F = F1 + F2 of Eq. F2-1 with the time derivatives as one-step
+                    backward differences (Model-II at any tau_g)                       */
   int ns;        /* 0: prescribed velocity, grad p = 0; 1: coupled Navier-Stokes        */
   double tau_g, mobility, sigma, width, phi_a, phi_b, rho_a, rho_b;
   double tau_f;    /* NS relaxation time, nu = cs^2 (tau_f - 1/2)                      */
@@ -82,9 +84,11 @@ void orc_init(const orc_params* p, const double* phi0, const double* ux0, const 
 
 /* Advance nsteps.  g (and f when ns = 1) hold the state on entry and exit.
  * Prescribed velocity at step n (from t_n to t_{n+1}) is tf[n]*ux, tf[n]*uy;
- * tf may be NULL (factor 1); ux/uy may be NULL (zero velocity). */
+ * tf may be NULL (factor 1); ux/uy may be NULL (zero velocity).  Model 3 also needs
+ * hist (4*nx*ny doubles: F1 and grad mu of the previous step, updated) and
+ * *hist_valid (0 before the first step, set to 1); both may be NULL otherwise. */
 void orc_run(const orc_params* p, double* g, double* f, const double* ux, const double* uy,
-             const double* tf, long nsteps);
+             const double* tf, long nsteps, double* hist, int* hist_valid);
 
 /* Macroscopic fields of a state.  For ns = 0 the velocity written is tfac*ux, tfac*uy
  * and p = 0.  Any output pointer may be NULL. */

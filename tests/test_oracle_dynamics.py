@@ -11,6 +11,10 @@
   F1 and F2, the eta-M relation and the streaming direction;
 * with sigma = 0, F2 of Eq. mark3 cancels the leading third-order phase error of the
   lattice advection at tau_g = 1 (Model-II) while Model-I keeps it;
+* model 3 (Eq. F2-1 at any tau_g, time derivatives as one-step backward differences):
+  the linear response of a mode equals an 11x11 update whose state is the populations
+  plus the previous step's (2 tau - 1 + 3K) F1 + 3 cs^2 eta K grad mu, built here from
+  Eqs. LB, geq, liangFi and F2-1; its first step equals Model-II's;
 * constant states are fixed points; a planar tanh is stationary to O((dx/W)^2);
   phi -> -phi with rho_A <-> rho_B and mirror x -> -x are symmetries;
 * the wall rule equals the periodic run on the mirrored doubled domain.
@@ -206,6 +210,86 @@ def test_linear_response_of_a_mode(tau, model):
         got1 = _mode_amplitude(oracle.State(p, phi0, np.full((ny, nx), u[0]),
                                             np.full((ny, nx), u[1])).run(1).phi, m_, l_) / eps
         assert abs(got1 - A) < 2e-6 * abs(A)
+
+
+def _linear_update_hist(tau, kx, ky, phibar, u, beta, kappa, eta, a, b, K):
+    """11x11 update of (g_hat, X_prev_hat) for model 3, X = (2 tau - 1 + 3K) F1 +
+    3 cs^2 eta K grad mu (Eq. F2-1 with d/dt over one step), and its initial vector (the
+    first step has no earlier state: X_prev = X)."""
+    G, lam = _symbols(kx, ky)
+    m = 4 * beta * (3 * phibar ** 2 - 1) + kappa * lam
+    rho = a * phibar + b
+    gmu = 1j * G * m                                  # grad mu / phi_hat
+    F1 = -(phibar ** 2 / rho) * gmu
+    X = (2 * tau - 1 + 3 * K) * F1 + 3 * CS2 * eta * K * gmu
+    F = F1 + X - K * G * (G @ u)                      # minus X_prev, added below
+    usq = u @ u
+    eq = np.zeros(9, complex)
+    s_phi = np.zeros(9, complex)
+    s_x = np.zeros((9, 2), complex)
+    for i in range(9):
+        cu = CX[i] * u[0] + CY[i] * u[1]
+        eq[i] = W[i] * eta * m + W[i] * (3 * cu + 4.5 * cu * cu - 1.5 * usq) \
+            + (1 - eta * m if i == 0 else 0)
+        s_phi[i] = 3 * W[i] * (CX[i] * F[0] + CY[i] * F[1])
+        s_x[i] = -3 * W[i] * np.array([CX[i], CY[i]])
+    om = 1 / tau
+    E = np.diag([np.exp(-1j * (kx * CX[i] + ky * CY[i])) for i in range(9)])
+    T = np.zeros((11, 11), complex)
+    T[:9, :9] = E @ ((1 - om) * np.eye(9) + np.outer(om * eq + (1 - om / 2) * s_phi,
+                                                     np.ones(9)))
+    T[:9, 9:] = E @ ((1 - om / 2) * s_x)
+    T[9:, :9] = np.outer(X, np.ones(9))
+    v0 = np.concatenate([eq, X])
+    return T, v0
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.8, 0.5 + math.sqrt(3) / 6, 1.4])
+def test_linear_response_model3(tau):
+    nx, ny = 32, 24
+    m_, l_ = 3, 2
+    kx, ky = 2 * math.pi * m_ / nx, 2 * math.pi * l_ / ny
+    phibar, eps = 0.8, 1e-6
+    u = np.array([0.03, -0.02])
+    p = oracle.Params(nx=nx, ny=ny, tau_g=tau, model=3, sigma=0.05, width=3.0,
+                      mobility=0.03, rho_a=1.0, rho_b=0.4)
+    c = oracle.coeffs(p)
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    phi0 = phibar + eps * np.cos(kx * x + ky * y)
+    T, v0 = _linear_update_hist(tau, kx, ky, phibar, u, c["beta"], c["kappa"], c["eta"],
+                                c["a"], c["b"], c["K"])
+    s = oracle.State(p, phi0, np.full((ny, nx), u[0]), np.full((ny, nx), u[1]))
+    for nsteps in (1, 2, 6):
+        s.run(nsteps - s.n)
+        want = (np.linalg.matrix_power(T, nsteps) @ v0)[:9].sum()
+        got = _mode_amplitude(s.phi, m_, l_) / eps
+        assert abs(got - want) < 2e-5 * abs(want), nsteps
+    # the history term changes the answer after the first step (the pin is not vacuous)
+    T2, eq2 = _linear_update(tau, kx, ky, phibar, u, c["beta"], c["kappa"], c["eta"], c["a"],
+                             c["b"], c["K"], 2)
+    m2 = np.ones(9) @ np.linalg.matrix_power(T2, 6) @ eq2
+    assert abs(m2 - want) > 1e-4 * abs(want)
+
+
+def test_model3_first_step_is_model2_and_remark1():
+    """Before any earlier state the time differences of Eq. F2-1 are zero, so step one
+    of model 3 equals Model-II; at tau = 1/2 + sqrt(3)/6 (Remark I) K = 0, so Model-II
+    reduces to Model-I while model 3 keeps (2 tau - 1) dF1/dt."""
+    n = 40
+    w = workloads.vortex(n, period=200, steps=20)
+    U, V = workloads.separable_field(w.velocity)
+    out = {}
+    for tau in (0.8, 0.5 + math.sqrt(3) / 6):
+        for model in (1, 2, 3):
+            p = oracle.Params(nx=n, ny=n, **dict(w.phys, tau_g=tau, model=model))
+            s = oracle.State(p, w.phi0, U, V, w.velocity["tf"])
+            out[tau, model, 1] = s.run(1).phi.copy()
+            out[tau, model, 5] = s.run(4).phi.copy()
+    for tau in (0.8, 0.5 + math.sqrt(3) / 6):
+        assert np.array_equal(out[tau, 3, 1], out[tau, 2, 1])
+        assert np.abs(out[tau, 3, 5] - out[tau, 2, 5]).max() > 1e-9
+    t1 = 0.5 + math.sqrt(3) / 6
+    assert np.abs(out[t1, 2, 5] - out[t1, 1, 5]).max() < 1e-13
 
 
 def test_model2_cancels_third_order_advection_error():
