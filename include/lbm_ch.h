@@ -10,6 +10,11 @@
  *   F1  = (phi/rho)(F_s + F_b - grad p), F_s = -phi grad mu,
  *         rho = a phi + b                                      Eqs. NS, rho, t0-phiu
  *   F2  = 3 cs^2 K grad(div(phi u))   (Model-II only)          Eq. mark3, K below Eq. F2-1
+ *         model 3, any tau_g: F2 = (2 tau_g - 1 + 3K) dF1/dt + 3 cs^2 eta K d(grad mu)/dt
+ *         + 3 cs^2 K grad(div(phi u)) (Eq. F2-1; the time derivatives on the whole time
+ *         scale as Remarks I and II allow, as differences over the last step, zero on
+ *         the first step; the state then holds X = (2 tau_g - 1 + 3K) F1
+ *         + 3 cs^2 eta K grad mu of the previous step)
  *   g_i^eq, S_i = w_i c_i.F/cs^2                               Eqs. geq, liangFi
  *   g_i(x + c_i, t + 1) = g_i - (g_i - g_i^eq)/tau_g
  *                         + (1 - 1/(2 tau_g)) S_i              Eq. LB
@@ -97,7 +102,8 @@ enum {
 typedef struct {
   int32_t nx, ny;         /* lattice nodes; 4 <= nx, ny and 9*nx*ny < 2^31          */
   int32_t walls;          /* 0: periodic in y; 1: no-slip walls (see above)         */
-  int32_t model;          /* 1: F = F1 (Model-I); 2: F = F1 + F2 (Model-II), Eq. reFi */
+  int32_t model;          /* 1: F = F1 (Model-I); 2: F = F1 + F2 of Eq. mark3 (Model-II);
+                             3: F = F1 + F2 of Eq. F2-1 (see below; LBM_CH_STORE_F32) */
   int32_t velocity_mode;  /* LBM_CH_VEL_*                                           */
   int32_t storage;        /* LBM_CH_STORE_* (population storage of g)                */
   double tau_g;           /* relaxation time of g, > 1/2 (Eq. LB)                   */
@@ -133,7 +139,8 @@ size_t lbm_ch_workspace_bytes(const lbm_ch_params* p);
  * context.  Errors: LBM_CH_EINVAL for tau_g <= 1/2, tau_f <= 1/2 (NS), sizes out of
  * range, phi_a == phi_b, rho_a or rho_b <= 0, model not 1 or 2, a NULL or unaligned
  * (4-byte) array the mode needs, a workspace smaller than lbm_ch_workspace_bytes or
- * not 256-byte aligned, or a storage mode outside LBM_CH_STORE_*. */
+ * not 256-byte aligned, or a storage mode outside LBM_CH_STORE_*; LBM_CH_EUNSUPPORTED
+ * for model 3 with 16-bit storage. */
 int lbm_ch_init(lbm_ch_ctx** out, const lbm_ch_params* p, const lbm_ch_velocity* vel,
                 void* workspace, size_t workspace_bytes, const float* phi0,
                 hipStream_t stream);
@@ -163,8 +170,8 @@ int lbm_ch_check_finite(lbm_ch_ctx* ctx, hipStream_t stream);
 /* Current step counter n. */
 int64_t lbm_ch_step_count(const lbm_ch_ctx* ctx);
 
-/* Bytes of the solver state: the g populations in their storage layout (followed
- * by the float32 f populations with NS). */
+/* Bytes of the solver state: the g populations in their storage layout, followed by
+ * the float32 f populations with NS, then for model 3 the two float32 planes of X. */
 size_t lbm_ch_state_bytes(const lbm_ch_ctx* ctx);
 
 /* Enqueue a device-to-device copy of the state into dst (checkpoint), or from src
@@ -221,8 +228,8 @@ int lbm_ch_record(lbm_ch_ctx* ctx, int64_t nsteps, float* phi_traj, hipStream_t 
  * with LBM_CH_VEL_FIELD; the products ax[x] ay[y] and bx[x] by[y] with
  * LBM_CH_VEL_SEPARABLE).  scratch: at least lbm_ch_adjoint_scratch_bytes device bytes,
  * 4-byte aligned, contents undefined afterwards.  The context's state and step counter
- * are not changed.  Errors: LBM_CH_EUNSUPPORTED unless tau_g == 1, walls == 0 and the
- * velocity is prescribed; LBM_CH_EINVAL for nsteps < 0, n_end < nsteps, NULL or
+ * are not changed.  Errors: LBM_CH_EUNSUPPORTED unless tau_g == 1, walls == 0, model
+ * is 1 or 2 and the velocity is prescribed; LBM_CH_EINVAL for nsteps < 0, n_end < nsteps, NULL or
  * unaligned arrays, or too little scratch. */
 int lbm_ch_adjoint(lbm_ch_ctx* ctx, int64_t n_end, int64_t nsteps, const float* phi_traj,
                    float* lam, float* grad_u, float* grad_v, void* scratch,
@@ -235,8 +242,8 @@ int lbm_ch_adjoint(lbm_ch_ctx* ctx, int64_t n_end, int64_t nsteps, const float* 
  * grid of workgroups walks, each XCD taking a contiguous range of it.  Results are
  * bitwise those of lbm_ch_step on each context.  Lattices with different tile widths
  * or kernel variants (velocity mode, Model-I/II) form groups of one launch each.
- * Supported: periodic lattices, LBM_CH_STORE_F32, prescribed velocity without a
- * time-factor table.  The contexts must outlive the batch; stepping a context on its
+ * Supported: periodic lattices, LBM_CH_STORE_F32, model 1 or 2, prescribed velocity
+ * without a time-factor table.  The contexts must outlive the batch; stepping a context on its
  * own between batch steps is allowed. */
 typedef struct lbm_ch_batch lbm_ch_batch; /* opaque, host-side */
 
@@ -246,8 +253,8 @@ size_t lbm_ch_batch_workspace_bytes(int32_t n);
 /* Create a batch over ctxs[0..n) (distinct, live).  workspace: caller device memory of
  * lbm_ch_batch_workspace_bytes(n) bytes, 256-byte aligned, kept until destroy.  No
  * device work is enqueued.  Errors: LBM_CH_EINVAL (sizes, NULL, duplicates),
- * LBM_CH_ESTATE (a dead context), LBM_CH_EUNSUPPORTED (walls, 16-bit storage, NS
- * velocity or a time-factor table). */
+ * LBM_CH_ESTATE (a dead context), LBM_CH_EUNSUPPORTED (walls, 16-bit storage, model 3,
+ * NS velocity or a time-factor table). */
 int lbm_ch_batch_create(lbm_ch_batch** out, lbm_ch_ctx* const* ctxs, int32_t n,
                         void* workspace, size_t workspace_bytes);
 

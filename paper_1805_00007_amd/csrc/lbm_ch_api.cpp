@@ -34,7 +34,7 @@ struct Layout {
   size_t g_bytes;  // one g population buffer, 256-byte aligned
   size_t f_bytes;  // one f population buffer, 256-byte aligned
   size_t off_ga, off_gb, off_fa, off_fb, off_u, off_v, off_p, off_phi, off_ztab, off_part,
-      off_diag, total;
+      off_diag, off_xh, total;
 };
 
 bool valid_params(const lbm_ch_params* p) {
@@ -42,7 +42,7 @@ bool valid_params(const lbm_ch_params* p) {
   if (p->nx < 4 || p->ny < 4) return false;
   if ((double)p->nx * (double)p->ny * 9.0 * 4.0 >= 2147483648.0) return false;
   if (p->walls != 0 && p->walls != 1) return false;
-  if (p->model != 1 && p->model != 2) return false;
+  if (p->model < 1 || p->model > 3) return false;
   if (p->velocity_mode < LBM_CH_VEL_NONE || p->velocity_mode > LBM_CH_VEL_NS) return false;
   if (p->storage < LBM_CH_STORE_F32 || p->storage > LBM_CH_STORE_BF16) return false;
   if (!(p->tau_g > 0.5) || !isfinite(p->tau_g)) return false;
@@ -78,6 +78,7 @@ Layout layout_of(const lbm_ch_params* p) {
   L.off_ztab = o; o += align_up((size_t)2 * (p->nx + p->ny) * sizeof(float));
   L.off_part = o; o += align_up((size_t)diag_partial_blocks() * 8 * sizeof(double));
   L.off_diag = o; o += align_up(8 * sizeof(double));
+  L.off_xh = o; if (p->model == 3) o += align_up(2 * nodes * sizeof(float));
   L.total = o;
   return L;
 }
@@ -92,7 +93,7 @@ struct lbm_ch_ctx {
   Layout L;
   char* ws;
   void* g[2];
-  float *f[2], *u, *v, *pr, *phi, *ztab;
+  float *f[2], *u, *v, *pr, *phi, *ztab, *xh;
   double *part, *diag;
   int cur;  // index of the buffer holding the current state
   int64_t step;
@@ -171,6 +172,7 @@ int lbm_ch_init(lbm_ch_ctx** out, const lbm_ch_params* p, const lbm_ch_velocity*
   if (!out) return LBM_CH_EINVAL;
   *out = nullptr;
   if (!valid_params(p)) return LBM_CH_EINVAL;
+  if (p->model == 3 && p->storage != LBM_CH_STORE_F32) return LBM_CH_EUNSUPPORTED;
   const Layout L = layout_of(p);
   if (!workspace || ((uintptr_t)workspace % ALIGN) != 0 || workspace_bytes < L.total)
     return LBM_CH_EINVAL;
@@ -206,6 +208,7 @@ int lbm_ch_init(lbm_ch_ctx** out, const lbm_ch_params* p, const lbm_ch_velocity*
   c->ztab = (float*)(c->ws + L.off_ztab);
   c->part = (double*)(c->ws + L.off_part);
   c->diag = (double*)(c->ws + L.off_diag);
+  c->xh = p->model == 3 ? (float*)(c->ws + L.off_xh) : nullptr;
   c->cur = 0;
   c->step = 0;
 
@@ -224,7 +227,7 @@ int lbm_ch_init(lbm_ch_ctx** out, const lbm_ch_params* p, const lbm_ch_velocity*
   k.phia = (float)p->phi_a;
   k.phib = (float)p->phi_b;
   k.eta = (float)eta;
-  k.k2 = p->model == 2 ? (float)(3.0 * cs2 * K) : 0.0f;
+  k.k2 = p->model >= 2 ? (float)(3.0 * cs2 * K) : 0.0f;
   k.a = (float)a;
   k.b = (float)b;
   k.omega = (float)(1.0 / p->tau_g);
@@ -235,6 +238,8 @@ int lbm_ch_init(lbm_ch_ctx** out, const lbm_ch_params* p, const lbm_ch_velocity*
   k.accel_x = ns ? (float)p->accel_x : 0.0f;
   k.rho_mean = (float)(0.5 * (p->rho_a + p->rho_b));
   k.aM = (float)(a * p->mobility);
+  k.x_f1 = (float)(2.0 * p->tau_g - 1.0 + 3.0 * K);
+  k.x_mu = (float)(3.0 * cs2 * eta * K);
 
   // Velocity inputs.  u = 0 is served by zero separable tables in the workspace.
   float* z = c->ztab;
@@ -327,7 +332,9 @@ static int run_steps(lbm_ch_ctx* c, int64_t nsteps, float* phi_out, hipStream_t 
                            phi_out + (size_t)s * c->p.nx * c->p.ny, stream);
       if (e != hipSuccess) return hip_fail(e);
     }
-    e = launch_phi_step(c->tx, walls, vmode, c->p.model == 2, c->p.storage, a, c->nblocks,
+    a.xh = c->xh;
+    a.xfirst = c->step == 0 ? 1 : 0;
+    e = launch_phi_step(c->tx, walls, vmode, c->p.model, c->p.storage, a, c->nblocks,
                         stream);
     if (e != hipSuccess) return hip_fail(e);
     c->cur = dst;
@@ -411,16 +418,20 @@ int64_t lbm_ch_step_count(const lbm_ch_ctx* c) { return live(c) ? c->step : -1; 
 size_t lbm_ch_state_bytes(const lbm_ch_ctx* c) {
   if (!live(c)) return 0;
   const size_t f = (size_t)9 * c->L.plane * sizeof(float);
-  return c->L.g_state + (c->p.velocity_mode == LBM_CH_VEL_NS ? f : 0);
+  const size_t x = (size_t)2 * c->p.nx * c->p.ny * sizeof(float);
+  return c->L.g_state + (c->p.velocity_mode == LBM_CH_VEL_NS ? f : 0) + (c->xh ? x : 0);
 }
 
 int lbm_ch_save_state(lbm_ch_ctx* c, void* dst, size_t bytes, hipStream_t stream) {
   if (!live(c)) return LBM_CH_ESTATE;
   if (!dst || bytes != lbm_ch_state_bytes(c)) return LBM_CH_EINVAL;
   const size_t g = c->L.g_state, f = (size_t)9 * c->L.plane * sizeof(float);
+  const size_t fo = c->f[0] ? f : 0, x = (size_t)2 * c->p.nx * c->p.ny * sizeof(float);
   hipError_t e = hipMemcpyAsync(dst, c->g[c->cur], g, hipMemcpyDeviceToDevice, stream);
   if (e == hipSuccess && c->f[0])
     e = hipMemcpyAsync((char*)dst + g, c->f[c->cur], f, hipMemcpyDeviceToDevice, stream);
+  if (e == hipSuccess && c->xh)
+    e = hipMemcpyAsync((char*)dst + g + fo, c->xh, x, hipMemcpyDeviceToDevice, stream);
   return e == hipSuccess ? LBM_CH_OK : hip_fail(e);
 }
 
@@ -429,9 +440,12 @@ int lbm_ch_load_state(lbm_ch_ctx* c, const void* src, size_t bytes, int64_t step
   if (!live(c)) return LBM_CH_ESTATE;
   if (!src || bytes != lbm_ch_state_bytes(c) || step < 0) return LBM_CH_EINVAL;
   const size_t g = c->L.g_state, f = (size_t)9 * c->L.plane * sizeof(float);
+  const size_t fo = c->f[0] ? f : 0, x = (size_t)2 * c->p.nx * c->p.ny * sizeof(float);
   hipError_t e = hipMemcpyAsync(c->g[c->cur], src, g, hipMemcpyDeviceToDevice, stream);
   if (e == hipSuccess && c->f[0])
     e = hipMemcpyAsync(c->f[c->cur], (const char*)src + g, f, hipMemcpyDeviceToDevice, stream);
+  if (e == hipSuccess && c->xh)
+    e = hipMemcpyAsync(c->xh, (const char*)src + g + fo, x, hipMemcpyDeviceToDevice, stream);
   if (e != hipSuccess) return hip_fail(e);
   c->step = step;
   return LBM_CH_OK;
@@ -520,7 +534,8 @@ int lbm_ch_adjoint(lbm_ch_ctx* c, int64_t n_end, int64_t nsteps, const float* ph
                    float* lam, float* grad_u, float* grad_v, void* scratch,
                    size_t scratch_bytes, hipStream_t stream) {
   if (!live(c)) return LBM_CH_ESTATE;
-  if (c->p.tau_g != 1.0 || c->p.walls != 0 || c->p.velocity_mode == LBM_CH_VEL_NS)
+  if (c->p.tau_g != 1.0 || c->p.walls != 0 || c->p.velocity_mode == LBM_CH_VEL_NS ||
+      c->p.model == 3)
     return LBM_CH_EUNSUPPORTED;
   if (nsteps < 0 || n_end < nsteps) return LBM_CH_EINVAL;
   if (nsteps == 0) return LBM_CH_OK;
@@ -766,7 +781,7 @@ int lbm_ch_batch_create(lbm_ch_batch** out, lbm_ch_ctx* const* ctxs, int32_t n,
     if (!live(c)) return LBM_CH_ESTATE;
     for (int32_t j = 0; j < i; ++j)
       if (ctxs[j] == c) return LBM_CH_EINVAL;
-    if (c->p.walls != 0 || c->p.storage != LBM_CH_STORE_F32 ||
+    if (c->p.walls != 0 || c->p.storage != LBM_CH_STORE_F32 || c->p.model == 3 ||
         c->p.velocity_mode == LBM_CH_VEL_NS || !c->tf.empty())
       return LBM_CH_EUNSUPPORTED;
   }

@@ -22,6 +22,9 @@ struct Coef {
   float srcf;       // 1 - 1/(2 tau_f)
   float gravity, accel_x, rho_mean;
   float aM;         // a * M, the factor of u lap(mu) in the NS force
+  // model 3 (Eq. F2-1): X = x_f1 F1 + x_mu grad mu, F2 = X(t_n) - X(t_{n-1}) + k2 grad D
+  float x_f1;       // 2 tau_g - 1 + 3K
+  float x_mu;       // 3 cs^2 eta K
 };
 
 // Arguments of the fused phase-field step.
@@ -39,6 +42,8 @@ struct StepArgs {
   // velocity field (u = tf ux, v = tf uy), and pressure field for the NS coupling
   const float *ux, *uy, *pf;
   float tf;
+  float* xh;          // model 3: X of the previous step (2 planes of nx*ny), rewritten
+  int xfirst;         // model 3: 1 on the first step (no earlier X: zero difference)
 };
 
 // Arguments of the batched step: one StepArgs per instance (src/dst as at parity 0),
@@ -70,7 +75,7 @@ enum VelMode { VEL_SEP = 0, VEL_FIELD = 1, VEL_NSFIELD = 2 };
 uint32_t population_bytes(int storage, uint32_t plane);
 
 // Launchers (return hipGetLastError() of the launch).
-hipError_t launch_phi_step(int tx, bool walls, int vmode, bool model2, int storage,
+hipError_t launch_phi_step(int tx, bool walls, int vmode, int model, int storage,
                            const StepArgs& a, int nblocks, hipStream_t s);
 // grid: a multiple of 8 workgroups; the kernel strides over the tiles.
 int phi_batch_blocks_per_cu(int tx, int vmode, bool model2);

@@ -244,14 +244,19 @@ struct RowRec {
   float lu, lv, lp;       // loaded velocity / pressure (field modes)
   float phi, lo, u, v;    // stage-1 results (u, v in the field modes)
   float fy_u, fy_v;       // separable mode: ay[y], by[y] as loaded, then times tf
+  float xpx, xpy;         // model 3: X of the previous step at this node
 };
 
 #ifndef WPE_PHI
 #define WPE_PHI 4
 #endif
 // One tile of the step: strip (L % nstrips) of TX columns, row chunk L / nstrips.
-template <int TX, bool WALLS, int VMODE, bool MODEL2, int ST>
+// MODEL 1: F = F1; 2: F = F1 + K grad(div(phi u)) (Eq. mark3); 3: Eq. F2-1 with the
+// time derivatives as one-step differences of X = cA F1 + cB grad mu, stored per node.
+template <int TX, bool WALLS, int VMODE, int MODEL, int ST>
 __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
+  constexpr bool MODEL2 = MODEL >= 2;
+  constexpr bool HIST = MODEL == 3;
   constexpr bool NSC = VMODE == VEL_NSFIELD;
   constexpr bool VFIELD = VMODE != VEL_SEP;
   constexpr int LW = TX + 4;
@@ -277,6 +282,8 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
     rv = make_rsrc(a.uy, nodes * 4u);
   }
   if (NSC) rp = make_rsrc(a.pf, nodes * 4u);
+  rsrc_t rxh;
+  if (HIST) rxh = make_rsrc(a.xh, 2u * nodes * 4u);
 
   const int t = threadIdx.x;
   const int x0 = (L % a.nstrips) * TX;
@@ -322,10 +329,14 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
 
   // Issue the pull of logical row r at one column (plus velocity and pressure in the
   // field modes) so that one wait covers all of it.
-  auto issue = [&](int r, uint32_t cc, uint32_t cm, uint32_t cp, RowRec& R) {
+  auto issue = [&](int r, uint32_t cc, uint32_t cm, uint32_t cp, RowRec& R, bool own = true) {
     float sg;
     const int sr = row_of<WALLS>(r, ny, sg);
     pull9<WALLS, ST>(rsrc, plane, nx, ny, sr, cc, cm, cp, R.g);
+    if (HIST && own) {
+      R.xpx = ldb(rxh, cc * 4u, (uint32_t)sr * rb);
+      R.xpy = ldb(rxh, cc * 4u, nodes * 4u + (uint32_t)sr * rb);
+    }
     if (VMODE == VEL_SEP) {
       // row factors of the separable velocity, fetched with the pull so that one wait
       // covers both (a later load would make the wait cover the whole prefetch)
@@ -390,6 +401,15 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
     }
     const float s1 = R.phi * rcp(rho);
     float fx = s1 * tx, fy = s1 * ty;
+    if (HIST) {  // (2 tau - 1 + 3K) dF1/dt + 3 cs^2 eta K d(grad mu)/dt of Eq. F2-1
+      const float xx = c.x_f1 * fx + c.x_mu * mux, xy = c.x_f1 * fy + c.x_mu * muy;
+      stb(rxh, xx, vc * 4u, (uint32_t)y * rb);
+      stb(rxh, xy, vc * 4u, nodes * 4u + (uint32_t)y * rb);
+      if (!a.xfirst) {
+        fx += xx - R.xpx;
+        fy += xy - R.xpy;
+      }
+    }
     if (MODEL2) {
       const float* dm = s_d[(y - 1) & 3];
       const float* d0 = s_d[y & 3];
@@ -421,21 +441,21 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
     stage1(y0 - 2 * d, T0, j, axc, bxc);
     stage1(y0 - d, T1, j, axc, bxc);
     if (hl) {
-      issue(y0 - 2 * d, hvc, hvm, hvp, T0);
-      issue(y0 - d, hvc, hvm, hvp, T1);
+      issue(y0 - 2 * d, hvc, hvm, hvp, T0, false);
+      issue(y0 - d, hvc, hvm, hvp, T1, false);
     }
     stage1(y0, A, j, axc, bxc);
     stage1(y0 + d, B, j, axc, bxc);
     if (hl) {
       stage1(y0 - 2 * d, T0, hj, axh, bxh);
       stage1(y0 - d, T1, hj, axh, bxh);
-      issue(y0, hvc, hvm, hvp, T0);
-      issue(y0 + d, hvc, hvm, hvp, T1);
+      issue(y0, hvc, hvm, hvp, T0, false);
+      issue(y0 + d, hvc, hvm, hvp, T1, false);
       stage1(y0, T0, hj, axh, bxh);
       stage1(y0 + d, T1, hj, axh, bxh);
     }
   }
-  issue(y0 + 2 * d, hvc, hvm, hvp, H0);
+  issue(y0 + 2 * d, hvc, hvm, hvp, H0, false);
   __builtin_amdgcn_sched_barrier(0);
   issue(y0 + 2 * d, vc, vm, vp, X0);
   __builtin_amdgcn_sched_barrier(0);
@@ -461,7 +481,7 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
     // would make each wait cover the other pull as well.
     __builtin_amdgcn_sched_barrier(0);
     stage1(y + 2 * d, H0, hj, axh, bxh, hl);
-    issue(ynext, hvc, hvm, hvp, H0);
+    issue(ynext, hvc, hvm, hvp, H0, false);
     __builtin_amdgcn_sched_barrier(0);
     issue(ynext, vc, vm, vp, N);
     __builtin_amdgcn_sched_barrier(0);
@@ -483,15 +503,18 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
   if (k < rows) row(k, X0, X1);
 }
 
-template <int TX, bool WALLS, int VMODE, bool MODEL2, int ST>
-__global__ void __launch_bounds__(TX) __attribute__((amdgpu_waves_per_eu(WPE_PHI, 8)))
+// Model 3 carries two more values per row record; it gets the register budget of
+// three waves per SIMD so that nothing spills.
+template <int TX, bool WALLS, int VMODE, int MODEL, int ST>
+__global__ void __launch_bounds__(TX)
+__attribute__((amdgpu_waves_per_eu(MODEL == 3 ? 3 : WPE_PHI, 8)))
 k_phi_step(const StepArgs a) {
   int L = blockIdx.x;
   if (a.xcd_remap) {  // workgroup w runs on XCD w % 8: give each XCD a band of chunks
     const int per = gridDim.x >> 3;
     L = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   }
-  phi_tile<TX, WALLS, VMODE, MODEL2, ST>(a, L);
+  phi_tile<TX, WALLS, VMODE, MODEL, ST>(a, L);
 }
 
 // Batched step: the tiles of many lattices (one instance table entry each) in one
@@ -526,7 +549,7 @@ k_phi_batch(const BatchArgs b) {
       a.src = a.dst;
       a.dst = const_cast<void*>(t);
     }
-    phi_tile<TX, false, VMODE, MODEL2, ST_F32>(a, v - b.start[inst]);
+    phi_tile<TX, false, VMODE, MODEL2 ? 2 : 1, ST_F32>(a, v - b.start[inst]);
     __syncthreads();  // the LDS rings are reused by the next tile
   }
 }
@@ -1051,11 +1074,15 @@ __global__ void __launch_bounds__(ATW * ATH) k_adjoint(const AdjArgs a) {
 }
 
 template <int TX, bool WALLS, int VMODE, int ST>
-hipError_t phi_step_m(bool model2, const StepArgs& a, int nb, hipStream_t s) {
-  if (model2)
-    hipLaunchKernelGGL((k_phi_step<TX, WALLS, VMODE, true, ST>), dim3(nb), dim3(TX), 0, s, a);
+hipError_t phi_step_m(int model, const StepArgs& a, int nb, hipStream_t s) {
+  if (model == 2)
+    hipLaunchKernelGGL((k_phi_step<TX, WALLS, VMODE, 2, ST>), dim3(nb), dim3(TX), 0, s, a);
+  else if (model == 1)
+    hipLaunchKernelGGL((k_phi_step<TX, WALLS, VMODE, 1, ST>), dim3(nb), dim3(TX), 0, s, a);
+  else if constexpr (ST == ST_F32)
+    hipLaunchKernelGGL((k_phi_step<TX, WALLS, VMODE, 3, ST>), dim3(nb), dim3(TX), 0, s, a);
   else
-    hipLaunchKernelGGL((k_phi_step<TX, WALLS, VMODE, false, ST>), dim3(nb), dim3(TX), 0, s, a);
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -1072,27 +1099,27 @@ hipError_t phi_batch_t(int vmode, bool model2, const BatchArgs& b, int grid, hip
 }
 
 template <int TX, bool WALLS, int ST>
-hipError_t phi_step_v(int vmode, bool model2, const StepArgs& a, int nb, hipStream_t s) {
+hipError_t phi_step_v(int vmode, int model, const StepArgs& a, int nb, hipStream_t s) {
   switch (vmode) {
-    case VEL_SEP: return phi_step_m<TX, WALLS, VEL_SEP, ST>(model2, a, nb, s);
-    case VEL_FIELD: return phi_step_m<TX, WALLS, VEL_FIELD, ST>(model2, a, nb, s);
-    default: return phi_step_m<TX, WALLS, VEL_NSFIELD, ST>(model2, a, nb, s);
+    case VEL_SEP: return phi_step_m<TX, WALLS, VEL_SEP, ST>(model, a, nb, s);
+    case VEL_FIELD: return phi_step_m<TX, WALLS, VEL_FIELD, ST>(model, a, nb, s);
+    default: return phi_step_m<TX, WALLS, VEL_NSFIELD, ST>(model, a, nb, s);
   }
 }
 
 template <int ST>
-hipError_t phi_step_t(int tx, bool walls, int vmode, bool model2, const StepArgs& a, int nb,
+hipError_t phi_step_t(int tx, bool walls, int vmode, int model, const StepArgs& a, int nb,
                       hipStream_t s) {
   switch (tx) {
     case 64:
-      return walls ? phi_step_v<64, true, ST>(vmode, model2, a, nb, s)
-                   : phi_step_v<64, false, ST>(vmode, model2, a, nb, s);
+      return walls ? phi_step_v<64, true, ST>(vmode, model, a, nb, s)
+                   : phi_step_v<64, false, ST>(vmode, model, a, nb, s);
     case 128:
-      return walls ? phi_step_v<128, true, ST>(vmode, model2, a, nb, s)
-                   : phi_step_v<128, false, ST>(vmode, model2, a, nb, s);
+      return walls ? phi_step_v<128, true, ST>(vmode, model, a, nb, s)
+                   : phi_step_v<128, false, ST>(vmode, model, a, nb, s);
     case 256:
-      return walls ? phi_step_v<256, true, ST>(vmode, model2, a, nb, s)
-                   : phi_step_v<256, false, ST>(vmode, model2, a, nb, s);
+      return walls ? phi_step_v<256, true, ST>(vmode, model, a, nb, s)
+                   : phi_step_v<256, false, ST>(vmode, model, a, nb, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1134,12 +1161,12 @@ void init_l(bool walls, int vmode, dim3 grid, hipStream_t s, const Coef& c, int 
 
 uint32_t population_bytes(int storage, uint32_t plane) { return pop_bytes(storage, plane); }
 
-hipError_t launch_phi_step(int tx, bool walls, int vmode, bool model2, int storage,
+hipError_t launch_phi_step(int tx, bool walls, int vmode, int model, int storage,
                            const StepArgs& a, int nblocks, hipStream_t s) {
   switch (storage) {
-    case ST_F32: return phi_step_t<ST_F32>(tx, walls, vmode, model2, a, nblocks, s);
-    case ST_F16: return phi_step_t<ST_F16>(tx, walls, vmode, model2, a, nblocks, s);
-    case ST_BF16: return phi_step_t<ST_BF16>(tx, walls, vmode, model2, a, nblocks, s);
+    case ST_F32: return phi_step_t<ST_F32>(tx, walls, vmode, model, a, nblocks, s);
+    case ST_F16: return phi_step_t<ST_F16>(tx, walls, vmode, model, a, nblocks, s);
+    case ST_BF16: return phi_step_t<ST_BF16>(tx, walls, vmode, model, a, nblocks, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -31,7 +31,7 @@ def _params(**kw):
     return lbm.make_params(64, 48, **kw)
 
 
-@pytest.mark.parametrize("bad", [dict(tau_g=0.5), dict(tau_g=0.2), dict(model=3),
+@pytest.mark.parametrize("bad", [dict(tau_g=0.5), dict(tau_g=0.2), dict(model=4), dict(model=0),
                                  dict(rho_a=0.0), dict(rho_b=-1.0), dict(phi_a=-1.0),
                                  dict(width=0.0), dict(walls=2), dict(velocity_mode=7),
                                  dict(ns=True, tau_f=0.5), dict(sigma=float("nan"))])
@@ -116,3 +116,10 @@ def test_adjoint_scratch_size():
     assert L.lbm_ch_adjoint_scratch_bytes(ctypes.byref(p)) == 96 * 40 * 4
     p.tau_g = 0.4
     assert L.lbm_ch_adjoint_scratch_bytes(ctypes.byref(p)) == 0
+
+
+def test_model3_workspace_holds_the_history():
+    L = lbm.lib()
+    a = L.lbm_ch_workspace_bytes(ctypes.byref(lbm.make_params(256, 256, model=2)))
+    b = L.lbm_ch_workspace_bytes(ctypes.byref(lbm.make_params(256, 256, model=3)))
+    assert b - a == 2 * 4 * 256 * 256
