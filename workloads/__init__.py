@@ -302,3 +302,67 @@ def batch_case(n_inst=64, seed=4, sides=(64, 128, 192, 256, 384, 512), modes=8, 
         U, V = random_stream_function(n, modes, seed * 1000 + 500 + i, umax)
         out.append(Workload("batch%d_%d" % (i, n), n, n, steps, phys, phi0, field=(U, V)))
     return out
+
+
+# ------------------------------------------------------------- the paper's setups
+
+def mobility_for_pe(pe, u_star, width, sigma, phi_a=1.0, phi_b=-1.0):
+    """M from Pe = U* W / (M beta (phi_A - phi_B)^2), beta of Eq. betakappa."""
+    d = abs(phi_a - phi_b)
+    beta = 12.0 * sigma / (width * d ** 4)
+    return u_star * width / (pe * beta * d * d)
+
+
+def slotted_disk(n, cx, cy, radius, slot_width, slot_top, width, phi_a=1.0, phi_b=-1.0):
+    """Zalesak's disk: a disk of phase A with a vertical slot of the given width cut
+    from its bottom up to y = cy + slot_top.  The signed distance is the minimum of the
+    disk's and the slot complement's (exact away from the slot corners)."""
+    y, x = np.mgrid[0:n, 0:n].astype(np.float64)
+    d_disk = radius - np.hypot(x - cx, y - cy)
+    # signed distance to the slot rectangle (positive inside it); the rectangle extends
+    # below the disk so only its top and sides bound the shape
+    hx = slot_width / 2.0
+    ybot = cy - 2.0 * radius
+    qx = np.abs(x - cx) - hx
+    qy = np.maximum(y - (cy + slot_top), ybot - y)
+    outside = np.hypot(np.maximum(qx, 0.0), np.maximum(qy, 0.0))
+    inside = np.minimum(np.maximum(qx, qy), 0.0)
+    d_slot = -(outside + inside)
+    return tanh_profile(np.minimum(d_disk, -d_slot), width, phi_a, phi_b)
+
+
+def paper_params(pe, u_star, width=2.0, sigma=0.01, tau_g=1.0, rho_a=1.0, rho_b=0.5, model=2):
+    return dict(tau_g=tau_g, mobility=mobility_for_pe(pe, u_star, width, sigma), sigma=sigma,
+                width=width, phi_a=1.0, phi_b=-1.0, rho_a=rho_a, rho_b=rho_b, model=model)
+
+
+def translation_paper(periods=1, tau_g=1.0, rho_b=0.5, model=2, n=200, u0=0.02, pe=200.0):
+    """Diagonal translation of Sec. III.A: L0 = 200, R = L0/5, U0 = 0.02 along (1, 1),
+    W = 2, sigma = 0.01, Pe = 200; one period is L0/U0 steps."""
+    steps = int(round(periods * n / u0))
+    phys = paper_params(pe, u0, tau_g=tau_g, rho_b=rho_b, model=model)
+    return Workload("translation_paper%d" % n, n, n, steps, phys,
+                    circle(n, n, n / 2, n / 2, n / 5.0, phys["width"]),
+                    uniform_velocity(n, n, u0, u0, steps))
+
+
+def zalesak(periods=2, model=2, n=200, radius=80.0, slot=16.0, u0=0.02, pe=200.0):
+    """Zalesak's disk of Sec. III.B: L0 = 200, R = 80, slot 16 wide reaching R/4 above the
+    centre, rigid rotation with U0 = 0.02 (period 2 L0 / U0), W = 2, sigma = 0.01,
+    Pe = 200, rho_A = 1, rho_B = 0.5."""
+    steps = int(round(periods * 2 * n / u0))
+    phys = paper_params(pe, u0, model=model)
+    return Workload("zalesak%d" % n, n, n, steps, phys,
+                    slotted_disk(n, n / 2, n / 2, radius, slot, radius / 4, phys["width"]),
+                    rigid_rotation(n, u0, steps))
+
+
+def shear_paper(model=2, n=200, u0=0.025, pe=1000.0):
+    """Circle in the reversing shear flow of Sec. III.C: L0 = 200, R = L0/5 at (100, 60),
+    U0 = 0.025, W = 2, Pe = 1000, reversed at T = L0 / U0, back at 2T."""
+    period = int(round(n / u0))
+    steps = 2 * period
+    phys = paper_params(pe, u0, model=model)
+    return Workload("shear_paper%d" % n, n, n, steps, phys,
+                    circle(n, n, 100.0 * n / 200, 60.0 * n / 200, n / 5.0, phys["width"]),
+                    shear_reversal(n, u0, period, steps))
