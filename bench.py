@@ -32,15 +32,20 @@ METRIC = ("MLUPS and % HBM peak (FP32 fused step, 2048^2) vs FP64 oracle accurac
           "adjoint ms")
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LU = 72.0
-KERNEL_SRC = os.path.join(ROOT, "paper_1805_00007_amd", "csrc", "lbm_ch_kernels.hip")
+# sources of the fused step kernel: a counter summary is used only while they are unchanged
+KERNEL_SRC = (os.path.join(ROOT, "paper_1805_00007_amd", "csrc", "lbm_ch_step.hip"),
+              os.path.join(ROOT, "paper_1805_00007_amd", "csrc", "lbm_ch_device.h"))
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "phi_step_vortex2048_traffic.txt")
 GOLDEN = os.path.join(ROOT, "tests", "golden", "vortex2048_oracle_1000.npz")
 ADJ_GOLDEN = os.path.join(ROOT, "tests", "golden", "adjoint256_oracle_2000.npz")
 
 
 def kernel_sha():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():

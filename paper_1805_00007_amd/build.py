@@ -3,27 +3,44 @@ from __future__ import annotations
 
 import os
 import subprocess
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblbm_ch.so")
-SOURCES = [os.path.join(HERE, "csrc", "lbm_ch_kernels.hip"),
+SOURCES = [os.path.join(HERE, "csrc", "lbm_ch_step.hip"),
+           os.path.join(HERE, "csrc", "lbm_ch_aux.hip"),
            os.path.join(HERE, "csrc", "lbm_ch_api.cpp")]
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          # no packed-FP32 instructions in the device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every source into liblbm_ch.so (always recompiles)."""
-    tmp = LIB + ".tmp"
-    cmd = ["hipcc", *FLAGS, *SOURCES, "-o", tmp]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + r.stderr)
-    if verbose and r.stderr:
-        print(r.stderr)
+    """Compile every source (in parallel) and link liblbm_ch.so (always recompiles)."""
+    with tempfile.TemporaryDirectory() as tmpdir:
+        objs, procs = [], []
+        for src in SOURCES:
+            obj = os.path.join(tmpdir, os.path.basename(src) + ".o")
+            objs.append(obj)
+            procs.append(subprocess.Popen(["hipcc", *FLAGS, "-c", src, "-o", obj],
+                                          stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                                          text=True))
+        errs = []
+        for src, p in zip(SOURCES, procs):
+            _, err = p.communicate()
+            if p.returncode != 0:
+                errs.append("%s:\n%s" % (src, err))
+            elif verbose and err:
+                print(err)
+        if errs:
+            raise RuntimeError("hipcc failed:\n" + "\n".join(errs))
+        tmp = LIB + ".tmp"
+        r = subprocess.run(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs,
+                            "-o", tmp], capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("link failed:\n" + r.stderr)
     os.replace(tmp, LIB)
     return LIB
 

@@ -1,0 +1,603 @@
+// gfx950 time-step kernels of the lattice Boltzmann Cahn-Hilliard solver
+// (Zhang, Guo & Liang, arXiv:1805.00007).  The public contract, the method and the
+// boundary rules are stated in include/lbm_ch.h; this file holds the fused phase-field
+// step (single lattice and batched) and the coupled Navier-Stokes step.
+//
+// The hot kernel, k_phi_step, is one fused pull-scheme update of all nine
+// phase-field populations.  A block owns a strip of TX columns and marches down TY
+// rows of it.  Per row it keeps three rolling rings in LDS:
+//   stage 1, row y+2: pull g_i(x) = g_i*(x - c_i), phi = sum g_i, q = phi u   (Eq. macroscopicg)
+//   stage 2, row y+1: mu = f'(phi) - kappa lap(phi), D = div q                 (Eqs. mu, mark3)
+//   stage 3, row y  : grad mu, grad D (and grad p), F = F1 + F2, g^eq, S, BGK,
+//                     store g*                                                 (Eqs. t0-phiu, mark3, geq, liangFi, LB)
+// so every value is computed once per node and the only HBM traffic is the nine
+// populations in and out (72 bytes per node update in float32).  The pops of a row
+// are pulled two iterations before they are collided and stay in registers; the
+// pull for the next row is issued before the barriers so that its latency overlaps
+// the stencil work.  Four lanes of the block also compute phi (and mu, D) of the
+// two halo columns on each side.  A row strip of the domain is handed to blocks in
+// an order that keeps a band of neighbouring strips on one XCD (one L2), so the
+// halo rows a block re-reads are L2 hits.
+#include "lbm_ch_device.h"
+
+namespace lbmch {
+namespace {
+
+// ---------------------------------------------------------------------------------
+// Fused phase-field step.
+//   VMODE VEL_SEP: u = tf ax[x] ay[y]; VEL_FIELD: u = tf ux[y][x];
+//   VEL_NSFIELD: u, p from the NS step, F1 = (phi/rho)(F_s + F_b - grad p).
+// One row record of the register pipeline: the pulled populations (plus velocity and
+// pressure in the field modes) and the order parameter and velocity of the row.
+struct RowRec {
+  float g[9];
+  float lu, lv, lp;       // loaded velocity / pressure (field modes)
+  float phi, lo, u, v;    // stage-1 results (u, v in the field modes)
+  float fy_u, fy_v;       // separable mode: ay[y], by[y] as loaded, then times tf
+  float xpx, xpy;         // model 3: X of the previous step at this node
+};
+
+#ifndef WPE_PHI
+#define WPE_PHI 4
+#endif
+// One tile of the step: strip (L % nstrips) of TX columns, row chunk L / nstrips.
+// MODEL 1: F = F1; 2: F = F1 + K grad(div(phi u)) (Eq. mark3); 3: Eq. F2-1 with the
+// time derivatives as one-step differences of X = cA F1 + cB grad mu, stored per node.
+template <int TX, bool WALLS, int VMODE, int MODEL, int ST>
+__device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
+  constexpr bool MODEL2 = MODEL >= 2;
+  constexpr bool HIST = MODEL == 3;
+  constexpr bool NSC = VMODE == VEL_NSFIELD;
+  constexpr bool VFIELD = VMODE != VEL_SEP;
+  constexpr int LW = TX + 4;
+  constexpr int QR = MODEL2 ? 4 : 1;
+  constexpr int PR = NSC ? 8 : 1;
+  __shared__ float s_phi[4][LW];
+  __shared__ float s_mu[4][LW];
+  __shared__ float s_qx[QR][LW];
+  __shared__ float s_qy[QR][LW];
+  __shared__ float s_d[QR][LW];
+  __shared__ float s_p[PR][LW];
+
+  const Coef& c = a.c;
+  const int nx = a.nx, ny = a.ny;
+  const uint32_t nodes = (uint32_t)nx * ny;
+  const uint32_t plane = a.plane;
+  const uint32_t rb = (uint32_t)nx * 4u;
+  const rsrc_t rsrc = make_rsrc(a.src, pop_bytes(ST, plane));
+  const rsrc_t rdst = make_rsrc(a.dst, pop_bytes(ST, plane));
+  rsrc_t ru, rv, rp;
+  if (VFIELD) {
+    ru = make_rsrc(a.ux, nodes * 4u);
+    rv = make_rsrc(a.uy, nodes * 4u);
+  }
+  if (NSC) rp = make_rsrc(a.pf, nodes * 4u);
+  rsrc_t rxh;
+  if (HIST) rxh = make_rsrc(a.xh, 2u * nodes * 4u);
+
+  const int t = threadIdx.x;
+  const int x0 = (L % a.nstrips) * TX;
+  const int chunk = L / a.nstrips;
+  const int rows = min(a.ty, ny - chunk * a.ty);
+  // Vertically adjacent chunks march in opposite directions, so the two blocks that
+  // share a chunk boundary pass it at the same moment (both at their start or both
+  // at their end) and the halo rows one re-reads are still in L2.
+  const int dir = (chunk & 1) ? -1 : 1;
+  const int y0 = dir > 0 ? chunk * a.ty : chunk * a.ty + rows - 1;  // first row marched
+
+  // Own column (wrapped) and its neighbours.
+  const int xl = x0 + t;
+  const bool active = xl < nx;
+  const int xc = xl % nx;
+  const uint32_t vc = xc;
+  const uint32_t vm = xc == 0 ? nx - 1 : xc - 1;
+  const uint32_t vp = xc == nx - 1 ? 0 : xc + 1;
+  // Halo lanes t < 4: logical columns x0-2, x0-1, x0+TX, x0+TX+1 -> LDS 0, 1, TX+2, TX+3.
+  const bool hl = t < 4;
+  const int hlog = t < 2 ? x0 - 2 + t : x0 + TX - 2 + t;
+  const int hc = ((hlog % nx) + nx) % nx;
+  // Every lane issues the halo pull, so that the wait-count bookkeeping does not depend
+  // on a branch; lanes other than the four halo lanes use an offset beyond the buffer,
+  // for which a raw buffer load returns 0 without accessing memory.
+  constexpr uint32_t OOB = 0x3FFFFFC0u;  // column index whose byte offset exceeds any buffer
+  const uint32_t hvc = hl ? hc : OOB;
+  const uint32_t hvm = hl ? (hc == 0 ? nx - 1 : hc - 1) : OOB;
+  const uint32_t hvp = hl ? (hc == nx - 1 ? 0 : hc + 1) : OOB;
+  const int hj = t < 2 ? t : TX + t;
+  const int j = t + 2;
+  const int j2 = t == 0 ? 1 : TX + 2;  // stage-2 halo column of lanes 0 and 1
+
+  float axc = 0.f, bxc = 0.f, axh = 0.f, bxh = 0.f;
+  if (VMODE == VEL_SEP) {
+    axc = a.ax[xc];
+    bxc = a.bx[xc];
+    if (hl) {
+      axh = a.ax[hc];
+      bxh = a.bx[hc];
+    }
+  }
+
+  // Issue the pull of logical row r at one column (plus velocity and pressure in the
+  // field modes) so that one wait covers all of it.
+  auto issue = [&](int r, uint32_t cc, uint32_t cm, uint32_t cp, RowRec& R, bool own = true) {
+    float sg;
+    const int sr = row_of<WALLS>(r, ny, sg);
+    pull9<WALLS, ST>(rsrc, plane, nx, ny, sr, cc, cm, cp, R.g);
+    if (HIST && own) {
+      R.xpx = ldb(rxh, cc * 4u, (uint32_t)sr * rb);
+      R.xpy = ldb(rxh, cc * 4u, nodes * 4u + (uint32_t)sr * rb);
+    }
+    if (VMODE == VEL_SEP) {
+      // row factors of the separable velocity, fetched with the pull so that one wait
+      // covers both (a later load would make the wait cover the whole prefetch)
+      R.fy_u = a.ay[sr];
+      R.fy_v = a.by[sr];
+    }
+    if (VFIELD) {
+      R.lu = ldb(ru, cc * 4u, (uint32_t)sr * rb);
+      R.lv = ldb(rv, cc * 4u, (uint32_t)sr * rb);
+      if (NSC) R.lp = ldb(rp, cc * 4u, (uint32_t)sr * rb);
+    }
+  };
+  // Stage 1 for logical row r: phi (and q = phi u, p) into the rings at column jj.
+  auto stage1 = [&](int r, RowRec& R, int jj, float axv, float bxv, bool wr = true) {
+    float sg;
+    row_of<WALLS>(r, ny, sg);
+    R.phi = sum9(R.g, R.lo);
+    float u, v;
+    if (VMODE == VEL_SEP) {
+      R.fy_u *= a.tf * sg;
+      R.fy_v *= a.tf * sg;
+      u = axv * R.fy_u;
+      v = bxv * R.fy_v;
+    } else {
+      u = R.u = a.tf * R.lu * sg;
+      v = R.v = a.tf * R.lv * sg;
+    }
+    if (!wr) return;
+    s_phi[r & 3][jj] = R.phi;
+    if (MODEL2) {
+      s_qx[r & 3][jj] = R.phi * u;
+      s_qy[r & 3][jj] = R.phi * v;
+    }
+    if (NSC) s_p[r & 7][jj] = R.lp;
+  };
+  // Stage 2 for logical row r at LDS column jj: mu (Eq. mu) and D = div(phi u).
+  auto stage2 = [&](int r, int jj) {
+    const float* pm = s_phi[(r - 1) & 3];
+    const float* p0 = s_phi[r & 3];
+    const float* pp = s_phi[(r + 1) & 3];
+    s_mu[r & 3][jj] = mu_bulk(c, p0[jj]) - c.kappa * lap9(pm, p0, pp, jj);
+    if (MODEL2) {
+      s_d[r & 3][jj] = ddx(s_qx[(r - 1) & 3], s_qx[r & 3], s_qx[(r + 1) & 3], jj) +
+                       ddy(s_qy[(r - 1) & 3], s_qy[r & 3], s_qy[(r + 1) & 3], jj);
+    }
+  };
+  // Stage 3 for lattice row y: F = F1 (+ F2), collision, store.
+  auto stage3 = [&](int y, RowRec& R) {
+    if (!active) return;
+    const float* mm = s_mu[(y - 1) & 3];
+    const float* m0 = s_mu[y & 3];
+    const float* mp = s_mu[(y + 1) & 3];
+    const float mux = ddx(mm, m0, mp, j), muy = ddy(mm, m0, mp, j);
+    const float rho = c.a * R.phi + c.b;
+    float tx = -R.phi * mux, ty = -R.phi * muy;
+    if (NSC) {
+      const float* qm = s_p[(y - 1) & 7];
+      const float* q0 = s_p[y & 7];
+      const float* qp = s_p[(y + 1) & 7];
+      tx += rho * c.accel_x - ddx(qm, q0, qp, j);
+      ty += -(rho - c.rho_mean) * c.gravity - ddy(qm, q0, qp, j);
+    }
+    const float s1 = R.phi * rcp(rho);
+    float fx = s1 * tx, fy = s1 * ty;
+    if (HIST) {  // (2 tau - 1 + 3K) dF1/dt + 3 cs^2 eta K d(grad mu)/dt of Eq. F2-1
+      const float xx = c.x_f1 * fx + c.x_mu * mux, xy = c.x_f1 * fy + c.x_mu * muy;
+      stb(rxh, xx, vc * 4u, (uint32_t)y * rb);
+      stb(rxh, xy, vc * 4u, nodes * 4u + (uint32_t)y * rb);
+      if (!a.xfirst) {
+        fx += xx - R.xpx;
+        fy += xy - R.xpy;
+      }
+    }
+    if (MODEL2) {
+      const float* dm = s_d[(y - 1) & 3];
+      const float* d0 = s_d[y & 3];
+      const float* dp = s_d[(y + 1) & 3];
+      fx += c.k2 * ddx(dm, d0, dp, j);
+      fy += c.k2 * ddy(dm, d0, dp, j);
+    }
+    const float u = VMODE == VEL_SEP ? axc * R.fy_u : R.u;
+    const float v = VMODE == VEL_SEP ? bxc * R.fy_v : R.v;
+    collide_g(c, R.phi, R.lo, m0[j], u, v, fx, fy, R.g);
+    finish_store<ST>(rdst, plane, nx, vc, (uint32_t)y, (double)R.phi + (double)R.lo, R.g);
+  };
+
+  // Prologue: rows y0-2d .. y0+d through stage 1, rows y0-d and y0 through stage 2,
+  // and the pull of row y0+2d in flight (d = dir).
+  //
+  // Register pipeline.  A holds row y (collided in stage 3), B row y+d; the pull of
+  // the next row lands in one of two slots, X0 or X1, which alternate, so registers
+  // with a load in flight are never copied (copying them would make the wave wait for
+  // every outstanding memory operation).  Completed rows move down A <- B <- X by copy.
+  const int d = dir;
+  RowRec A, B, X0, X1, H0;
+  {
+    RowRec T0, T1;
+    issue(y0 - 2 * d, vc, vm, vp, T0);
+    issue(y0 - d, vc, vm, vp, T1);
+    issue(y0, vc, vm, vp, A);
+    issue(y0 + d, vc, vm, vp, B);
+    stage1(y0 - 2 * d, T0, j, axc, bxc);
+    stage1(y0 - d, T1, j, axc, bxc);
+    if (hl) {
+      issue(y0 - 2 * d, hvc, hvm, hvp, T0, false);
+      issue(y0 - d, hvc, hvm, hvp, T1, false);
+    }
+    stage1(y0, A, j, axc, bxc);
+    stage1(y0 + d, B, j, axc, bxc);
+    if (hl) {
+      stage1(y0 - 2 * d, T0, hj, axh, bxh);
+      stage1(y0 - d, T1, hj, axh, bxh);
+      issue(y0, hvc, hvm, hvp, T0, false);
+      issue(y0 + d, hvc, hvm, hvp, T1, false);
+      stage1(y0, T0, hj, axh, bxh);
+      stage1(y0 + d, T1, hj, axh, bxh);
+    }
+  }
+  issue(y0 + 2 * d, hvc, hvm, hvp, H0, false);
+  __builtin_amdgcn_sched_barrier(0);
+  issue(y0 + 2 * d, vc, vm, vp, X0);
+  __builtin_amdgcn_sched_barrier(0);
+  __syncthreads();
+  stage2(y0 - d, j);
+  stage2(y0, j);
+  if (t < 2) {
+    stage2(y0 - d, j2);
+    stage2(y0, j2);
+  }
+  __syncthreads();
+
+  // One marching row: issue row y+3d into slot N, stage 1 of row y+2d from slot C
+  // (pulled one row earlier), stage 2 of row y+d, stage 3 of row y.  On a block's last
+  // row the pull of y+3d is not needed; it is clamped to the last row the block does
+  // need (already in cache), so the pipeline has no branch and fetches nothing extra.
+  const int last_needed = y0 + (rows + 1) * d;
+  auto row = [&](int k, RowRec& C, RowRec& N) {
+    const int y = y0 + k * d;
+    const int ynext = k + 1 < rows ? y + 3 * d : last_needed;
+    // Halo first: its pull was issued before C's, so waiting for it leaves C in flight.
+    // The scheduling barriers keep the compiler from interleaving the two pulls, which
+    // would make each wait cover the other pull as well.
+    __builtin_amdgcn_sched_barrier(0);
+    stage1(y + 2 * d, H0, hj, axh, bxh, hl);
+    issue(ynext, hvc, hvm, hvp, H0, false);
+    __builtin_amdgcn_sched_barrier(0);
+    issue(ynext, vc, vm, vp, N);
+    __builtin_amdgcn_sched_barrier(0);
+    stage1(y + 2 * d, C, j, axc, bxc);
+    __syncthreads();
+    stage2(y + d, j);
+    if (t < 2) stage2(y + d, j2);
+    __syncthreads();
+    stage3(y, A);
+    A = B;
+    B = C;
+  };
+  int k = 0;
+#pragma unroll 1
+  for (; k + 2 <= rows; k += 2) {
+    row(k, X0, X1);
+    row(k + 1, X1, X0);
+  }
+  if (k < rows) row(k, X0, X1);
+}
+
+// Model 3 carries two more values per row record; it gets the register budget of
+// three waves per SIMD so that nothing spills.
+template <int TX, bool WALLS, int VMODE, int MODEL, int ST>
+__global__ void __launch_bounds__(TX)
+__attribute__((amdgpu_waves_per_eu(MODEL == 3 ? 3 : WPE_PHI, 8)))
+k_phi_step(const StepArgs a) {
+  int L = blockIdx.x;
+  if (a.xcd_remap) {  // workgroup w runs on XCD w % 8: give each XCD a band of chunks
+    const int per = gridDim.x >> 3;
+    L = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  }
+  phi_tile<TX, WALLS, VMODE, MODEL, ST>(a, L);
+}
+
+// Batched step: the tiles of many lattices (one instance table entry each) in one
+// persistent launch.  The tiles are numbered instance by instance; XCD x (workgroups
+// w with w % 8 == x) owns the contiguous range [x per, (x + 1) per) and its workgroups
+// stride through it, so vertically adjacent tiles of one lattice share that XCD's L2.
+// Every workgroup leaves the loop after at most ceil(per / slots) tiles.
+#ifndef WPE_BATCH
+#define WPE_BATCH 3
+#endif
+template <int TX, int VMODE, bool MODEL2>
+__global__ void __launch_bounds__(TX) __attribute__((amdgpu_waves_per_eu(WPE_BATCH, 8)))
+k_phi_batch(const BatchArgs b) {
+  const int slots = gridDim.x >> 3;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int per = (b.total + 7) >> 3;
+  const int lo = xcd * per, hi = min(b.total, lo + per);
+  int v = lo + slot;
+  if (v >= hi) return;
+  int lo_i = 0, hi_i = b.n;  // instance of tile v: start[inst] <= v < start[inst + 1]
+  while (hi_i - lo_i > 1) {
+    const int mid = (lo_i + hi_i) >> 1;
+    if (b.start[mid] <= v) lo_i = mid; else hi_i = mid;
+  }
+  int inst = lo_i;
+#pragma unroll 1
+  for (; v < hi; v += slots) {
+    while (b.start[inst + 1] <= v) ++inst;
+    StepArgs a = b.args[inst];
+    if (b.parity) {
+      const void* t = a.src;
+      a.src = a.dst;
+      a.dst = const_cast<void*>(t);
+    }
+    phi_tile<TX, false, VMODE, MODEL2 ? 2 : 1, ST_F32>(a, v - b.start[inst]);
+    __syncthreads();  // the LDS rings are reused by the next tile
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Coupled Navier-Stokes step (pressure-based incompressible D2Q9 BGK, see lbm_ch.h).
+// Same marching layout: stage 1 pulls g for phi, stage 2 computes mu, stage 3 pulls
+// f, forms the force, velocity and pressure, writes u, v, p and (if fdst) collides
+// and stores f.
+template <int TX, bool WALLS, int ST>
+__global__ void __launch_bounds__(TX) k_ns_step(const NsArgs a) {
+  constexpr int LW = TX + 4;
+  __shared__ float s_phi[8][LW];
+  __shared__ float s_mu[4][LW];
+  const Coef& c = a.c;
+  const int nx = a.nx, ny = a.ny;
+  const uint32_t nodes = (uint32_t)nx * ny;
+  const uint32_t pb = a.plane * 4u;
+  const rsrc_t rg = make_rsrc(a.gsrc, pop_bytes(ST, a.plane));
+  const rsrc_t rf = make_rsrc(a.fsrc, 9u * pb);
+  const rsrc_t rfd = make_rsrc(a.fdst, a.fdst ? 9u * pb : 0u);
+  const rsrc_t ru = make_rsrc(a.u, nodes * 4u);
+  const rsrc_t rv = make_rsrc(a.v, nodes * 4u);
+  const rsrc_t rpr = make_rsrc(a.p, nodes * 4u);
+  const int t = threadIdx.x;
+  int L = blockIdx.x;
+  if (a.xcd_remap) {
+    const int per = gridDim.x >> 3;
+    L = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  }
+  const int x0 = (L % a.nstrips) * TX;
+  const int y0 = (L / a.nstrips) * a.ty;
+  const int rows = min(a.ty, ny - y0);
+  const int xl = x0 + t;
+  const bool active = xl < nx;
+  const int xc = xl % nx;
+  const int xm = xc == 0 ? nx - 1 : xc - 1;
+  const int xp = xc == nx - 1 ? 0 : xc + 1;
+  const bool hl = t < 4;
+  const int hlog = t < 2 ? x0 - 2 + t : x0 + TX - 2 + t;
+  const int hc = ((hlog % nx) + nx) % nx;
+  const int hm = hc == 0 ? nx - 1 : hc - 1;
+  const int hp = hc == nx - 1 ? 0 : hc + 1;
+  const int hj = t < 2 ? t : TX + t;
+  const int j = t + 2;
+  const int j2 = t == 0 ? 1 : TX + 2;
+
+  const uint32_t rb = (uint32_t)nx * 4u;
+  auto phi_at = [&](int r, int col, int cm, int cq) {
+    float sg, g[9];
+    const int sr = row_of<WALLS>(r, ny, sg);
+    pull9<WALLS, ST>(rg, a.plane, nx, ny, sr, col, cm, cq, g);
+    return sum9(g);
+  };
+  auto stage2 = [&](int r, int jj) {
+    const float* pm = s_phi[(r - 1) & 7];
+    const float* p0 = s_phi[r & 7];
+    const float* pp = s_phi[(r + 1) & 7];
+    s_mu[r & 3][jj] = mu_bulk(c, p0[jj]) - c.kappa * lap9(pm, p0, pp, jj);
+  };
+
+#pragma unroll 1
+  for (int r = y0 - 2; r <= y0 + 1; ++r) {
+    s_phi[r & 7][j] = phi_at(r, xc, xm, xp);
+    if (hl) s_phi[r & 7][hj] = phi_at(r, hc, hm, hp);
+  }
+  __syncthreads();
+  stage2(y0 - 1, j);
+  stage2(y0, j);
+  if (t < 2) {
+    stage2(y0 - 1, j2);
+    stage2(y0, j2);
+  }
+  float fpop[9];
+  pull9<WALLS, ST_F32>(rf, a.plane, nx, ny, y0, xc, xm, xp, fpop);
+  __syncthreads();
+
+#pragma unroll 1
+  for (int k = 0; k < rows; ++k) {
+    const int y = y0 + k;
+    float fnext[9];
+    if (k + 1 < rows) pull9<WALLS, ST_F32>(rf, a.plane, nx, ny, y + 1, xc, xm, xp, fnext);
+    s_phi[(y + 2) & 7][j] = phi_at(y + 2, xc, xm, xp);
+    if (hl) s_phi[(y + 2) & 7][hj] = phi_at(y + 2, hc, hm, hp);
+    __syncthreads();
+    stage2(y + 1, j);
+    if (t < 2) stage2(y + 1, j2);
+    __syncthreads();
+    if (active) {
+      const float* pm = s_phi[(y - 1) & 7];
+      const float* p0 = s_phi[y & 7];
+      const float* pp = s_phi[(y + 1) & 7];
+      const float* mm = s_mu[(y - 1) & 3];
+      const float* m0 = s_mu[y & 3];
+      const float* mp = s_mu[(y + 1) & 3];
+      const float phi = p0[j];
+      const float rho = c.a * phi + c.b;
+      const float fsx = -phi * ddx(mm, m0, mp, j), fsy = -phi * ddy(mm, m0, mp, j);
+      const float fbx = rho * c.accel_x, fby = -(rho - c.rho_mean) * c.gravity;
+      const float corr = c.aM * lap9(mm, m0, mp, j);
+      float mx = 0.f, my = 0.f, s = 0.f;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        mx += CX[i] * fpop[i];
+        my += CY[i] * fpop[i];
+        if (i > 0) s += fpop[i];
+      }
+      const float inv = rcp(rho - 0.5f * corr);
+      const float u = (mx + 0.5f * (fsx + fbx)) * inv;
+      const float v = (my + 0.5f * (fsy + fby)) * inv;
+      const float Fx = fsx + fbx + u * corr, Fy = fsy + fby + v * corr;
+      const float drx = c.a * ddx(pm, p0, pp, j), dry = c.a * ddy(pm, p0, pp, j);
+      const float usq15 = 1.5f * (u * u + v * v);
+      // p = cs^2/(1 - w0) [sum_{i>0} f_i + u.grad rho / 2 + rho w0 s_0(u)], cs^2/(1-w0) = 3/5
+      const float pr = 0.6f * (s + 0.5f * (u * drx + v * dry) - WT[0] * rho * usq15);
+      const uint32_t off = xc * 4u, ro = (uint32_t)y * rb;
+      stb(ru, u, off, ro);
+      stb(rv, v, off, ro);
+      stb(rpr, pr, off, ro);
+      if (a.fdst) {
+        const float om = c.omega_f, om1 = 1.0f - om;
+        const float p3 = 3.0f * pr;  // p / cs^2
+        const float uF = u * Fx + v * Fy;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          const float cu = CX[i] * u + CY[i] * v;
+          const float cF = CX[i] * Fx + CY[i] * Fy;
+          const float cr = CX[i] * drx + CY[i] * dry;
+          const float su = cu * (3.0f + 4.5f * cu) - usq15;
+          const float feq = WT[i] * (p3 + rho * su) - (i == 0 ? p3 : 0.0f);
+          const float G = WT[i] * (3.0f * (cF - uF) + 9.0f * cu * cF + 3.0f * cu * cr);
+          stb(rfd, om1 * fpop[i] + om * feq + c.srcf * G, off, i * pb + ro);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fpop[i] = fnext[i];
+  }
+}
+
+template <int TX, bool WALLS, int VMODE, int ST>
+hipError_t phi_step_m(int model, const StepArgs& a, int nb, hipStream_t s) {
+  if (model == 2)
+    hipLaunchKernelGGL((k_phi_step<TX, WALLS, VMODE, 2, ST>), dim3(nb), dim3(TX), 0, s, a);
+  else if (model == 1)
+    hipLaunchKernelGGL((k_phi_step<TX, WALLS, VMODE, 1, ST>), dim3(nb), dim3(TX), 0, s, a);
+  else if constexpr (ST == ST_F32)
+    hipLaunchKernelGGL((k_phi_step<TX, WALLS, VMODE, 3, ST>), dim3(nb), dim3(TX), 0, s, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <int TX>
+hipError_t phi_batch_t(int vmode, bool model2, const BatchArgs& b, int grid, hipStream_t s) {
+  if (vmode == VEL_SEP) {
+    if (model2) hipLaunchKernelGGL((k_phi_batch<TX, VEL_SEP, true>), dim3(grid), dim3(TX), 0, s, b);
+    else hipLaunchKernelGGL((k_phi_batch<TX, VEL_SEP, false>), dim3(grid), dim3(TX), 0, s, b);
+  } else {
+    if (model2) hipLaunchKernelGGL((k_phi_batch<TX, VEL_FIELD, true>), dim3(grid), dim3(TX), 0, s, b);
+    else hipLaunchKernelGGL((k_phi_batch<TX, VEL_FIELD, false>), dim3(grid), dim3(TX), 0, s, b);
+  }
+  return hipGetLastError();
+}
+
+template <int TX, bool WALLS, int ST>
+hipError_t phi_step_v(int vmode, int model, const StepArgs& a, int nb, hipStream_t s) {
+  switch (vmode) {
+    case VEL_SEP: return phi_step_m<TX, WALLS, VEL_SEP, ST>(model, a, nb, s);
+    case VEL_FIELD: return phi_step_m<TX, WALLS, VEL_FIELD, ST>(model, a, nb, s);
+    default: return phi_step_m<TX, WALLS, VEL_NSFIELD, ST>(model, a, nb, s);
+  }
+}
+
+template <int ST>
+hipError_t phi_step_t(int tx, bool walls, int vmode, int model, const StepArgs& a, int nb,
+                      hipStream_t s) {
+  switch (tx) {
+    case 64:
+      return walls ? phi_step_v<64, true, ST>(vmode, model, a, nb, s)
+                   : phi_step_v<64, false, ST>(vmode, model, a, nb, s);
+    case 128:
+      return walls ? phi_step_v<128, true, ST>(vmode, model, a, nb, s)
+                   : phi_step_v<128, false, ST>(vmode, model, a, nb, s);
+    case 256:
+      return walls ? phi_step_v<256, true, ST>(vmode, model, a, nb, s)
+                   : phi_step_v<256, false, ST>(vmode, model, a, nb, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int TX, int ST>
+void ns_step_l(bool walls, const NsArgs& a, int nb, hipStream_t s) {
+  if (walls) hipLaunchKernelGGL((k_ns_step<TX, true, ST>), dim3(nb), dim3(TX), 0, s, a);
+  else hipLaunchKernelGGL((k_ns_step<TX, false, ST>), dim3(nb), dim3(TX), 0, s, a);
+}
+
+template <int ST>
+hipError_t ns_step_t(int tx, bool walls, const NsArgs& a, int nb, hipStream_t s) {
+  switch (tx) {
+    case 64: ns_step_l<64, ST>(walls, a, nb, s); break;
+    case 128: ns_step_l<128, ST>(walls, a, nb, s); break;
+    case 256: ns_step_l<256, ST>(walls, a, nb, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_phi_step(int tx, bool walls, int vmode, int model, int storage,
+                           const StepArgs& a, int nblocks, hipStream_t s) {
+  switch (storage) {
+    case ST_F32: return phi_step_t<ST_F32>(tx, walls, vmode, model, a, nblocks, s);
+    case ST_F16: return phi_step_t<ST_F16>(tx, walls, vmode, model, a, nblocks, s);
+    case ST_BF16: return phi_step_t<ST_BF16>(tx, walls, vmode, model, a, nblocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int phi_batch_blocks_per_cu(int tx, int vmode, bool model2) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  const bool sep = vmode == VEL_SEP;
+#define LBM_OCC(T)                                                                          \
+  e = sep ? (model2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phi_batch<T, VEL_SEP, true>, T, 0)    \
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phi_batch<T, VEL_SEP, false>, T, 0))   \
+          : (model2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phi_batch<T, VEL_FIELD, true>, T, 0)  \
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phi_batch<T, VEL_FIELD, false>, T, 0))
+  switch (tx) {
+    case 64: LBM_OCC(64); break;
+    case 128: LBM_OCC(128); break;
+    case 256: LBM_OCC(256); break;
+    default: break;
+  }
+#undef LBM_OCC
+  return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
+hipError_t launch_phi_batch(int tx, int vmode, bool model2, const BatchArgs& b, int grid,
+                            hipStream_t s) {
+  if (grid <= 0 || (grid & 7) != 0 || b.n <= 0) return hipErrorInvalidValue;
+  switch (tx) {
+    case 64: return phi_batch_t<64>(vmode, model2, b, grid, s);
+    case 128: return phi_batch_t<128>(vmode, model2, b, grid, s);
+    case 256: return phi_batch_t<256>(vmode, model2, b, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_ns_step(int tx, bool walls, int storage, const NsArgs& a, int nblocks,
+                          hipStream_t s) {
+  switch (storage) {
+    case ST_F32: return ns_step_t<ST_F32>(tx, walls, a, nblocks, s);
+    case ST_F16: return ns_step_t<ST_F16>(tx, walls, a, nblocks, s);
+    case ST_BF16: return ns_step_t<ST_BF16>(tx, walls, a, nblocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace lbmch
