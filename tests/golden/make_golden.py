@@ -8,6 +8,7 @@ the final extrema.
     python tests/golden/make_golden.py vortex2048     # 2048^2, 1000 steps
     python tests/golden/make_golden.py vortex512      # 512^2, one period T = 20000
     python tests/golden/make_golden.py rt256          # 256x1024 Rayleigh-Taylor, 1000 steps
+    python tests/golden/make_golden.py rt256_4000     # the same after 4000 steps (0.44 T)
     python tests/golden/make_golden.py adjoint256     # 256^2, 2000 steps: target + FD gradients
 
 The adjoint case stores the target field phi_target (the oracle run with the held-out
@@ -31,6 +32,7 @@ CASES = {
     "vortex2048": (lambda: workloads.metric2048(steps=1000), 1000, 0),
     "vortex512": (lambda: workloads.vortex(512, period=20000), 20000, 0),
     "rt256": (lambda: workloads.rayleigh_taylor_case(256, 1024, steps=1000), 1000, 1),
+    "rt256_4000": (lambda: workloads.rayleigh_taylor_case(256, 1024, steps=4000), 4000, 1),
 }
 
 
@@ -51,7 +53,7 @@ def make(name):
     d = oracle.diag(p, phi, w.phi0)
     rng = np.random.default_rng(20240601)
     idx = np.sort(rng.choice(w.nx * w.ny, size=4096, replace=False))
-    out = os.path.join(HERE, "%s_oracle_%d.npz" % (name, steps))
+    out = os.path.join(HERE, "%s_oracle_%d.npz" % (name.split("_")[0], steps))
     np.savez_compressed(out, steps=steps, index=idx, phi=phi.ravel()[idx],
                         mass0=d0["mass"], abs_mass0=d0["abs_mass"], mass=d["mass"],
                         e_phi=np.sqrt(d["err2"] / d["ref2"]), max=d["max"], min=d["min"],

@@ -80,3 +80,27 @@ def test_ns_walls_equal_mirrored_periodic_domain():
     np.testing.assert_allclose(fa[0], fb[0][:ny], atol=1e-14)      # phi
     np.testing.assert_allclose(fa[3], fb[3][:ny], atol=1e-15)      # v
     np.testing.assert_allclose(fa[4], fb[4][:ny], atol=1e-14)      # p
+
+
+def test_translating_density_interface_converges():
+    """Variable-density terms of the NS step (the u.grad rho parts of the forcing and of
+    the pressure): two layers of density ratio 3 moving with a uniform velocity are an
+    exact solution (u = u0, div u = 0, constant p).  The lattice keeps it up to a
+    discretisation error that falls with the interface width W: div u at second order
+    (the interface gradients are resolved over W nodes), u - u0 at least at first order.
+    A wrong sign or factor in those terms leaves an O(u0) error that does not shrink."""
+    errs = []
+    for W in (4.0, 8.0, 16.0):
+        n = int(16 * W)
+        x = np.arange(n)[None, :] * np.ones((8, 1))
+        d = np.minimum(x - n / 4, 3 * n / 4 - x)
+        phi0 = np.tanh(2 * d / W)
+        p = oracle.Params(nx=n, ny=8, ns=1, tau_g=1.0, mobility=0.01, sigma=1e-4, width=W,
+                          rho_a=1.0, rho_b=1 / 3, tau_f=0.8, gravity=0.0, model=2)
+        s = oracle.State(p, phi0, np.full((8, n), 0.02), np.zeros((8, n))).run(int(20 * W))
+        _, _, u, v, _ = s.fields()
+        div = (np.roll(u, -1, 1) - np.roll(u, 1, 1)) / 2 + (np.roll(v, -1, 0) - np.roll(v, 1, 0)) / 2
+        errs.append((np.abs(u - 0.02).max(), np.abs(div).max()))
+    (u4, d4), (u8, d8), (u16, d16) = errs
+    assert d4 / d8 > 3.5 and d8 / d16 > 3.5
+    assert u4 / u16 > 3.0 and u16 < 0.025 * 0.02
