@@ -137,7 +137,9 @@ def storage_variant(lbm, torch, storage, steps):
 def adjoint_leg(lbm, torch, reps=3):
     """One forward plus backward pass of the 256^2, 2000-step interface-matching problem
     (16 stream-function coefficients, sqrt(N) checkpointing), against the plain forward
-    run of the same workload, and its gradients against stored FP64 central differences."""
+    run of the same workload, and its gradients against stored FP64 central differences.
+    Both run on the tile shape the autotuner picks for this lattice (tuned once, not
+    timed)."""
     import numpy as np
     import workloads
     from paper_1805_00007_amd.adjoint import evolve
@@ -151,8 +153,13 @@ def adjoint_leg(lbm, torch, reps=3):
     basis = torch.tensor(case.basis, dtype=torch.float32, device=dev)
     U, V = case.field()
 
+    probe = lbm.Solver(case.n, case.n, case.phi0, field=(U, V), device=dev, **case.phys)
+    tiles, _ = probe.autotune(5)
+    probe.close()
+
     def plain():
         s = lbm.Solver(case.n, case.n, case.phi0, field=(U, V), device=dev, **case.phys)
+        s.set_tiles(*tiles)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.step(steps)
@@ -167,7 +174,7 @@ def adjoint_leg(lbm, torch, reps=3):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         uv = case.scale * torch.tensordot(theta, basis, dims=1)
-        phi = evolve(phi0, uv[0], uv[1], steps, **case.phys)
+        phi = evolve(phi0, uv[0], uv[1], steps, tiles=tiles, **case.phys)
         loss = ((phi - target) ** 2).sum()
         loss.backward()
         torch.cuda.synchronize()
@@ -187,6 +194,7 @@ def adjoint_leg(lbm, torch, reps=3):
             "forward_ms_plain": round(t_plain * 1e3, 2),
             "ratio_to_plain_forward": round(t_adj / t_plain, 2),
             "checkpoints": -(-steps // (int(np.ceil(np.sqrt(steps))))),
+            "tiles": {"tx": tiles[0], "ty": tiles[1]},
             "loss_rel_err": abs(loss - float(g["loss"])) / float(g["loss"]),
             "grad_theta_rel_err": float(np.linalg.norm(gt - ref_t) / np.linalg.norm(ref_t)),
             "grad_phi0_rel_err": float(np.linalg.norm(gp.ravel()[g["phi0_index"]] - ref_p)

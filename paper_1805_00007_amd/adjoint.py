@@ -24,11 +24,15 @@ from . import Solver
 
 class _Evolve(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, phi0, U, V, steps, segment, tf, params):
+    def forward(ctx, phi0, U, V, steps, segment, tf, params, tune):
         ny, nx = phi0.shape
         s = Solver(nx, ny, phi0.detach(), field=(U.detach(), V.detach()), tf=tf,
                    device=phi0.device, **params)
         s.stream.wait_stream(torch.cuda.current_stream(phi0.device))
+        if isinstance(tune, tuple):
+            s.set_tiles(*tune)
+        elif tune:
+            s.autotune(trial_steps=tune)
         seg = int(segment) if segment else max(1, math.isqrt(max(steps - 1, 0)) + 1)
         ckpts = []
         n = 0
@@ -60,13 +64,17 @@ class _Evolve(torch.autograd.Function):
                 s.record(k, traj)
                 s.adjoint(n0 + k, k, traj, lam, gu, gv, scratch)
         torch.cuda.current_stream(dev).wait_stream(s.stream)
-        return lam, gu, gv, None, None, None, None
+        return lam, gu, gv, None, None, None, None, None
 
 
-def evolve(phi0, U, V, steps, *, tf=None, segment=None, **params):
+def evolve(phi0, U, V, steps, *, tf=None, segment=None, autotune=0, tiles=None, **params):
     """phi after ``steps`` steps from ``phi0`` (ny, nx) in the velocity field tf[n] (U, V),
     differentiable in phi0, U and V.  ``params`` are those of ``lbm_ch_params``; the
-    derivative needs tau_g = 1, periodic boundaries and a prescribed velocity."""
+    derivative needs tau_g = 1, periodic boundaries and a prescribed velocity.
+    ``tiles=(tx, ty)`` fixes the step kernels' tile shape; otherwise ``autotune`` > 0
+    times that many trial steps per tile shape first (the state is restored; the
+    forward run and its recomputation then use the fastest shape)."""
     if float(params.get("tau_g", 1.0)) != 1.0 or params.get("walls", 0):
         raise ValueError("the discrete adjoint covers tau_g = 1 on a periodic lattice")
-    return _Evolve.apply(phi0, U, V, int(steps), segment, tf, dict(params))
+    tune = tuple(int(t) for t in tiles) if tiles is not None else int(autotune)
+    return _Evolve.apply(phi0, U, V, int(steps), segment, tf, dict(params), tune)

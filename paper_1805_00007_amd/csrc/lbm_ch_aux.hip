@@ -282,7 +282,10 @@ __device__ __forceinline__ float d2bulk(const Coef& c, float p) {
   const float a = p - c.phia, b = p - c.phib, s = 2.0f * p - c.phia - c.phib;
   return c.beta2 * (b * s + a * s + 2.0f * a * b);
 }
+// Periodic index of any i; the division is only done for indices outside [0, n) (tile
+// halos, and tiles wider than the lattice).
 __device__ __forceinline__ int wrap(int i, int n) {
+  if (i >= 0 && i < n) return i;
   i %= n;
   return i < 0 ? i + n : i;
 }

@@ -50,7 +50,7 @@ def _fd(f, x0, dirs, target):
     return np.array(out)
 
 
-def _gpu_grads(lbm, case, target, steps, segment=None, model=None):
+def _gpu_grads(lbm, case, target, steps, segment=None, model=None, **kw):
     from paper_1805_00007_amd.adjoint import evolve
     dev = torch.device("cuda:0")
     phys = dict(case.phys)
@@ -60,7 +60,7 @@ def _gpu_grads(lbm, case, target, steps, segment=None, model=None):
     theta = torch.tensor(case.theta, dtype=torch.float32, device=dev, requires_grad=True)
     basis = torch.tensor(case.basis, dtype=torch.float32, device=dev)
     uv = case.scale * torch.tensordot(theta, basis, dims=1)
-    phi = evolve(phi0, uv[0], uv[1], steps, segment=segment, **phys)
+    phi = evolve(phi0, uv[0], uv[1], steps, segment=segment, **kw, **phys)
     loss = ((phi - torch.tensor(target, dtype=torch.float32, device=dev)) ** 2).sum()
     loss.backward()
     torch.cuda.synchronize()
@@ -163,17 +163,19 @@ def test_adjoint_separable_time_dependent_velocity(lbm):
 
 def test_checkpoint_segments_agree(lbm):
     """sqrt(N) checkpointing recomputes the same trajectory: gradients with segment
-    lengths 1, 7, sqrt(N) and N agree bitwise."""
+    lengths 1, 7, sqrt(N) and N, and with other or autotuned tile shapes, agree
+    bitwise."""
     n, steps = 32, 50
     case = workloads.adjoint_case(n, steps)
     target = np.zeros((n, n))
     ref = None
-    for seg in (None, 1, 7, steps):
-        _, gt, gp = _gpu_grads(lbm, case, target, steps, segment=seg)
+    for seg, kw in ((None, {}), (1, {}), (7, {}), (steps, {}), (None, dict(tiles=(64, 4))),
+                    (None, dict(autotune=2))):
+        _, gt, gp = _gpu_grads(lbm, case, target, steps, segment=seg, **kw)
         if ref is None:
             ref = (gt, gp)
         else:
-            assert np.array_equal(gt, ref[0]) and np.array_equal(gp, ref[1]), seg
+            assert np.array_equal(gt, ref[0]) and np.array_equal(gp, ref[1]), (seg, kw)
 
 
 def test_adjoint_zero_steps_is_identity(lbm):
