@@ -1,5 +1,6 @@
 // Internal interface between the host ABI (lbm_ch_api.cpp) and the gfx950 kernels
-// (lbm_ch_kernels.hip).  Not installed; the public interface is include/lbm_ch.h.
+// (lbm_ch_step.hip, lbm_ch_aux.hip).  Not installed; the public interface is
+// include/lbm_ch.h.
 #pragma once
 
 #include <hip/hip_runtime.h>
