@@ -203,8 +203,9 @@ def adjoint_leg(lbm, torch, reps=3):
 
 
 def batch_leg(lbm, torch, steps=5000, plain_steps=200, check_steps=100):
-    """64 lattices of uneven sizes (sides 64-512, seeded): the batched persistent kernel
-    with autotuned tiles, `steps` steps captured in one hipGraph and launched once,
+    """64 lattices of uneven sizes (sides 64-512, seeded): the batched kernel with the
+    autotuned schedule (persistent grid or one workgroup per tile) and tiles, `steps`
+    steps captured in one hipGraph and launched once,
     against the plain form (one lbm_ch_step launch per lattice per step) on the same GPU;
     both give bitwise the same fields."""
     import numpy as np
@@ -215,6 +216,7 @@ def batch_leg(lbm, torch, steps=5000, plain_steps=200, check_steps=100):
     ref = [lbm.solver_for(w) for w in ws]
     b = lbm.Batch(sol)
     tiles, tuned_us = b.autotune(5)
+    persistent = b.persistent
     b.step(check_steps, graph=True)
     for s in ref:
         s.step(check_steps)
@@ -252,7 +254,8 @@ def batch_leg(lbm, torch, steps=5000, plain_steps=200, check_steps=100):
             "plain_MLUPS": round(nodes / t_plain / 1e6, 1),
             "plain_us_per_step": round(t_plain * 1e6, 2),
             "speedup_vs_plain": round(t_plain / t_batch, 2),
-            "autotuned_tiles": {"tx": tiles[0], "ty": tiles[1], "trial_us": round(tuned_us, 2)},
+            "autotuned_tiles": {"tx": tiles[0], "ty": tiles[1], "trial_us": round(tuned_us, 2),
+                                "schedule": "persistent" if persistent else "tile per workgroup"},
             "bitwise_equal_to_plain_after_%d" % check_steps: bool(same),
             "nonfinite": int(nonfinite),
             "bytes_per_lu": 80}

@@ -238,8 +238,9 @@ int lbm_ch_adjoint(lbm_ch_ctx* ctx, int64_t n_end, int64_t nsteps, const float* 
 /* Batched stepping
  * ----------------
  * A batch advances many independent lattices (contexts created by lbm_ch_init) in one
- * launch per step: the tiles of every lattice form one work list that a persistent
- * grid of workgroups walks, each XCD taking a contiguous range of it.  Results are
+ * launch per step: the tiles of every lattice form one work list, each XCD taking a
+ * contiguous range of it, walked either by a persistent grid sized to the resident
+ * capacity or by one workgroup per tile (lbm_ch_batch_set_schedule).  Results are
  * bitwise those of lbm_ch_step on each context.  Lattices with different tile widths
  * or kernel variants (velocity mode, Model-I/II) form groups of one launch each.
  * Supported: periodic lattices, LBM_CH_STORE_F32, model 1 or 2, prescribed velocity
@@ -264,6 +265,13 @@ int lbm_ch_batch_create(lbm_ch_batch** out, lbm_ch_ctx* const* ctxs, int32_t n,
 int lbm_ch_batch_set_tiles(lbm_ch_batch* b, int32_t tx, int32_t ty);
 int lbm_ch_batch_get_tiles(const lbm_ch_batch* b, int32_t* tx, int32_t* ty);
 
+/* Schedule of the batched launch: 1 = persistent (a grid of as many workgroups as the
+ * GPU holds at once strides over the tiles), 0 = one workgroup per tile (default; the
+ * kernel then has the register budget of the single-lattice step).  get returns the
+ * schedule, or LBM_CH_ESTATE for a dead batch. */
+int lbm_ch_batch_set_schedule(lbm_ch_batch* b, int32_t persistent);
+int lbm_ch_batch_get_schedule(const lbm_ch_batch* b);
+
 /* Enqueue nsteps steps of every lattice on `stream`.  use_graph != 0: the nsteps
  * launches are captured once into a hipGraph (cached for this nsteps) and the graph is
  * launched once.  When the instance tables must be (re)uploaded (first call, new tiles,
@@ -273,8 +281,9 @@ int lbm_ch_batch_step(lbm_ch_batch* b, int64_t nsteps, int32_t use_graph, hipStr
 /* Bytes of a backup of every lattice's state (each rounded to 256 bytes). */
 size_t lbm_ch_batch_state_bytes(const lbm_ch_batch* b);
 
-/* Autotuner: time trial_steps >= 1 batch steps (after one untimed step) for every tile
- * policy tx in {0, 64, 128, 256} and ty in {4, 8, 16, 32}, keep the fastest, and
+/* Autotuner: time trial_steps >= 1 batch steps (after one untimed step) for both
+ * schedules, every tile policy tx in {0, 64, 128, 256} and ty in {4, 8, 16, 32}, keep the
+ * fastest, and
  * restore every lattice's state and step counter from `backup` (device memory of
  * exactly lbm_ch_batch_state_bytes bytes, 256-byte aligned).  Synchronises `stream`.
  * *best_us (may be NULL): the chosen shape's time per batch step in microseconds. */

@@ -31,7 +31,8 @@ EXPORTS = ("lbm_ch_workspace_bytes", "lbm_ch_init", "lbm_ch_step", "lbm_ch_momen
            "lbm_ch_set_tiles", "lbm_ch_get_tiles", "lbm_ch_autotune",
            "lbm_ch_adjoint_scratch_bytes", "lbm_ch_record", "lbm_ch_adjoint",
            "lbm_ch_batch_workspace_bytes", "lbm_ch_batch_create", "lbm_ch_batch_set_tiles",
-           "lbm_ch_batch_get_tiles", "lbm_ch_batch_step", "lbm_ch_batch_state_bytes",
+           "lbm_ch_batch_get_tiles", "lbm_ch_batch_set_schedule", "lbm_ch_batch_get_schedule",
+           "lbm_ch_batch_step", "lbm_ch_batch_state_bytes",
            "lbm_ch_batch_autotune", "lbm_ch_batch_destroy", "lbm_ch_destroy",
            "lbm_ch_strerror", "lbm_ch_last_hip_error")
 
@@ -106,6 +107,8 @@ def lib():
         L.lbm_ch_batch_set_tiles.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
         L.lbm_ch_batch_get_tiles.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
                                              ctypes.POINTER(ctypes.c_int32)]
+        L.lbm_ch_batch_set_schedule.argtypes = [vp, ctypes.c_int32]
+        L.lbm_ch_batch_get_schedule.argtypes = [vp]
         L.lbm_ch_batch_step.argtypes = [vp, i64, ctypes.c_int32, vp]
         L.lbm_ch_batch_state_bytes.argtypes = [vp]
         L.lbm_ch_batch_state_bytes.restype = ctypes.c_size_t
@@ -369,7 +372,18 @@ class Batch:
         _check(lib().lbm_ch_batch_set_tiles(self.b, int(tx), int(ty)), "lbm_ch_batch_set_tiles")
         return self
 
+    @property
+    def persistent(self):
+        return bool(lib().lbm_ch_batch_get_schedule(self.b))
+
+    def set_schedule(self, persistent):
+        _check(lib().lbm_ch_batch_set_schedule(self.b, 1 if persistent else 0),
+               "lbm_ch_batch_set_schedule")
+        return self
+
     def autotune(self, trial_steps=5):
+        """Time every schedule and tile policy; returns ((tx, ty), us per step) and leaves
+        the fastest set (see ``persistent``)."""
         t = self.torch
         n = lib().lbm_ch_batch_state_bytes(self.b)
         backup = t.empty(n, dtype=t.uint8, device=self.device)

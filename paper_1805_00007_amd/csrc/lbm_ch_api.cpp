@@ -621,6 +621,7 @@ struct lbm_ch_batch {
   std::vector<BatchGroup> groups;
   int tx_policy;  // 0: per-instance width, else one width for all
   int ty;
+  int persistent; // 1: a resident-size grid strides over the tiles; 0: a tile per workgroup
   int phase;      // steps taken since the tables were built, mod 2
   bool built;
   int cus;
@@ -711,10 +712,14 @@ static int batch_build(lbm_ch_batch* b, hipStream_t stream) {
   }
   b->hstart.push_back(b->groups.back().total);
   for (BatchGroup& g : b->groups) {
-    const int per_cu = phi_batch_blocks_per_cu(g.tx, g.vmode, g.model2);
-    const int resident = b->cus * per_cu / 8 * 8;
     const int want = (g.total + 7) / 8 * 8;
-    g.grid = want < resident ? want : (resident > 8 ? resident : 8);
+    if (b->persistent) {
+      const int per_cu = phi_batch_blocks_per_cu(g.tx, g.vmode, g.model2);
+      const int resident = b->cus * per_cu / 8 * 8;
+      g.grid = want < resident ? want : (resident > 8 ? resident : 8);
+    } else {
+      g.grid = want;
+    }
   }
   e = hipMemcpyAsync(b->dargs, b->hargs.data(), n * sizeof(StepArgs), hipMemcpyHostToDevice,
                      stream);
@@ -747,7 +752,7 @@ static hipError_t batch_enqueue(lbm_ch_batch* b, int64_t nsteps, int phase, hipS
       a.n = g.count;
       a.total = g.total;
       a.parity = (int)((phase + k) & 1);
-      hipError_t e = launch_phi_batch(g.tx, g.vmode, g.model2, a, g.grid, s);
+      hipError_t e = launch_phi_batch(g.tx, g.vmode, g.model2, b->persistent != 0, a, g.grid, s);
       if (e != hipSuccess) return e;
     }
   }
@@ -797,6 +802,7 @@ int lbm_ch_batch_create(lbm_ch_batch** out, lbm_ch_ctx* const* ctxs, int32_t n,
   b->dstart = (int*)((char*)workspace + align_up((size_t)n * sizeof(StepArgs)));
   b->tx_policy = 64;
   b->ty = 16;
+  b->persistent = 0;
   b->phase = 0;
   b->built = false;
   b->cus = cus > 0 ? cus : 1;
@@ -817,6 +823,18 @@ int lbm_ch_batch_set_tiles(lbm_ch_batch* b, int32_t tx, int32_t ty) {
   b->ty = ty;
   b->built = false;
   return LBM_CH_OK;
+}
+
+int lbm_ch_batch_set_schedule(lbm_ch_batch* b, int32_t persistent) {
+  if (!batch_live(b)) return LBM_CH_ESTATE;
+  if (persistent != 0 && persistent != 1) return LBM_CH_EINVAL;
+  b->persistent = persistent;
+  b->built = false;
+  return LBM_CH_OK;
+}
+
+int lbm_ch_batch_get_schedule(const lbm_ch_batch* b) {
+  return batch_live(b) ? b->persistent : LBM_CH_ESTATE;
 }
 
 int lbm_ch_batch_get_tiles(const lbm_ch_batch* b, int32_t* tx, int32_t* ty) {
@@ -886,16 +904,18 @@ int lbm_ch_batch_autotune(lbm_ch_batch* b, void* backup, size_t backup_bytes,
     if (r != LBM_CH_OK) return r;
     off += align_up(lbm_ch_state_bytes(c));
   }
-  const int tx0 = b->tx_policy, ty0 = b->ty;
+  const int tx0 = b->tx_policy, ty0 = b->ty, pe0 = b->persistent;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   int r = LBM_CH_OK;
   float best = -1.0f;
-  int btx = tx0, bty = ty0;
+  int btx = tx0, bty = ty0, bpe = pe0;
+  for (int pe : {0, 1})
   for (int xx : {0, 64, 128, 256}) {
     for (int yy : {4, 8, 16, 32}) {
       if (e != hipSuccess || r != LBM_CH_OK) break;
+      b->persistent = pe;
       b->tx_policy = xx;
       b->ty = yy;
       b->built = false;
@@ -911,6 +931,7 @@ int lbm_ch_batch_autotune(lbm_ch_batch* b, void* backup, size_t backup_bytes,
         best = ms;
         btx = xx;
         bty = yy;
+        bpe = pe;
       }
     }
   }
@@ -919,6 +940,7 @@ int lbm_ch_batch_autotune(lbm_ch_batch* b, void* backup, size_t backup_bytes,
   const bool ok = e == hipSuccess && r == LBM_CH_OK;
   b->tx_policy = ok ? btx : tx0;
   b->ty = ok ? bty : ty0;
+  b->persistent = ok ? bpe : pe0;
   b->built = false;
   off = 0;
   int r2 = LBM_CH_OK;

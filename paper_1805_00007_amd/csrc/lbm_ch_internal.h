@@ -78,10 +78,11 @@ uint32_t population_bytes(int storage, uint32_t plane);
 // Launchers (return hipGetLastError() of the launch).
 hipError_t launch_phi_step(int tx, bool walls, int vmode, int model, int storage,
                            const StepArgs& a, int nblocks, hipStream_t s);
-// grid: a multiple of 8 workgroups; the kernel strides over the tiles.
+// grid: a multiple of 8 workgroups.  persistent: the grid strides over the tiles (size
+// it with phi_batch_blocks_per_cu); otherwise one tile per workgroup (grid >= tiles).
 int phi_batch_blocks_per_cu(int tx, int vmode, bool model2);
-hipError_t launch_phi_batch(int tx, int vmode, bool model2, const BatchArgs& b, int grid,
-                            hipStream_t s);
+hipError_t launch_phi_batch(int tx, int vmode, bool model2, bool persistent, const BatchArgs& b,
+                            int grid, hipStream_t s);
 hipError_t launch_ns_step(int tx, bool walls, int storage, const NsArgs& a, int nblocks,
                           hipStream_t s);
 

@@ -307,8 +307,36 @@ k_phi_step(const StepArgs a) {
   phi_tile<TX, WALLS, VMODE, MODEL, ST>(a, L);
 }
 
-// Batched step: the tiles of many lattices (one instance table entry each) in one
-// persistent launch.  The tiles are numbered instance by instance; XCD x (workgroups
+// Batched step, one tile per workgroup: the tiles of many lattices (one instance table
+// entry each) in one launch.  The tiles are numbered instance by instance; when the grid
+// is a multiple of 8, XCD x (workgroups w with w % 8 == x) gets the contiguous range
+// [x per, (x + 1) per), so vertically adjacent tiles of one lattice share an L2.  Same
+// register budget as the single-lattice kernel.
+template <int TX, int VMODE, bool MODEL2>
+__global__ void __launch_bounds__(TX) __attribute__((amdgpu_waves_per_eu(WPE_PHI, 8)))
+k_phi_batch(const BatchArgs b) {
+  int v = blockIdx.x;
+  if ((gridDim.x & 7) == 0) {
+    const int per = gridDim.x >> 3;
+    v = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  }
+  if (v >= b.total) return;
+  int lo_i = 0, hi_i = b.n;  // instance of tile v: start[inst] <= v < start[inst + 1]
+  while (hi_i - lo_i > 1) {
+    const int mid = (lo_i + hi_i) >> 1;
+    if (b.start[mid] <= v) lo_i = mid; else hi_i = mid;
+  }
+  StepArgs a = b.args[lo_i];
+  if (b.parity) {
+    const void* t = a.src;
+    a.src = a.dst;
+    a.dst = const_cast<void*>(t);
+  }
+  phi_tile<TX, false, VMODE, MODEL2 ? 2 : 1, ST_F32>(a, v - b.start[lo_i]);
+}
+
+// Batched step, persistent: the tiles of many lattices (one instance table entry each)
+// in one launch of a grid sized to the resident capacity.  The tiles are numbered instance by instance; XCD x (workgroups
 // w with w % 8 == x) owns the contiguous range [x per, (x + 1) per) and its workgroups
 // stride through it, so vertically adjacent tiles of one lattice share that XCD's L2.
 // Every workgroup leaves the loop after at most ceil(per / slots) tiles.
@@ -317,7 +345,7 @@ k_phi_step(const StepArgs a) {
 #endif
 template <int TX, int VMODE, bool MODEL2>
 __global__ void __launch_bounds__(TX) __attribute__((amdgpu_waves_per_eu(WPE_BATCH, 8)))
-k_phi_batch(const BatchArgs b) {
+k_phi_batch_persistent(const BatchArgs b) {
   const int slots = gridDim.x >> 3;
   const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
   const int per = (b.total + 7) >> 3;
@@ -493,15 +521,19 @@ hipError_t phi_step_m(int model, const StepArgs& a, int nb, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int TX>
+template <int TX, bool PERSIST>
 hipError_t phi_batch_t(int vmode, bool model2, const BatchArgs& b, int grid, hipStream_t s) {
+#define LBM_BATCH_LAUNCH(V, M)                                                             \
+  if (PERSIST)                                                                             \
+    hipLaunchKernelGGL((k_phi_batch_persistent<TX, V, M>), dim3(grid), dim3(TX), 0, s, b); \
+  else                                                                                     \
+    hipLaunchKernelGGL((k_phi_batch<TX, V, M>), dim3(grid), dim3(TX), 0, s, b)
   if (vmode == VEL_SEP) {
-    if (model2) hipLaunchKernelGGL((k_phi_batch<TX, VEL_SEP, true>), dim3(grid), dim3(TX), 0, s, b);
-    else hipLaunchKernelGGL((k_phi_batch<TX, VEL_SEP, false>), dim3(grid), dim3(TX), 0, s, b);
+    if (model2) { LBM_BATCH_LAUNCH(VEL_SEP, true); } else { LBM_BATCH_LAUNCH(VEL_SEP, false); }
   } else {
-    if (model2) hipLaunchKernelGGL((k_phi_batch<TX, VEL_FIELD, true>), dim3(grid), dim3(TX), 0, s, b);
-    else hipLaunchKernelGGL((k_phi_batch<TX, VEL_FIELD, false>), dim3(grid), dim3(TX), 0, s, b);
+    if (model2) { LBM_BATCH_LAUNCH(VEL_FIELD, true); } else { LBM_BATCH_LAUNCH(VEL_FIELD, false); }
   }
+#undef LBM_BATCH_LAUNCH
   return hipGetLastError();
 }
 
@@ -564,11 +596,11 @@ int phi_batch_blocks_per_cu(int tx, int vmode, bool model2) {
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
   const bool sep = vmode == VEL_SEP;
-#define LBM_OCC(T)                                                                          \
-  e = sep ? (model2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phi_batch<T, VEL_SEP, true>, T, 0)    \
-                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phi_batch<T, VEL_SEP, false>, T, 0))   \
-          : (model2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phi_batch<T, VEL_FIELD, true>, T, 0)  \
-                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phi_batch<T, VEL_FIELD, false>, T, 0))
+#define LBM_OCC(T)                                                                            \
+  e = sep ? (model2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phi_batch_persistent<T, VEL_SEP, true>, T, 0)    \
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phi_batch_persistent<T, VEL_SEP, false>, T, 0))   \
+          : (model2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phi_batch_persistent<T, VEL_FIELD, true>, T, 0)  \
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phi_batch_persistent<T, VEL_FIELD, false>, T, 0))
   switch (tx) {
     case 64: LBM_OCC(64); break;
     case 128: LBM_OCC(128); break;
@@ -579,13 +611,21 @@ int phi_batch_blocks_per_cu(int tx, int vmode, bool model2) {
   return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
-hipError_t launch_phi_batch(int tx, int vmode, bool model2, const BatchArgs& b, int grid,
-                            hipStream_t s) {
+hipError_t launch_phi_batch(int tx, int vmode, bool model2, bool persistent, const BatchArgs& b,
+                            int grid, hipStream_t s) {
   if (grid <= 0 || (grid & 7) != 0 || b.n <= 0) return hipErrorInvalidValue;
+  if (persistent) {
+    switch (tx) {
+      case 64: return phi_batch_t<64, true>(vmode, model2, b, grid, s);
+      case 128: return phi_batch_t<128, true>(vmode, model2, b, grid, s);
+      case 256: return phi_batch_t<256, true>(vmode, model2, b, grid, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (tx) {
-    case 64: return phi_batch_t<64>(vmode, model2, b, grid, s);
-    case 128: return phi_batch_t<128>(vmode, model2, b, grid, s);
-    case 256: return phi_batch_t<256>(vmode, model2, b, grid, s);
+    case 64: return phi_batch_t<64, false>(vmode, model2, b, grid, s);
+    case 128: return phi_batch_t<128, false>(vmode, model2, b, grid, s);
+    case 256: return phi_batch_t<256, false>(vmode, model2, b, grid, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -100,6 +100,8 @@ def test_context_calls_reject_null_and_strerror():
     assert L.lbm_ch_batch_step(None, 1, 0, None) == lbm.ESTATE
     assert L.lbm_ch_batch_autotune(None, None, 0, 1, None, None) == lbm.ESTATE
     assert L.lbm_ch_batch_state_bytes(None) == 0
+    assert L.lbm_ch_batch_set_schedule(None, 1) == lbm.ESTATE
+    assert L.lbm_ch_batch_get_schedule(None) == lbm.ESTATE
     assert L.lbm_ch_batch_destroy(None) == lbm.OK
     b = ctypes.c_void_p()
     assert L.lbm_ch_batch_create(ctypes.byref(b), None, 0, None, 0) == lbm.EINVAL

@@ -41,9 +41,10 @@ def _small_case(n_inst=12, seed=9):
     return workloads.batch_case(n_inst, seed=seed, sides=(64, 128, 192, 256), steps=200)
 
 
-@pytest.mark.parametrize("tiles,graph", [((0, 16), False), ((0, 16), True), ((64, 4), True),
-                                         ((256, 32), False), ((128, 1), True)])
-def test_batch_bitwise_equals_single(lbm, tiles, graph):
+@pytest.mark.parametrize("tiles,graph,persistent", [
+    ((0, 16), False, 0), ((0, 16), True, 1), ((64, 4), True, 0), ((64, 4), True, 1),
+    ((256, 32), False, 1), ((128, 1), True, 0)])
+def test_batch_bitwise_equals_single(lbm, tiles, graph, persistent):
     ws = _small_case()
     ref = _solvers(lbm, ws)
     for s in ref:
@@ -51,7 +52,8 @@ def test_batch_bitwise_equals_single(lbm, tiles, graph):
     want = _phis(ref)
     _close(ref)
     sol = _solvers(lbm, ws)
-    b = lbm.Batch(sol).set_tiles(*tiles)
+    b = lbm.Batch(sol).set_tiles(*tiles).set_schedule(persistent)
+    assert b.persistent == bool(persistent)
     b.step(20, graph=graph)
     b.step(17, graph=graph)
     got = _phis(sol)
@@ -151,7 +153,8 @@ def test_batch_autotune_restores_state(lbm):
         s.step(3)
     b = lbm.Batch(sol)
     tiles, us = b.autotune(trial_steps=3)
-    print("batch autotune ->", tiles, "%.1f us/step" % us)
+    print("batch autotune ->", tiles, "persistent" if b.persistent else "tile per workgroup",
+          "%.1f us/step" % us)
     assert all(s.step_count == 3 for s in sol)
     assert tiles[0] in (0, 64, 128, 256) and tiles[1] in (4, 8, 16, 32) and us > 0
     b.step(10, graph=True)
