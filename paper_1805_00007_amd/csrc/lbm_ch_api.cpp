@@ -128,18 +128,18 @@ static void apply_tiles(lbm_ch_ctx* c, int tx, int ty) {
   c->xcd_remap = (c->nblocks % 8 == 0) ? 1 : 0;
 }
 
-// Default: the tallest tile (fewest halo rows per row), then the widest, that still
-// gives at least 4 blocks per CU on 256 CUs; small lattices get the most blocks.
-// LBM_CH_TILE=TXxTY overrides; lbm_ch_autotune measures.
+// Default: the widest tile (fewest halo columns), then the tallest (fewest halo rows
+// per row), that still gives at least 2 workgroups per CU on 256 CUs; small lattices
+// get the most workgroups.  LBM_CH_TILE=TXxTY overrides; lbm_ch_autotune measures.
 static void choose_tiles(lbm_ch_ctx* c) {
   const int nx = c->p.nx, ny = c->p.ny;
   int tx = 64, ty = 4;
   bool found = false;
-  for (int yy : {16, 8, 4}) {
-    for (int xx : {256, 128, 64}) {
-      if (xx > nx && xx > 64) continue;
+  for (int xx : {256, 128, 64}) {
+    if (xx > nx && xx > 64) continue;
+    for (int yy : {32, 16, 8, 4}) {
       const long nb = (long)((nx + xx - 1) / xx) * ((ny + yy - 1) / yy);
-      if (nb >= 1024) {
+      if (nb >= 512) {
         tx = xx;
         ty = yy;
         found = true;

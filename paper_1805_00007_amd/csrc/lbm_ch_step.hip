@@ -175,7 +175,12 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
   };
   // Stage 3 for lattice row y: F = F1 (+ F2), collision, store.
   auto stage3 = [&](int y, RowRec& R) {
-    if (!active) return;
+    // Lanes past the right edge of a ragged last strip wrap to columns another strip
+    // owns and compute the very same values from the very same inputs, so their stores
+    // duplicate identical data; they need no branch (which would make the wait for the
+    // next row's pull also wait for this row's stores).  Model 3 keeps the branch: a
+    // duplicate lane could read a history value its owner has already replaced.
+    if (HIST && !active) return;
     const float* mm = s_mu[(y - 1) & 3];
     const float* m0 = s_mu[y & 3];
     const float* mp = s_mu[(y + 1) & 3];
@@ -213,15 +218,15 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
     finish_store<ST>(rdst, plane, nx, vc, (uint32_t)y, (double)R.phi + (double)R.lo, R.g);
   };
 
-  // Prologue: rows y0-2d .. y0+d through stage 1, rows y0-d and y0 through stage 2,
-  // and the pull of row y0+2d in flight (d = dir).
+  // Prologue: rows y0-2d .. y0+2d through stage 1, rows y0-d and y0 through stage 2.
   //
-  // Register pipeline.  A holds row y (collided in stage 3), B row y+d; the pull of
-  // the next row lands in one of two slots, X0 or X1, which alternate, so registers
-  // with a load in flight are never copied (copying them would make the wave wait for
-  // every outstanding memory operation).  Completed rows move down A <- B <- X by copy.
+  // Register pipeline.  Iteration y issues the pull of row y+3d first, then runs stage
+  // 2 of row y+d and stage 3 of row y while it is in flight, and consumes it (stage 1)
+  // last, so no load is outstanding when the loop branches back (a record with a load
+  // in flight is then never moved between registers, which would make the wave wait
+  // for every outstanding load).  A, B, C hold rows y, y+d, y+2d; N receives y+3d.
   const int d = dir;
-  RowRec A, B, X0, X1, H0;
+  RowRec A, B, C, N, H0;
   {
     RowRec T0, T1;
     issue(y0 - 2 * d, vc, vm, vp, T0);
@@ -246,9 +251,7 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
     }
   }
   issue(y0 + 2 * d, hvc, hvm, hvp, H0, false);
-  __builtin_amdgcn_sched_barrier(0);
-  issue(y0 + 2 * d, vc, vm, vp, X0);
-  __builtin_amdgcn_sched_barrier(0);
+  issue(y0 + 2 * d, vc, vm, vp, C);
   __syncthreads();
   stage2(y0 - d, j);
   stage2(y0, j);
@@ -257,40 +260,36 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
     stage2(y0, j2);
   }
   __syncthreads();
+  // row y0+2d shares its ring slot with y0-2d, which stage 2 no longer needs
+  stage1(y0 + 2 * d, H0, hj, axh, bxh, hl);
+  stage1(y0 + 2 * d, C, j, axc, bxc);
 
-  // One marching row: issue row y+3d into slot N, stage 1 of row y+2d from slot C
-  // (pulled one row earlier), stage 2 of row y+d, stage 3 of row y.  On a block's last
-  // row the pull of y+3d is not needed; it is clamped to the last row the block does
-  // need (already in cache), so the pipeline has no branch and fetches nothing extra.
+  // One marching row.  On a block's last rows the pull of y+3d is not needed; it is
+  // clamped to the last row the block does need (already in cache), so the pipeline
+  // has no branch and fetches nothing extra.
   const int last_needed = y0 + (rows + 1) * d;
-  auto row = [&](int k, RowRec& C, RowRec& N) {
+#pragma unroll 1
+  for (int k = 0; k < rows; ++k) {
     const int y = y0 + k * d;
     const int ynext = k + 1 < rows ? y + 3 * d : last_needed;
-    // Halo first: its pull was issued before C's, so waiting for it leaves C in flight.
-    // The scheduling barriers keep the compiler from interleaving the two pulls, which
-    // would make each wait cover the other pull as well.
     __builtin_amdgcn_sched_barrier(0);
-    stage1(y + 2 * d, H0, hj, axh, bxh, hl);
     issue(ynext, hvc, hvm, hvp, H0, false);
     __builtin_amdgcn_sched_barrier(0);
     issue(ynext, vc, vm, vp, N);
     __builtin_amdgcn_sched_barrier(0);
-    stage1(y + 2 * d, C, j, axc, bxc);
     __syncthreads();
     stage2(y + d, j);
     if (t < 2) stage2(y + d, j2);
     __syncthreads();
     stage3(y, A);
+    __builtin_amdgcn_sched_barrier(0);
+    // row y+3d takes the ring slot of row y-d, which no later stage reads
+    stage1(y + 3 * d, H0, hj, axh, bxh, hl);
+    stage1(y + 3 * d, N, j, axc, bxc);
     A = B;
     B = C;
-  };
-  int k = 0;
-#pragma unroll 1
-  for (; k + 2 <= rows; k += 2) {
-    row(k, X0, X1);
-    row(k + 1, X1, X0);
+    C = N;
   }
-  if (k < rows) row(k, X0, X1);
 }
 
 // Model 3 carries two more values per row record; it gets the register budget of
