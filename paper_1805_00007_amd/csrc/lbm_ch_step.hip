@@ -93,12 +93,15 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
   const uint32_t vm = xc == 0 ? nx - 1 : xc - 1;
   const uint32_t vp = xc == nx - 1 ? 0 : xc + 1;
   // Halo lanes t < 4: logical columns x0-2, x0-1, x0+TX, x0+TX+1 -> LDS 0, 1, TX+2, TX+3.
+  // They sit in wave 0; the other waves skip the halo pull (a scalar branch).
   const bool hl = t < 4;
+  const bool hwave = __builtin_amdgcn_readfirstlane(t) < 64;
   const int hlog = t < 2 ? x0 - 2 + t : x0 + TX - 2 + t;
   const int hc = ((hlog % nx) + nx) % nx;
-  // Every lane issues the halo pull, so that the wait-count bookkeeping does not depend
-  // on a branch; lanes other than the four halo lanes use an offset beyond the buffer,
-  // for which a raw buffer load returns 0 without accessing memory.
+  // Every lane of wave 0 issues the halo pull (a wave-uniform branch, so the wait for
+  // the halo row is the only wait inside it); lanes other than the four halo lanes use
+  // an offset beyond the buffer, for which a raw buffer load returns 0 without
+  // accessing memory.
   constexpr uint32_t OOB = 0x3FFFFFC0u;  // column index whose byte offset exceeds any buffer
   const uint32_t hvc = hl ? hc : OOB;
   const uint32_t hvm = hl ? (hc == 0 ? nx - 1 : hc - 1) : OOB;
@@ -250,7 +253,7 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
       stage1(y0 + d, T1, hj, axh, bxh);
     }
   }
-  issue(y0 + 2 * d, hvc, hvm, hvp, H0, false);
+  if (hwave) issue(y0 + 2 * d, hvc, hvm, hvp, H0, false);
   issue(y0 + 2 * d, vc, vm, vp, C);
   __syncthreads();
   stage2(y0 - d, j);
@@ -261,7 +264,7 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
   }
   __syncthreads();
   // row y0+2d shares its ring slot with y0-2d, which stage 2 no longer needs
-  stage1(y0 + 2 * d, H0, hj, axh, bxh, hl);
+  if (hwave) stage1(y0 + 2 * d, H0, hj, axh, bxh, hl);
   stage1(y0 + 2 * d, C, j, axc, bxc);
 
   // One marching row.  On a block's last rows the pull of y+3d is not needed; it is
@@ -273,7 +276,7 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
     const int y = y0 + k * d;
     const int ynext = k + 1 < rows ? y + 3 * d : last_needed;
     __builtin_amdgcn_sched_barrier(0);
-    issue(ynext, hvc, hvm, hvp, H0, false);
+    if (hwave) issue(ynext, hvc, hvm, hvp, H0, false);
     __builtin_amdgcn_sched_barrier(0);
     issue(ynext, vc, vm, vp, N);
     __builtin_amdgcn_sched_barrier(0);
@@ -284,7 +287,7 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
     stage3(y, A);
     __builtin_amdgcn_sched_barrier(0);
     // row y+3d takes the ring slot of row y-d, which no later stage reads
-    stage1(y + 3 * d, H0, hj, axh, bxh, hl);
+    if (hwave) stage1(y + 3 * d, H0, hj, axh, bxh, hl);
     stage1(y + 3 * d, N, j, axc, bxc);
     A = B;
     B = C;

@@ -69,3 +69,13 @@ def test_autotune_restores_state(lbm):
     s.close()
     ref = _run(lbm, w, 70)
     assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("storage,expect", [(0, (256, 32)), (1, (256, 16)), (2, (256, 16))])
+def test_default_tiles(lbm, storage, expect):
+    """Default tile of a 2048^2 lattice: the widest, then tallest, shape with at least 512
+    blocks for float32 populations and 1024 for 16-bit ones."""
+    w = workloads.metric2048(steps=1)
+    s = lbm.solver_for(w, storage=storage)
+    assert s.tiles == expect
+    s.close()
