@@ -330,15 +330,23 @@ static int run_steps(lbm_ch_ctx* c, int64_t nsteps, float* phi_out, hipStream_t 
     }
     a.src = c->g[src];
     a.dst = c->g[dst];
-    if (phi_out) {
-      e = launch_phi_field(walls, c->p.storage, c->g[src], c->L.plane, c->p.nx, c->p.ny,
-                           phi_out + (size_t)s * c->p.nx * c->p.ny, stream);
-      if (e != hipSuccess) return hip_fail(e);
-    }
     a.xh = c->xh;
     a.xfirst = c->step == 0 ? 1 : 0;
-    e = launch_phi_step(c->tx, walls, vmode, c->p.model, c->p.storage, a, c->nblocks,
-                        stream);
+    float* rec = phi_out ? phi_out + (size_t)s * c->p.nx * c->p.ny : nullptr;
+    if (rec && phi_record_fused(walls, vmode, c->p.model, c->p.storage)) {
+      // the step writes phi of its source state itself
+      a.phi_rec = rec;
+      e = launch_phi_record(c->tx, vmode, c->p.model, a, c->nblocks, stream);
+      a.phi_rec = nullptr;
+    } else {
+      if (rec) {
+        e = launch_phi_field(walls, c->p.storage, c->g[src], c->L.plane, c->p.nx, c->p.ny,
+                             rec, stream);
+        if (e != hipSuccess) return hip_fail(e);
+      }
+      e = launch_phi_step(c->tx, walls, vmode, c->p.model, c->p.storage, a, c->nblocks,
+                          stream);
+    }
     if (e != hipSuccess) return hip_fail(e);
     c->cur = dst;
     c->step += 1;

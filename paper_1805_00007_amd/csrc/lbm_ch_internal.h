@@ -45,6 +45,7 @@ struct StepArgs {
   float tf;
   float* xh;          // model 3: X of the previous step (2 planes of nx*ny), rewritten
   int xfirst;         // model 3: 1 on the first step (no earlier X: zero difference)
+  float* phi_rec;     // launch_phi_record only: phi of the source state (nx*ny), written
 };
 
 // Arguments of the batched step: one StepArgs per instance (src/dst as at parity 0),
@@ -78,6 +79,12 @@ uint32_t population_bytes(int storage, uint32_t plane);
 // Launchers (return hipGetLastError() of the launch).
 hipError_t launch_phi_step(int tx, bool walls, int vmode, int model, int storage,
                            const StepArgs& a, int nblocks, hipStream_t s);
+// The same step that also writes phi of the source state to a.phi_rec (the sums stage 1
+// forms anyway).  Periodic float32 lattices with a prescribed velocity (VEL_SEP or
+// VEL_FIELD) and model 1 or 2 only; hipErrorInvalidValue otherwise.
+bool phi_record_fused(bool walls, int vmode, int model, int storage);
+hipError_t launch_phi_record(int tx, int vmode, int model, const StepArgs& a, int nblocks,
+                             hipStream_t s);
 // grid: a multiple of 8 workgroups.  persistent: the grid strides over the tiles (size
 // it with phi_batch_blocks_per_cu); otherwise one tile per workgroup (grid >= tiles).
 int phi_batch_blocks_per_cu(int tx, int vmode, bool model2);

@@ -43,7 +43,9 @@ struct RowRec {
 // One tile of the step: strip (L % nstrips) of TX columns, row chunk L / nstrips.
 // MODEL 1: F = F1; 2: F = F1 + K grad(div(phi u)) (Eq. mark3); 3: Eq. F2-1 with the
 // time derivatives as one-step differences of X = cA F1 + cB grad mu, stored per node.
-template <int TX, bool WALLS, int VMODE, int MODEL, int ST>
+// REC: also store phi of every marched row (the source state's order parameter) to
+// a.phi_rec.
+template <int TX, bool WALLS, int VMODE, int MODEL, int ST, bool REC = false>
 __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
   constexpr bool MODEL2 = MODEL >= 2;
   constexpr bool HIST = MODEL == 3;
@@ -74,6 +76,8 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
   if (NSC) rp = make_rsrc(a.pf, nodes * 4u);
   rsrc_t rxh;
   if (HIST) rxh = make_rsrc(a.xh, 2u * nodes * 4u);
+  rsrc_t rrec;
+  if (REC) rrec = make_rsrc(a.phi_rec, nodes * 4u);
 
   const int t = threadIdx.x;
   const int x0 = (L % a.nstrips) * TX;
@@ -217,6 +221,7 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
     }
     const float u = VMODE == VEL_SEP ? axc * R.fy_u : R.u;
     const float v = VMODE == VEL_SEP ? bxc * R.fy_v : R.v;
+    if (REC) stb(rrec, R.phi, vc * 4u, (uint32_t)y * rb);
     collide_g(c, R.phi, R.lo, m0[j], u, v, fx, fy, R.g);
     finish_store<ST>(rdst, plane, nx, vc, (uint32_t)y, (double)R.phi + (double)R.lo, R.g);
   };
@@ -297,7 +302,7 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
 
 // Model 3 carries two more values per row record; it gets the register budget of
 // three waves per SIMD so that nothing spills.
-template <int TX, bool WALLS, int VMODE, int MODEL, int ST>
+template <int TX, bool WALLS, int VMODE, int MODEL, int ST, bool REC = false>
 __global__ void __launch_bounds__(TX)
 __attribute__((amdgpu_waves_per_eu(MODEL == 3 ? 3 : WPE_PHI, 8)))
 k_phi_step(const StepArgs a) {
@@ -306,7 +311,7 @@ k_phi_step(const StepArgs a) {
     const int per = gridDim.x >> 3;
     L = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   }
-  phi_tile<TX, WALLS, VMODE, MODEL, ST>(a, L);
+  phi_tile<TX, WALLS, VMODE, MODEL, ST, REC>(a, L);
 }
 
 // Batched step, one tile per workgroup: the tiles of many lattices (one instance table
@@ -583,6 +588,35 @@ hipError_t ns_step_t(int tx, bool walls, const NsArgs& a, int nb, hipStream_t s)
 }
 
 }  // namespace
+
+bool phi_record_fused(bool walls, int vmode, int model, int storage) {
+  return !walls && storage == ST_F32 && (vmode == VEL_SEP || vmode == VEL_FIELD) &&
+         (model == 1 || model == 2);
+}
+
+template <int TX>
+static hipError_t phi_record_t(int vmode, int model, const StepArgs& a, int nb, hipStream_t s) {
+#define LBM_REC_LAUNCH(V, M) \
+  hipLaunchKernelGGL((k_phi_step<TX, false, V, M, ST_F32, true>), dim3(nb), dim3(TX), 0, s, a)
+  if (vmode == VEL_SEP) {
+    if (model == 2) { LBM_REC_LAUNCH(VEL_SEP, 2); } else { LBM_REC_LAUNCH(VEL_SEP, 1); }
+  } else {
+    if (model == 2) { LBM_REC_LAUNCH(VEL_FIELD, 2); } else { LBM_REC_LAUNCH(VEL_FIELD, 1); }
+  }
+#undef LBM_REC_LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_phi_record(int tx, int vmode, int model, const StepArgs& a, int nblocks,
+                             hipStream_t s) {
+  if (!phi_record_fused(false, vmode, model, ST_F32) || !a.phi_rec) return hipErrorInvalidValue;
+  switch (tx) {
+    case 64: return phi_record_t<64>(vmode, model, a, nblocks, s);
+    case 128: return phi_record_t<128>(vmode, model, a, nblocks, s);
+    case 256: return phi_record_t<256>(vmode, model, a, nblocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_phi_step(int tx, bool walls, int vmode, int model, int storage,
                            const StepArgs& a, int nblocks, hipStream_t s) {

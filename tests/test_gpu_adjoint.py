@@ -232,3 +232,50 @@ def test_adjoint_full_size_against_stored_fd(lbm):
     assert e_loss <= 1e-4
     assert e_theta <= 2e-3
     assert e_phi <= 2e-3
+
+
+@pytest.mark.parametrize("mode", ["field-model2", "separable-model1", "walls", "half"])
+def test_record_matches_plain_steps(lbm, mode):
+    """lbm_ch_record writes phi^n before every step n (fused into the step kernel for
+    periodic float32 lattices with a prescribed velocity and model 1 or 2, a separate
+    phi launch otherwise): the trajectory equals phi() taken before each plain step,
+    and the state afterwards equals the plain run's, bitwise.  Ragged 200 x 136 lattice
+    (the last strip and row chunk are partial)."""
+    nx, ny, steps = 200, 136, 7
+    dev = torch.device("cuda:0")
+    phi0 = workloads.random_blobs(nx, seed=3, width=4.0)[:ny]
+    phys = dict(workloads.PRESCRIBED, model=2)
+    kw = {}
+    if mode == "separable-model1":
+        tabs = workloads.single_vortex(nx, 0.05, 400, steps)
+        tabs = dict(tabs, ay=tabs["ay"][:ny], by=tabs["by"][:ny])
+        kw["velocity"] = tabs
+        phys["model"] = 1
+    else:
+        U, V = workloads.random_stream_function(nx, 4, seed=4, umax=0.05)
+        kw["field"] = (U[:ny], V[:ny])
+    if mode == "walls":
+        phys["walls"] = 1
+    if mode == "half":
+        phys["storage"] = 1
+
+    def solver():
+        return lbm.Solver(nx, ny, phi0, device=dev, **kw, **phys)
+
+    a = solver()
+    ref = []
+    for _ in range(steps):
+        ref.append(a.phi().cpu().numpy())
+        a.step(1)
+    ref_end = a.phi().cpu().numpy()
+    b = solver()
+    traj = torch.empty((steps, ny, nx), dtype=torch.float32, device=dev)
+    b.record(steps, traj)
+    got = traj.cpu().numpy()
+    got_end = b.phi().cpu().numpy()
+    assert b.step_count == steps
+    a.close()
+    b.close()
+    for n in range(steps):
+        assert np.array_equal(got[n], ref[n]), (mode, n)
+    assert np.array_equal(got_end, ref_end), mode
