@@ -190,7 +190,7 @@ int lbm_ch_get_tiles(const lbm_ch_ctx* ctx, int32_t* tx, int32_t* ty);
 
 /* Autotuner: time trial_steps >= 1 steps (after one untimed step) for each tile shape
  * tx in {64, 128, 256} (skipping widths with more than half the lanes idle) and ty in
- * {2, 4, 8, 16, 32}, keep the fastest, and restore the state and step counter from
+ * {1, 2, 4, 8, 16, 32}, keep the fastest, and restore the state and step counter from
  * `backup`, a caller device buffer of exactly lbm_ch_state_bytes(ctx) bytes.
  * Synchronises `stream`.  *best_us (may be NULL) receives the chosen shape's time per
  * step in microseconds. */

@@ -495,7 +495,7 @@ int lbm_ch_autotune(lbm_ch_ctx* c, void* backup, size_t backup_bytes, int32_t tr
   for (int xx : {64, 128, 256}) {
     if (e != hipSuccess) break;
     if (xx > 64 && xx / 2 >= nx) continue;  // more than half the lanes idle
-    for (int yy : {2, 4, 8, 16, 32}) {
+    for (int yy : {1, 2, 4, 8, 16, 32}) {
       if (yy > ny && yy > 2) continue;
       apply_tiles(c, xx, yy);
       r = lbm_ch_step(c, 1, stream);  // untimed: first launch of this kernel shape

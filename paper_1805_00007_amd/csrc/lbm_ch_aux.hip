@@ -307,6 +307,26 @@ __global__ void __launch_bounds__(ATW * ATH) k_adjoint(const AdjArgs a) {
   const int nx = a.nx, ny = a.ny;
   const int t = threadIdx.x;
   const int x0 = blockIdx.x * ATW, y0 = blockIdx.y * ATH;
+  // This thread's own node: its velocity and accumulated gradients are loaded first, so
+  // that their latency overlaps the staging below instead of following the barriers.
+  const int ty = t / ATW, tx = t - ty * ATW;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool own = x < nx && y < ny;
+  const uint32_t k = own ? (uint32_t)y * nx + x : 0u;
+  float u = 0.f, v = 0.f, gu0 = 0.f, gv0 = 0.f;
+  if (own) {
+    if (a.vmode == VEL_SEP) {
+      u = a.tf * a.ax[x] * a.ay[y];
+      v = a.tf * a.bx[x] * a.by[y];
+    } else {
+      u = a.tf * a.ux[k];
+      v = a.tf * a.uy[k];
+    }
+    if (a.gu) {
+      gu0 = a.gu[k];
+      gv0 = a.gv[k];
+    }
+  }
   for (int i = t; i < L3H * L3W; i += NT) {
     const int r = i / L3W, cc = i - r * L3W;
     sl[r][cc] = a.lam1[(uint32_t)wrap(y0 - 3 + r, ny) * nx + wrap(x0 - 3 + cc, nx)];
@@ -345,19 +365,8 @@ __global__ void __launch_bounds__(ATW * ATH) k_adjoint(const AdjArgs a) {
                             ddy(slfy[r], slfy[r + 1], slfy[r + 2], cc + 1));
   }
   __syncthreads();
-  const int ty = t / ATW, tx = t - ty * ATW;
-  const int x = x0 + tx, y = y0 + ty;
-  if (x >= nx || y >= ny) return;
-  const uint32_t k = (uint32_t)y * nx + x;
+  if (!own) return;
   const float phi = sp[ty + 2][tx + 2];
-  float u, v;
-  if (a.vmode == VEL_SEP) {
-    u = a.tf * a.ax[x] * a.ay[y];
-    v = a.tf * a.bx[x] * a.by[y];
-  } else {
-    u = a.tf * a.ux[k];
-    v = a.tf * a.uy[k];
-  }
   const float usq = u * u + v * v;
   // advection part: sum_i w_i s_i(u) lam'(x + c_i), and its u-derivative times phi
   float lam = sl[ty + 3][tx + 3], lu = 0.f, lv = 0.f;
@@ -387,8 +396,8 @@ __global__ void __launch_bounds__(ATW * ATH) k_adjoint(const AdjArgs a) {
   }
   a.lam0[k] = lam;
   if (a.gu) {
-    a.gu[k] += a.tf * phi * gx;
-    a.gv[k] += a.tf * phi * gy;
+    a.gu[k] = gu0 + a.tf * phi * gx;
+    a.gv[k] = gv0 + a.tf * phi * gy;
   }
 }
 

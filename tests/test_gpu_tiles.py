@@ -63,7 +63,7 @@ def test_autotune_restores_state(lbm):
     tiles, us = s.autotune(trial_steps=5)
     print("autotune 256^2 ->", tiles, "%.2f us/step" % us)
     assert s.step_count == 30
-    assert tiles[0] in (64, 128, 256) and tiles[1] in (2, 4, 8, 16, 32) and us > 0
+    assert tiles[0] in (64, 128, 256) and tiles[1] in (1, 2, 4, 8, 16, 32) and us > 0
     s.step(40)
     got = s.phi().cpu().numpy()
     s.close()
