@@ -49,6 +49,15 @@ __device__ __forceinline__ float ldb(rsrc_t r, uint32_t voff, uint32_t soff) {
 __device__ __forceinline__ void stb(rsrc_t r, float v, uint32_t voff, uint32_t soff) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
 }
+// Cache-policy bit "nt" (non-temporal) of a buffer access on gfx950: the populations a
+// step writes are read again only by the next step, not by this one, so their stores
+// stream past the caches and leave L2 to the rows that neighbouring tiles re-read.
+// Measured on MI355X (2048^2): 2-5 % faster for float32 stores; the 2-byte stores of
+// the 16-bit storage modes become ~10 % slower with it, so they keep the default.
+constexpr int CP_NT = 2;
+__device__ __forceinline__ void stb_nt(rsrc_t r, float v, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, CP_NT);
+}
 
 // Population storage.  ST_F32: nine float32 planes.  ST_F16 / ST_BF16: the rest
 // population g_0 as a float32 plane, then eight 16-bit planes holding g_i / w_i
@@ -149,7 +158,7 @@ __device__ __forceinline__ void finish_store(rsrc_t d, uint32_t plane, uint32_t 
   if (ST == ST_F32) {
     close_mass(m, g);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) stb(d, g[i], col * 4u, ((uint32_t)i * plane + row * nx) * 4u);
+    for (int i = 0; i < 9; ++i) stb_nt(d, g[i], col * 4u, ((uint32_t)i * plane + row * nx) * 4u);
     return;
   }
   uint32_t h[9];

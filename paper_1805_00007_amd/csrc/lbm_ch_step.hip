@@ -205,8 +205,8 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
     float fx = s1 * tx, fy = s1 * ty;
     if (HIST) {  // (2 tau - 1 + 3K) dF1/dt + 3 cs^2 eta K d(grad mu)/dt of Eq. F2-1
       const float xx = c.x_f1 * fx + c.x_mu * mux, xy = c.x_f1 * fy + c.x_mu * muy;
-      stb(rxh, xx, vc * 4u, (uint32_t)y * rb);
-      stb(rxh, xy, vc * 4u, nodes * 4u + (uint32_t)y * rb);
+      stb_nt(rxh, xx, vc * 4u, (uint32_t)y * rb);
+      stb_nt(rxh, xy, vc * 4u, nodes * 4u + (uint32_t)y * rb);
       if (!a.xfirst) {
         fx += xx - R.xpx;
         fy += xy - R.xpy;
@@ -221,7 +221,7 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
     }
     const float u = VMODE == VEL_SEP ? axc * R.fy_u : R.u;
     const float v = VMODE == VEL_SEP ? bxc * R.fy_v : R.v;
-    if (REC) stb(rrec, R.phi, vc * 4u, (uint32_t)y * rb);
+    if (REC) stb_nt(rrec, R.phi, vc * 4u, (uint32_t)y * rb);
     collide_g(c, R.phi, R.lo, m0[j], u, v, fx, fy, R.g);
     finish_store<ST>(rdst, plane, nx, vc, (uint32_t)y, (double)R.phi + (double)R.lo, R.g);
   };
@@ -506,7 +506,7 @@ __global__ void __launch_bounds__(TX) k_ns_step(const NsArgs a) {
           const float su = cu * (3.0f + 4.5f * cu) - usq15;
           const float feq = WT[i] * (p3 + rho * su) - (i == 0 ? p3 : 0.0f);
           const float G = WT[i] * (3.0f * (cF - uF) + 9.0f * cu * cF + 3.0f * cu * cr);
-          stb(rfd, om1 * fpop[i] + om * feq + c.srcf * G, off, i * pb + ro);
+          stb_nt(rfd, om1 * fpop[i] + om * feq + c.srcf * G, off, i * pb + ro);
         }
       }
     }
