@@ -1,0 +1,143 @@
+"""Brute-force pin of the oracle: two whole steps on an 8x8 periodic lattice computed
+here in 50-digit arithmetic, node by node, against the FP64 oracle.
+
+The computation below is written from the equations of the paper in forms that differ
+from the oracle's: the isotropic derivatives as weighted sums over the lattice
+directions, (1/cs^2) sum_i w_i c_i psi(x + c_i) and (2/cs^2) sum_i w_i (psi(x + c_i) -
+psi(x)), instead of explicit neighbour formulas; streaming as a push of every
+post-collision population to x + c_i instead of a pull; the lattice vectors and
+weights generated from their definition (|c_i|^2 = 0, 1, 2 with w = 4/9, 1/9, 1/36)
+instead of a table.  With 50 digits its own rounding is ~1e-50, so any difference
+above the oracle's FP64 rounding (~1e-15 on O(1) populations) is a slip in one of the
+two: a dropped term, a wrong sign, index or direction.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+
+mpmath = pytest.importorskip("mpmath")
+mp = mpmath.mp
+
+
+def _lattice():
+    """D2Q9: c in {-1,0,1}^2; w = 4/9, 1/9, 1/36 for |c|^2 = 0, 1, 2 (Sec. II)."""
+    cs = [(0, 0)] + [c for c in itertools.product((-1, 0, 1), repeat=2) if c != (0, 0)]
+    w = {0: mp.mpf(4) / 9, 1: mp.mpf(1) / 9, 2: mp.mpf(1) / 36}
+    return cs, [w[cx * cx + cy * cy] for cx, cy in cs]
+
+
+def _step_mp(g, ux, uy, par, n, first):
+    """One step of Eqs. LB, geq, liangFi, mu, t0-phiu, mark3 on the periodic lattice;
+    g maps (c, x, y) -> population.  Returns the new populations.  With first, g is
+    ignored and the equilibrium start of the scheme is returned instead."""
+    cs, w = _lattice()
+    cs2 = mp.mpf(1) / 3
+    tau = par["tau"]
+    pa, pb = par["phi_a"], par["phi_b"]
+    beta = 12 * par["sigma"] / (par["width"] * (pa - pb) ** 4)
+    kappa = 3 * par["sigma"] * par["width"] / (2 * (pa - pb) ** 2)
+    eta = par["mobility"] / (cs2 * (tau - mp.mpf(1) / 2))
+    K = (tau - mp.mpf(1) / 6 - tau * tau) / (tau - mp.mpf(1) / 2)
+    a = (par["rho_a"] - par["rho_b"]) / (pa - pb)
+    b = (par["rho_b"] * pa - pb * par["rho_a"]) / (pa - pb)
+    nodes = [(x, y) for y in range(n) for x in range(n)]
+
+    def shift(x, y, c):
+        return ((x + c[0]) % n, (y + c[1]) % n)
+
+    def grad(psi):
+        return {p: (sum(wi * c[0] * psi[shift(*p, c)] for c, wi in zip(cs, w)) / cs2,
+                    sum(wi * c[1] * psi[shift(*p, c)] for c, wi in zip(cs, w)) / cs2)
+                for p in nodes}
+
+    def lap(psi):
+        return {p: 2 * sum(wi * (psi[shift(*p, c)] - psi[p]) for c, wi in zip(cs, w)) / cs2
+                for p in nodes}
+
+    if first:
+        phi = par["phi0"]
+    else:
+        phi = {p: sum(g[(c, *p)] for c in cs) for p in nodes}
+    lp = lap(phi)
+    mu = {p: 2 * beta * (phi[p] - pa) * (phi[p] - pb) * (2 * phi[p] - pa - pb) - kappa * lp[p]
+          for p in nodes}
+
+    def geq(p, c, wi):
+        u, v = ux[p], uy[p]
+        cu = c[0] * u + c[1] * v
+        s = cu / cs2 + cu * cu / (2 * cs2 * cs2) - (u * u + v * v) / (2 * cs2)
+        if c == (0, 0):
+            return phi[p] - (1 - wi) * eta * mu[p] + wi * phi[p] * s
+        return wi * (eta * mu[p] + phi[p] * s)
+
+    if first:  # equilibrium start, no source term
+        return {(c, *p): geq(p, c, wi) for p in nodes for c, wi in zip(cs, w)}
+    gm = grad(mu)
+    force = {}
+    for p in nodes:
+        rho = a * phi[p] + b
+        force[p] = [phi[p] / rho * (-phi[p] * gm[p][0]), phi[p] / rho * (-phi[p] * gm[p][1])]
+    if par["model"] == 2:
+        qx = {p: phi[p] * ux[p] for p in nodes}
+        qy = {p: phi[p] * uy[p] for p in nodes}
+        gqx, gqy = grad(qx), grad(qy)
+        div = {p: gqx[p][0] + gqy[p][1] for p in nodes}
+        gd = grad(div)
+        for p in nodes:
+            force[p][0] += 3 * cs2 * K * gd[p][0]
+            force[p][1] += 3 * cs2 * K * gd[p][1]
+    out = {}
+    for p in nodes:
+        for c, wi in zip(cs, w):
+            src = wi * (c[0] * force[p][0] + c[1] * force[p][1]) / cs2
+            post = g[(c, *p)] - (g[(c, *p)] - geq(p, c, wi)) / tau + (1 - 1 / (2 * tau)) * src
+            out[(c, *shift(*p, c))] = post  # push
+    return out
+
+
+@pytest.mark.parametrize("tau,model", [(1.0, 2), (0.8, 2), (0.8, 1), (1.3, 2)])
+def test_two_steps_match_50_digit_brute_force(tau, model):
+    mp.dps = 50
+    n = 8
+    rng = np.random.default_rng(21)
+    phi0 = np.clip(rng.normal(0.0, 0.6, (n, n)), -1.2, 1.2)
+    ux = rng.uniform(-0.05, 0.05, (n, n))
+    uy = rng.uniform(-0.05, 0.05, (n, n))
+    phys = dict(tau_g=tau, mobility=0.02, sigma=0.01, width=3.0, phi_a=1.0, phi_b=-1.0,
+                rho_a=1.0, rho_b=0.4)
+    p = oracle.Params(nx=n, ny=n, model=model, **phys)
+    st = oracle.State(p, phi0, ux, uy)
+    orc = [st.g.copy()]
+    for _ in range(2):
+        st.run(1)
+        orc.append(st.g.copy())
+
+    par = {"tau": mp.mpf(tau), "model": model, "phi0": {}}
+    for k in ("mobility", "sigma", "width", "phi_a", "phi_b", "rho_a", "rho_b"):
+        par[k] = mp.mpf(phys[k])
+    U, V = {}, {}
+    for y in range(n):
+        for x in range(n):
+            par["phi0"][(x, y)] = mp.mpf(phi0[y, x])
+            U[(x, y)] = mp.mpf(ux[y, x])
+            V[(x, y)] = mp.mpf(uy[y, x])
+    g = _step_mp(None, U, V, par, n, first=True)
+    states = [g]
+    for _ in range(2):
+        g = _step_mp(g, U, V, par, n, first=False)
+        states.append(g)
+
+    # oracle population index i has c = (CX[i], CY[i]) in the standard D2Q9 order
+    cx = [0, 1, 0, -1, 0, 1, -1, -1, 1]
+    cy = [0, 0, 1, 0, -1, 1, 1, -1, -1]
+    for k, (gm, go) in enumerate(zip(states, orc)):
+        err = 0.0
+        for i in range(9):
+            for y in range(n):
+                for x in range(n):
+                    err = max(err, abs(float(gm[((cx[i], cy[i]), x, y)]) - go[i, y, x]))
+        print("tau %.2f model %d after %d steps: max |g_oracle - g_brute| = %.2e" % (tau, model, k, err))
+        assert err <= 1e-14, (k, err)
