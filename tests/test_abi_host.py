@@ -44,6 +44,12 @@ def test_invalid_params_rejected(bad):
     assert st == lbm.EINVAL and not ctx.value
 
 
+def test_largest_lattice_accepted():
+    # float32 populations of one buffer must stay below 2^31 bytes (9 x 4 B per node)
+    assert lbm.lib().lbm_ch_workspace_bytes(ctypes.byref(lbm.make_params(7680, 7760))) > 0
+    assert lbm.lib().lbm_ch_workspace_bytes(ctypes.byref(lbm.make_params(7680, 7776))) == 0
+
+
 def test_sizes_rejected():
     for nx, ny in [(3, 64), (64, 3), (40000, 40000)]:
         p = lbm.make_params(nx, ny)
