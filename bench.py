@@ -137,7 +137,8 @@ def storage_variant(lbm, torch, storage, steps):
 def adjoint_leg(lbm, torch, reps=3):
     """One forward plus backward pass of the 256^2, 2000-step interface-matching problem
     (16 stream-function coefficients, sqrt(N) checkpointing), against the plain forward
-    run of the same workload, and its gradients against stored FP64 central differences.
+    run of the same workload (one call of N plain launches; also its segments replayed
+    from captured hipGraphs), and its gradients against stored FP64 central differences.
     Both run on the tile shape the autotuner picks for this lattice (tuned once, not
     timed)."""
     import numpy as np
@@ -157,12 +158,23 @@ def adjoint_leg(lbm, torch, reps=3):
     tiles, _ = probe.autotune(5)
     probe.close()
 
-    def plain():
+    seg = int(np.ceil(np.sqrt(steps)))
+
+    def plain(graphs=False):
+        # graphs: the forward pass's own launch pattern (segments of ceil(sqrt(N)) steps
+        # replayed from captured hipGraphs, the captures included in the time)
         s = lbm.Solver(case.n, case.n, case.phi0, field=(U, V), device=dev, **case.phys)
         s.set_tiles(*tiles)
+        s.set_graphs(graphs)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        s.step(steps)
+        if graphs:
+            n = 0
+            while n < steps:
+                s.step(min(seg, steps - n))
+                n += seg
+        else:
+            s.step(steps)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         s.close()
@@ -183,8 +195,10 @@ def adjoint_leg(lbm, torch, reps=3):
             phi0.grad.double().cpu().numpy()
 
     plain()
+    plain(True)
     fwd_bwd()
     t_plain = min(plain() for _ in range(reps))
+    t_plain_g = min(plain(True) for _ in range(reps))
     runs = [fwd_bwd() for _ in range(reps)]
     t_adj = min(r[0] for r in runs)
     _, loss, gt, gp = runs[0]
@@ -193,6 +207,9 @@ def adjoint_leg(lbm, torch, reps=3):
             "adjoint_ms": round(t_adj * 1e3, 2),
             "forward_ms_plain": round(t_plain * 1e3, 2),
             "ratio_to_plain_forward": round(t_adj / t_plain, 2),
+            "forward_ms_plain_graphs": round(t_plain_g * 1e3, 2),
+            "ratio_to_plain_forward_graphs": round(t_adj / t_plain_g, 2),
+
             "checkpoints": -(-steps // (int(np.ceil(np.sqrt(steps))))),
             "tiles": {"tx": tiles[0], "ty": tiles[1]},
             "loss_rel_err": abs(loss - float(g["loss"])) / float(g["loss"]),

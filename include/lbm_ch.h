@@ -188,6 +188,20 @@ int lbm_ch_load_state(lbm_ch_ctx* ctx, const void* src, size_t bytes, int64_t st
 int lbm_ch_set_tiles(lbm_ch_ctx* ctx, int32_t tx, int32_t ty);
 int lbm_ch_get_tiles(const lbm_ch_ctx* ctx, int32_t* tx, int32_t* ty);
 
+/* Graph replay (enable = 1; 0, the default, turns it off and frees the cached graphs).
+ * With it on, lbm_ch_step, lbm_ch_record and lbm_ch_adjoint capture the launches of a
+ * call once into a hipGraph, on a capture stream the context owns, and replay it with
+ * one graph launch whenever a later call repeats the same arguments (step count,
+ * current buffer, caller pointers): on small lattices, where each launch is short, this
+ * removes most of the gap between dependent launches.  Results are identical to the
+ * plain launches.  Runs whose launch arguments change from step to step (a per-step
+ * time-factor table) keep the plain launches; model 3's first step is launched plainly.
+ * Up to 16 graphs are cached per context (least recently used dropped first); a change
+ * of tile shape drops them all.  The caller buffers named in a cached graph must stay
+ * allocated while it may be replayed; calls on one context must not overlap.  Errors:
+ * LBM_CH_EINVAL for other values of enable. */
+int lbm_ch_set_graphs(lbm_ch_ctx* ctx, int32_t enable);
+
 /* Autotuner: time trial_steps >= 1 steps (after one untimed step) for each tile shape
  * tx in {64, 128, 256} (skipping widths with more than half the lanes idle) and ty in
  * {1, 2, 4, 8, 16, 32}, keep the fastest, and restore the state and step counter from

@@ -28,7 +28,7 @@ STORE_F32, STORE_F16, STORE_BF16 = 0, 1, 2
 EXPORTS = ("lbm_ch_workspace_bytes", "lbm_ch_init", "lbm_ch_step", "lbm_ch_moments",
            "lbm_ch_diagnostics", "lbm_ch_check_finite", "lbm_ch_step_count",
            "lbm_ch_state_bytes", "lbm_ch_save_state", "lbm_ch_load_state",
-           "lbm_ch_set_tiles", "lbm_ch_get_tiles", "lbm_ch_autotune",
+           "lbm_ch_set_tiles", "lbm_ch_get_tiles", "lbm_ch_set_graphs", "lbm_ch_autotune",
            "lbm_ch_adjoint_scratch_bytes", "lbm_ch_record", "lbm_ch_adjoint",
            "lbm_ch_batch_workspace_bytes", "lbm_ch_batch_create", "lbm_ch_batch_set_tiles",
            "lbm_ch_batch_get_tiles", "lbm_ch_batch_set_schedule", "lbm_ch_batch_get_schedule",
@@ -92,6 +92,7 @@ def lib():
         L.lbm_ch_save_state.argtypes = [vp, vp, ctypes.c_size_t, vp]
         L.lbm_ch_load_state.argtypes = [vp, vp, ctypes.c_size_t, i64, vp]
         L.lbm_ch_set_tiles.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+        L.lbm_ch_set_graphs.argtypes = [vp, ctypes.c_int32]
         L.lbm_ch_get_tiles.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32)]
         L.lbm_ch_autotune.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int32, vp,
@@ -277,6 +278,11 @@ class Solver:
 
     def set_tiles(self, tx, ty):
         _check(lib().lbm_ch_set_tiles(self.ctx, int(tx), int(ty)), "lbm_ch_set_tiles")
+        return self
+
+    def set_graphs(self, enable=True):
+        """Replay repeated step / record / adjoint calls as captured hipGraphs."""
+        _check(lib().lbm_ch_set_graphs(self.ctx, int(bool(enable))), "lbm_ch_set_graphs")
         return self
 
     def autotune(self, trial_steps=20):

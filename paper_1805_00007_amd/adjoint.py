@@ -7,7 +7,8 @@ times fixed mode fields) reaches its parameters through ordinary torch operation
 and V before the call.
 
 Forward: the solver runs N steps on the GPU and keeps its state every S = ceil(sqrt(N))
-steps (``lbm_ch_save_state``).  Backward: for each segment from the last, the state is
+steps (``lbm_ch_save_state``); with ``graphs=True`` the repeated segment launches are
+replayed as captured hipGraphs.  Backward: for each segment from the last, the state is
 reloaded, the segment re-run with ``lbm_ch_record`` (phi^n of every step), and
 ``lbm_ch_adjoint`` carries dL/dphi back over it while accumulating dL/d(U, V).  Memory:
 ceil(N/S) states plus S phi fields.  All derivative arithmetic runs in the library's
@@ -24,11 +25,12 @@ from . import Solver
 
 class _Evolve(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, phi0, U, V, steps, segment, tf, params, tune):
+    def forward(ctx, phi0, U, V, steps, segment, tf, params, tune, graphs):
         ny, nx = phi0.shape
         s = Solver(nx, ny, phi0.detach(), field=(U.detach(), V.detach()), tf=tf,
                    device=phi0.device, **params)
         s.stream.wait_stream(torch.cuda.current_stream(phi0.device))
+        s.set_graphs(graphs)
         if isinstance(tune, tuple):
             s.set_tiles(*tune)
         elif tune:
@@ -64,17 +66,20 @@ class _Evolve(torch.autograd.Function):
                 s.record(k, traj)
                 s.adjoint(n0 + k, k, traj, lam, gu, gv, scratch)
         torch.cuda.current_stream(dev).wait_stream(s.stream)
-        return lam, gu, gv, None, None, None, None, None
+        return lam, gu, gv, None, None, None, None, None, None
 
 
-def evolve(phi0, U, V, steps, *, tf=None, segment=None, autotune=0, tiles=None, **params):
+def evolve(phi0, U, V, steps, *, tf=None, segment=None, autotune=0, tiles=None, graphs=False,
+           **params):
     """phi after ``steps`` steps from ``phi0`` (ny, nx) in the velocity field tf[n] (U, V),
     differentiable in phi0, U and V.  ``params`` are those of ``lbm_ch_params``; the
     derivative needs tau_g = 1, periodic boundaries and a prescribed velocity.
     ``tiles=(tx, ty)`` fixes the step kernels' tile shape; otherwise ``autotune`` > 0
     times that many trial steps per tile shape first (the state is restored; the
-    forward run and its recomputation then use the fastest shape)."""
+    forward run and its recomputation then use the fastest shape).  ``graphs``: replay
+    the repeated segment launches as captured hipGraphs (``lbm_ch_set_graphs``; same
+    results; at 256^2 the captures a pass needs cost about what the replays save)."""
     if float(params.get("tau_g", 1.0)) != 1.0 or params.get("walls", 0):
         raise ValueError("the discrete adjoint covers tau_g = 1 on a periodic lattice")
     tune = tuple(int(t) for t in tiles) if tiles is not None else int(autotune)
-    return _Evolve.apply(phi0, U, V, int(steps), segment, tf, dict(params), tune)
+    return _Evolve.apply(phi0, U, V, int(steps), segment, tf, dict(params), tune, bool(graphs))

@@ -101,8 +101,26 @@ struct lbm_ch_ctx {
   const float *ax, *ay, *bx, *by, *ux, *uy;
   std::vector<double> tf;
   int tx, ty, nstrips, nblocks, xcd_remap;
+  int graphs;                     // lbm_ch_set_graphs: replay captured launch sequences
+  hipStream_t cap;                // capture stream, created at the first capture
+  std::vector<struct CtxExec> execs;  // cached executable graphs, most recently used last
   uint32_t magic;
 };
+
+// One cached launch sequence: kind 0 = steps, 1 = recorded steps, 2 = reverse steps;
+// n steps starting from buffer `cur` (kinds 0, 1); p = the caller pointers it uses.
+struct CtxExec {
+  hipGraphExec_t exec;
+  int kind;
+  int64_t n;
+  int cur;
+  const void* p[5];
+};
+
+static void drop_graphs(lbm_ch_ctx* c) {
+  for (CtxExec& x : c->execs) (void)hipGraphExecDestroy(x.exec);
+  c->execs.clear();
+}
 
 static constexpr uint32_t CTX_MAGIC = 0x4c424d43u;
 
@@ -118,6 +136,7 @@ static float time_factor(const lbm_ch_ctx* c, int64_t n) {
 static bool valid_tile(int tx, int ty) { return (tx == 64 || tx == 128 || tx == 256) && ty >= 1; }
 
 static void apply_tiles(lbm_ch_ctx* c, int tx, int ty) {
+  drop_graphs(c);  // the launch shape is part of every captured sequence
   const int nx = c->p.nx, ny = c->p.ny;
   if (ty > ny) ty = ny;
   c->tx = tx;
@@ -354,10 +373,98 @@ static int run_steps(lbm_ch_ctx* c, int64_t nsteps, float* phi_out, hipStream_t 
   return LBM_CH_OK;
 }
 
+extern "C++" {
+// Replay of captured launch sequences (lbm_ch_set_graphs).  A sequence is captured once
+// per key on the context's own stream and replayed with one graph launch; the key holds
+// everything the captured kernel arguments depend on besides the context's fixed
+// buffers and launch shape (apply_tiles drops the cache).
+static bool same_key(const CtxExec& a, const CtxExec& b) {
+  if (a.kind != b.kind || a.n != b.n || a.cur != b.cur) return false;
+  for (int i = 0; i < 5; ++i)
+    if (a.p[i] != b.p[i]) return false;
+  return true;
+}
+
+// Launch the cached graph for `key`, or capture `enqueue(stream)` into one and launch it.
+// Returns 1 if a cached graph was launched (the caller then applies the host-side effects
+// of the sequence itself), 0 if it was captured now (enqueue has applied them), or a
+// negative status.
+template <class F>
+static int graph_run(lbm_ch_ctx* c, CtxExec key, hipStream_t stream, F&& enqueue) {
+  for (size_t i = 0; i < c->execs.size(); ++i) {
+    if (!same_key(c->execs[i], key)) continue;
+    const CtxExec hit = c->execs[i];
+    c->execs.erase(c->execs.begin() + (long)i);
+    c->execs.push_back(hit);
+    const hipError_t e = hipGraphLaunch(hit.exec, stream);
+    return e == hipSuccess ? 1 : hip_fail(e);
+  }
+  hipError_t e = hipSuccess;
+  if (!c->cap) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e);
+  const int r = enqueue(c->cap);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(c->cap, &graph);
+  hipGraphExec_t exec = nullptr;
+  if (r == LBM_CH_OK && e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (r != LBM_CH_OK) return r;
+  if (e != hipSuccess) return hip_fail(e);
+  if (c->execs.size() >= 16) {
+    (void)hipGraphExecDestroy(c->execs.front().exec);
+    c->execs.erase(c->execs.begin());
+  }
+  key.exec = exec;
+  c->execs.push_back(key);
+  e = hipGraphLaunch(exec, stream);
+  return e == hipSuccess ? 0 : hip_fail(e);
+}
+
+// Steps (phi_out: recorded steps) through a graph where the launch arguments do not
+// change from step to step: no per-step time-factor table, and past model 3's first step
+// (the only one without an earlier history).
+static int graph_steps(lbm_ch_ctx* c, int64_t nsteps, float* phi_out, hipStream_t stream) {
+  if (!c->graphs || !c->tf.empty() || nsteps == 0) return run_steps(c, nsteps, phi_out, stream);
+  if (c->p.model == 3 && c->step == 0) {
+    const int r = run_steps(c, 1, phi_out, stream);
+    if (r != LBM_CH_OK || nsteps == 1) return r;
+    nsteps -= 1;
+    if (phi_out) phi_out += (size_t)c->p.nx * c->p.ny;
+  }
+  CtxExec key{};
+  key.kind = phi_out ? 1 : 0;
+  key.n = nsteps;
+  key.cur = c->cur;
+  key.p[0] = phi_out;
+  const int cur0 = c->cur;
+  const int64_t step0 = c->step;
+  const int r = graph_run(c, key, stream, [&](hipStream_t s) { return run_steps(c, nsteps, phi_out, s); });
+  if (r == 1) {
+    c->cur = cur0 ^ (int)(nsteps & 1);
+    c->step = step0 + nsteps;
+    return LBM_CH_OK;
+  }
+  if (r < 0) {  // nothing ran: the captured host-side updates are undone
+    c->cur = cur0;
+    c->step = step0;
+  }
+  return r;
+}
+}  // extern "C++"
+
 int lbm_ch_step(lbm_ch_ctx* c, int64_t nsteps, hipStream_t stream) {
   if (!live(c)) return LBM_CH_ESTATE;
   if (nsteps < 0) return LBM_CH_EINVAL;
-  return run_steps(c, nsteps, nullptr, stream);
+  return graph_steps(c, nsteps, nullptr, stream);
+}
+
+int lbm_ch_set_graphs(lbm_ch_ctx* c, int32_t enable) {
+  if (!live(c)) return LBM_CH_ESTATE;
+  if (enable != 0 && enable != 1) return LBM_CH_EINVAL;
+  c->graphs = enable;
+  if (!enable) drop_graphs(c);
+  return LBM_CH_OK;
 }
 
 int lbm_ch_moments(lbm_ch_ctx* c, float* phi, float* mu, float* ux, float* uy, float* p,
@@ -498,10 +605,10 @@ int lbm_ch_autotune(lbm_ch_ctx* c, void* backup, size_t backup_bytes, int32_t tr
     for (int yy : {1, 2, 4, 8, 16, 32}) {
       if (yy > ny && yy > 2) continue;
       apply_tiles(c, xx, yy);
-      r = lbm_ch_step(c, 1, stream);  // untimed: first launch of this kernel shape
+      r = run_steps(c, 1, nullptr, stream);  // untimed: first launch of this kernel shape
       if (r == LBM_CH_OK) {
         e = hipEventRecord(e0, stream);
-        if (e == hipSuccess) r = lbm_ch_step(c, trial_steps, stream);
+        if (e == hipSuccess) r = run_steps(c, trial_steps, nullptr, stream);
         if (e == hipSuccess && r == LBM_CH_OK) e = hipEventRecord(e1, stream);
         if (e == hipSuccess && r == LBM_CH_OK) e = hipEventSynchronize(e1);
       }
@@ -538,7 +645,7 @@ int lbm_ch_record(lbm_ch_ctx* c, int64_t nsteps, float* phi_traj, hipStream_t st
   if (nsteps < 0) return LBM_CH_EINVAL;
   if (nsteps == 0) return LBM_CH_OK;
   if (!phi_traj || !aligned4(phi_traj)) return LBM_CH_EINVAL;
-  return run_steps(c, nsteps, phi_traj, stream);
+  return graph_steps(c, nsteps, phi_traj, stream);
 }
 
 int lbm_ch_adjoint(lbm_ch_ctx* c, int64_t n_end, int64_t nsteps, const float* phi_traj,
@@ -556,29 +663,45 @@ int lbm_ch_adjoint(lbm_ch_ctx* c, int64_t n_end, int64_t nsteps, const float* ph
   if (!scratch || !aligned4(scratch) || scratch_bytes < lbm_ch_adjoint_scratch_bytes(&c->p))
     return LBM_CH_EINVAL;
   const size_t nodes = (size_t)c->p.nx * c->p.ny;
-  // lam and the scratch field alternate as source and destination
-  float* buf[2] = {lam, (float*)scratch};
-  int cur = 0;
-  for (int64_t k = nsteps - 1; k >= 0; --k) {
-    const int64_t n = n_end - nsteps + k;
-    hipError_t e = launch_adjoint_step(
-        c->c, (float)c->p.mobility, c->p.nx, c->p.ny, c->vmode, c->ax, c->ay, c->bx, c->by,
-        c->ux, c->uy, time_factor(c, n), phi_traj + (size_t)k * nodes, buf[cur], buf[cur ^ 1],
-        grad_u, grad_v, stream);
-    if (e != hipSuccess) return hip_fail(e);
-    cur ^= 1;
-  }
-  if (cur != 0) {
-    hipError_t e = hipMemcpyAsync(lam, scratch, nodes * sizeof(float), hipMemcpyDeviceToDevice,
-                                  stream);
-    if (e != hipSuccess) return hip_fail(e);
-  }
-  return LBM_CH_OK;
+  auto enqueue = [&](hipStream_t s) -> int {
+    // lam and the scratch field alternate as source and destination
+    float* buf[2] = {lam, (float*)scratch};
+    int cur = 0;
+    for (int64_t k = nsteps - 1; k >= 0; --k) {
+      const int64_t n = n_end - nsteps + k;
+      hipError_t e = launch_adjoint_step(
+          c->c, (float)c->p.mobility, c->p.nx, c->p.ny, c->vmode, c->ax, c->ay, c->bx, c->by,
+          c->ux, c->uy, time_factor(c, n), phi_traj + (size_t)k * nodes, buf[cur],
+          buf[cur ^ 1], grad_u, grad_v, s);
+      if (e != hipSuccess) return hip_fail(e);
+      cur ^= 1;
+    }
+    if (cur != 0) {
+      hipError_t e = hipMemcpyAsync(lam, scratch, nodes * sizeof(float),
+                                    hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return hip_fail(e);
+    }
+    return LBM_CH_OK;
+  };
+  // the reverse steps of a steady velocity depend on n_end only through the trajectory
+  if (!c->graphs || !c->tf.empty()) return enqueue(stream);
+  CtxExec key{};
+  key.kind = 2;
+  key.n = nsteps;
+  key.p[0] = phi_traj;
+  key.p[1] = lam;
+  key.p[2] = grad_u;
+  key.p[3] = grad_v;
+  key.p[4] = scratch;
+  const int r = graph_run(c, key, stream, enqueue);
+  return r > 0 ? LBM_CH_OK : r;
 }
 
 int lbm_ch_destroy(lbm_ch_ctx* c) {
   if (!c) return LBM_CH_OK;
   if (!live(c)) return LBM_CH_ESTATE;
+  drop_graphs(c);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   c->magic = 0;
   delete c;
   return LBM_CH_OK;

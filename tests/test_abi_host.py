@@ -101,6 +101,7 @@ def test_context_calls_reject_null_and_strerror():
     assert L.lbm_ch_diagnostics(None, None, None, None) == lbm.ESTATE
     assert L.lbm_ch_step_count(None) == -1
     assert L.lbm_ch_record(None, 1, None, None) == lbm.ESTATE
+    assert L.lbm_ch_set_graphs(None, 1) == lbm.ESTATE
     assert L.lbm_ch_adjoint(None, 1, 1, None, None, None, None, None, 0, None) == lbm.ESTATE
     assert L.lbm_ch_destroy(None) == lbm.OK
     assert L.lbm_ch_batch_step(None, 1, 0, None) == lbm.ESTATE
