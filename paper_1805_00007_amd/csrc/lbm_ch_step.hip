@@ -236,26 +236,30 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
   const int d = dir;
   RowRec A, B, C, N, H0;
   {
-    RowRec T0, T1;
+    // wave 0 pulls the first two halo rows with the own rows, so the prologue has two
+    // dependent round trips to memory instead of three
+    RowRec T0, T1, U0, U1;
+    if (hwave) {
+      issue(y0 - 2 * d, hvc, hvm, hvp, U0, false);
+      issue(y0 - d, hvc, hvm, hvp, U1, false);
+    }
     issue(y0 - 2 * d, vc, vm, vp, T0);
     issue(y0 - d, vc, vm, vp, T1);
     issue(y0, vc, vm, vp, A);
     issue(y0 + d, vc, vm, vp, B);
+    if (hwave) {
+      stage1(y0 - 2 * d, U0, hj, axh, bxh, hl);
+      stage1(y0 - d, U1, hj, axh, bxh, hl);
+      issue(y0, hvc, hvm, hvp, U0, false);
+      issue(y0 + d, hvc, hvm, hvp, U1, false);
+    }
     stage1(y0 - 2 * d, T0, j, axc, bxc);
     stage1(y0 - d, T1, j, axc, bxc);
-    if (hl) {
-      issue(y0 - 2 * d, hvc, hvm, hvp, T0, false);
-      issue(y0 - d, hvc, hvm, hvp, T1, false);
-    }
     stage1(y0, A, j, axc, bxc);
     stage1(y0 + d, B, j, axc, bxc);
-    if (hl) {
-      stage1(y0 - 2 * d, T0, hj, axh, bxh);
-      stage1(y0 - d, T1, hj, axh, bxh);
-      issue(y0, hvc, hvm, hvp, T0, false);
-      issue(y0 + d, hvc, hvm, hvp, T1, false);
-      stage1(y0, T0, hj, axh, bxh);
-      stage1(y0 + d, T1, hj, axh, bxh);
+    if (hwave) {
+      stage1(y0, U0, hj, axh, bxh, hl);
+      stage1(y0 + d, U1, hj, axh, bxh, hl);
     }
   }
   if (hwave) issue(y0 + 2 * d, hvc, hvm, hvp, H0, false);
@@ -272,9 +276,10 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
   if (hwave) stage1(y0 + 2 * d, H0, hj, axh, bxh, hl);
   stage1(y0 + 2 * d, C, j, axc, bxc);
 
-  // One marching row.  On a block's last rows the pull of y+3d is not needed; it is
-  // clamped to the last row the block does need (already in cache), so the pipeline
-  // has no branch and fetches nothing extra.
+  // One marching row.  On a block's last row the pull of y+3d is not needed; it is
+  // clamped to the last row the block does need (already in cache), so the pull has no
+  // branch and fetches nothing extra, and its stage 1 is skipped (a scalar branch), so
+  // the block does not wait for it.
   const int last_needed = y0 + (rows + 1) * d;
 #pragma unroll 1
   for (int k = 0; k < rows; ++k) {
@@ -292,8 +297,10 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
     stage3(y, A);
     __builtin_amdgcn_sched_barrier(0);
     // row y+3d takes the ring slot of row y-d, which no later stage reads
-    if (hwave) stage1(y + 3 * d, H0, hj, axh, bxh, hl);
-    stage1(y + 3 * d, N, j, axc, bxc);
+    if (k + 1 < rows) {
+      if (hwave) stage1(y + 3 * d, H0, hj, axh, bxh, hl);
+      stage1(y + 3 * d, N, j, axc, bxc);
+    }
     A = B;
     B = C;
     C = N;
