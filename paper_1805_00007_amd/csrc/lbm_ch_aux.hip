@@ -307,33 +307,56 @@ __global__ void __launch_bounds__(ATW * ATH) k_adjoint(const AdjArgs a) {
   const int nx = a.nx, ny = a.ny;
   const int t = threadIdx.x;
   const int x0 = blockIdx.x * ATW, y0 = blockIdx.y * ATH;
-  // This thread's own node: its velocity and accumulated gradients are loaded first, so
-  // that their latency overlaps the staging below instead of following the barriers.
+  // Every global load of the step is issued up front, into registers, and used only
+  // after that: the staged lam' and phi values of this thread, and its own node's
+  // velocity and accumulated gradients.  So the step waits for memory once.
   const int ty = t / ATW, tx = t - ty * ATW;
   const int x = x0 + tx, y = y0 + ty;
   const bool own = x < nx && y < ny;
   const uint32_t k = own ? (uint32_t)y * nx + x : 0u;
-  float u = 0.f, v = 0.f, gu0 = 0.f, gv0 = 0.f;
+  constexpr int NL = (L3H * L3W + NT - 1) / NT, NP = (P2H * P2W + NT - 1) / NT;
+  float vl[NL], vp[NP];
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int i = t + q * NT;
+    const int r = i / L3W, cc = i - r * L3W;
+    vl[q] = i < L3H * L3W
+                ? a.lam1[(uint32_t)wrap(y0 - 3 + r, ny) * nx + wrap(x0 - 3 + cc, nx)]
+                : 0.f;
+  }
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    const int i = t + q * NT;
+    const int r = i / P2W, cc = i - r * P2W;
+    vp[q] = i < P2H * P2W
+                ? a.phi[(uint32_t)wrap(y0 - 2 + r, ny) * nx + wrap(x0 - 2 + cc, nx)]
+                : 0.f;
+  }
+  float u1 = 0.f, u2 = 0.f, v1 = 0.f, v2 = 0.f, gu0 = 0.f, gv0 = 0.f;
   if (own) {
     if (a.vmode == VEL_SEP) {
-      u = a.tf * a.ax[x] * a.ay[y];
-      v = a.tf * a.bx[x] * a.by[y];
+      u1 = a.ax[x];
+      u2 = a.ay[y];
+      v1 = a.bx[x];
+      v2 = a.by[y];
     } else {
-      u = a.tf * a.ux[k];
-      v = a.tf * a.uy[k];
+      u1 = a.ux[k];
+      v1 = a.uy[k];
     }
     if (a.gu) {
       gu0 = a.gu[k];
       gv0 = a.gv[k];
     }
   }
-  for (int i = t; i < L3H * L3W; i += NT) {
-    const int r = i / L3W, cc = i - r * L3W;
-    sl[r][cc] = a.lam1[(uint32_t)wrap(y0 - 3 + r, ny) * nx + wrap(x0 - 3 + cc, nx)];
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int i = t + q * NT;
+    if (i < L3H * L3W) sl[i / L3W][i - (i / L3W) * L3W] = vl[q];
   }
-  for (int i = t; i < P2H * P2W; i += NT) {
-    const int r = i / P2W, cc = i - r * P2W;
-    sp[r][cc] = a.phi[(uint32_t)wrap(y0 - 2 + r, ny) * nx + wrap(x0 - 2 + cc, nx)];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    const int i = t + q * NT;
+    if (i < P2H * P2W) sp[i / P2W][i - (i / P2W) * P2W] = vp[q];
   }
   __syncthreads();
   // lamF = grad(lam')/2 and h lamF on the halo-2 region (sl is offset by one more)
@@ -367,6 +390,14 @@ __global__ void __launch_bounds__(ATW * ATH) k_adjoint(const AdjArgs a) {
   __syncthreads();
   if (!own) return;
   const float phi = sp[ty + 2][tx + 2];
+  float u, v;
+  if (a.vmode == VEL_SEP) {
+    u = a.tf * u1 * u2;
+    v = a.tf * v1 * v2;
+  } else {
+    u = a.tf * u1;
+    v = a.tf * v1;
+  }
   const float usq = u * u + v * v;
   // advection part: sum_i w_i s_i(u) lam'(x + c_i), and its u-derivative times phi
   float lam = sl[ty + 3][tx + 3], lu = 0.f, lv = 0.f;
