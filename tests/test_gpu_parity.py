@@ -159,6 +159,20 @@ def test_diagnostics_match_oracle(lbm):
     assert s.check_finite() == lbm.OK
 
 
+def test_nonfinite_is_reported(lbm):
+    """A NaN in the initial field spreads through the stencils; the FP64 diagnostics
+    count the non-finite nodes and lbm_ch_check_finite reports LBM_CH_ENONFINITE."""
+    w = workloads.vortex(64, period=400, steps=20)
+    phi0 = np.array(w.phi0, dtype=np.float64)
+    phi0[20, 30] = np.nan
+    s = lbm.Solver(64, 64, phi0, velocity=w.velocity, **w.phys).step(5)
+    d = s.diagnostics()
+    print("non-finite nodes after 5 steps:", d["nonfinite"])
+    assert d["nonfinite"] > 1
+    assert s.check_finite() == lbm.ENONFINITE
+    s.close()
+
+
 def _golden(name):
     import os
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
