@@ -219,6 +219,35 @@ def adjoint_leg(lbm, torch, reps=3):
             "reference": "FP64 oracle central differences, h = %g" % float(g["h"])}
 
 
+def rt_leg(lbm, torch, steps=500, warm=50):
+    """The coupled Rayleigh-Taylor step at its full 256x1024 size (walls in y, Atwood
+    0.5, Re 3000): one Navier-Stokes launch plus one phase-field launch per step.
+    Algorithmic bytes per node update: NS 36 (g) + 36 + 36 (f) + 12 (u, v, p written),
+    phase field 36 + 36 (g) + 12 (u, v, p read) = 204 B in float32; 16-bit g storage
+    saves 3 x 16 B = 48 B."""
+    import workloads
+    w = workloads.rayleigh_taylor_case(256, 1024, steps=steps + warm)
+    out = {"workload": "rayleigh_taylor 256x1024 (coupled NS + phase field, walls)"}
+    for name, st, bytes_lu in (("f32", 0, 204), ("f16", 1, 156)):
+        s = lbm.solver_for(w, storage=st)
+        s.step(warm)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s.stream)
+        s.step(steps)
+        e1.record(s.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        d = s.diagnostics()
+        s.close()
+        lu = w.nx * w.ny / (ms * 1e-3)
+        out[name] = {"MLUPS": round(lu / 1e6, 1), "us_per_step": round(ms * 1e3, 2),
+                     "bytes_per_lu": bytes_lu,
+                     "effective_GBps": round(lu * bytes_lu / 1e9, 1),
+                     "nonfinite": int(d["nonfinite"])}
+    return out
+
+
 def batch_leg(lbm, torch, steps=5000, plain_steps=200, check_steps=100):
     """64 lattices of uneven sizes (sides 64-512, seeded): the batched kernel with the
     autotuned schedule (persistent grid or one workgroup per tile) and tiles, `steps`
@@ -390,6 +419,7 @@ def main():
         out["storage_variants"] = {name: storage_variant(lbm, torch, st, args.steps)
                                    for name, st in (("f16", 1), ("bf16", 2))}
         out["adjoint"] = adjoint_leg(lbm, torch)
+        out["rayleigh_taylor"] = rt_leg(lbm, torch)
         out["batched"] = batch_leg(lbm, torch)
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(workloads.metric2048(steps=args.cpu_steps),

@@ -183,8 +183,9 @@ int lbm_ch_load_state(lbm_ch_ctx* ctx, const void* src, size_t bytes, int64_t st
 
 /* Tile shape of the step kernels: tx columns (one lane each; 64, 128 or 256) by ty >= 1
  * rows per thread block (ty is clipped to ny).  The default is chosen at init from the
- * lattice size and storage (the widest, then tallest, shape that gives at least 512
- * blocks with float32 storage, 1024 with 16-bit); it changes speed only, never results.  Errors: LBM_CH_EINVAL for other shapes. */
+ * lattice size and storage (the widest, then tallest, shape with ty from 32 down to 1
+ * that gives at least 512 blocks with float32 storage, 1024 with 16-bit; 64 x 1 if none
+ * does); it changes speed only, never results.  Errors: LBM_CH_EINVAL for other shapes. */
 int lbm_ch_set_tiles(lbm_ch_ctx* ctx, int32_t tx, int32_t ty);
 int lbm_ch_get_tiles(const lbm_ch_ctx* ctx, int32_t* tx, int32_t* ty);
 

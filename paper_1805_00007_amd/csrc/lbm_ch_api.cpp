@@ -148,18 +148,19 @@ static void apply_tiles(lbm_ch_ctx* c, int tx, int ty) {
 }
 
 // Default: the widest tile (fewest halo columns), then the tallest (fewest halo rows
-// per row), that still gives at least 2 workgroups per CU on 256 CUs (float32), or 4
-// with 16-bit storage, whose extra decode work per byte needs more waves in flight to
-// cover memory latency; small lattices get the most workgroups.  LBM_CH_TILE=TXxTY
+// per row; heights 32 down to 1), that still gives at least 2 workgroups per CU on 256
+// CUs (float32), or 4 with 16-bit storage, whose extra decode work per byte needs more
+// waves in flight to cover memory latency.  Small lattices thus get short row chunks
+// (each block's march is a chain of dependent loads), and the smallest get 64 x 1.  LBM_CH_TILE=TXxTY
 // overrides; lbm_ch_autotune measures.
 static void choose_tiles(lbm_ch_ctx* c) {
   const int nx = c->p.nx, ny = c->p.ny;
   const long min_blocks = c->p.storage == LBM_CH_STORE_F32 ? 512 : 1024;
-  int tx = 64, ty = 4;
+  int tx = 64, ty = 1;
   bool found = false;
   for (int xx : {256, 128, 64}) {
     if (xx > nx && xx > 64) continue;
-    for (int yy : {32, 16, 8, 4}) {
+    for (int yy : {32, 16, 8, 4, 2, 1}) {
       const long nb = (long)((nx + xx - 1) / xx) * ((ny + yy - 1) / yy);
       if (nb >= min_blocks) {
         tx = xx;
