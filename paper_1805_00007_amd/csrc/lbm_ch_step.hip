@@ -430,12 +430,6 @@ __global__ void __launch_bounds__(TX) k_ns_step(const NsArgs a) {
   const int j2 = t == 0 ? 1 : TX + 2;
 
   const uint32_t rb = (uint32_t)nx * 4u;
-  auto phi_at = [&](int r, int col, int cm, int cq) {
-    float sg, g[9];
-    const int sr = row_of<WALLS>(r, ny, sg);
-    pull9<WALLS, ST>(rg, a.plane, nx, ny, sr, col, cm, cq, g);
-    return sum9(g);
-  };
   auto stage2 = [&](int r, int jj) {
     const float* pm = s_phi[(r - 1) & 7];
     const float* p0 = s_phi[r & 7];
@@ -443,10 +437,37 @@ __global__ void __launch_bounds__(TX) k_ns_step(const NsArgs a) {
     s_mu[r & 3][jj] = mu_bulk(c, p0[jj]) - c.kappa * lap9(pm, p0, pp, jj);
   };
 
-#pragma unroll 1
-  for (int r = y0 - 2; r <= y0 + 1; ++r) {
-    s_phi[r & 7][j] = phi_at(r, xc, xm, xp);
-    if (hl) s_phi[r & 7][hj] = phi_at(r, hc, hm, hp);
+  // Halo columns come from the four halo lanes of wave 0; the other lanes of that wave
+  // issue the same pulls at an out-of-range offset (a raw buffer load returns 0 without
+  // a memory access), and waves 1.. skip them (a scalar branch).
+  constexpr uint32_t OOB = 0x3FFFFFC0u;
+  const bool hwave = __builtin_amdgcn_readfirstlane(t) < 64;
+  const uint32_t hvc = hl ? (uint32_t)hc : OOB, hvm = hl ? (uint32_t)hm : OOB,
+                 hvp = hl ? (uint32_t)hp : OOB;
+  auto pull_g = [&](int r, uint32_t cc, uint32_t cm, uint32_t cq, float g[9]) {
+    float sg;
+    const int sr = row_of<WALLS>(r, ny, sg);
+    pull9<WALLS, ST>(rg, a.plane, nx, ny, sr, cc, cm, cq, g);
+  };
+  {
+    // prologue: rows y0-2 .. y0+1 of g (own and halo columns), all pulled before any
+    // is used, so the block waits for memory once
+    float ga[4][9], gh[4][9];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) pull_g(y0 - 2 + q, xc, xm, xp, ga[q]);
+    if (hwave) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) pull_g(y0 - 2 + q, hvc, hvm, hvp, gh[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s_phi[(y0 - 2 + q) & 7][j] = sum9(ga[q]);
+    if (hwave) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float ph = sum9(gh[q]);
+        if (hl) s_phi[(y0 - 2 + q) & 7][hj] = ph;
+      }
+    }
   }
   __syncthreads();
   stage2(y0 - 1, j);
@@ -455,17 +476,26 @@ __global__ void __launch_bounds__(TX) k_ns_step(const NsArgs a) {
     stage2(y0 - 1, j2);
     stage2(y0, j2);
   }
-  float fpop[9];
-  pull9<WALLS, ST_F32>(rf, a.plane, nx, ny, y0, xc, xm, xp, fpop);
   __syncthreads();
 
 #pragma unroll 1
   for (int k = 0; k < rows; ++k) {
     const int y = y0 + k;
-    float fnext[9];
-    if (k + 1 < rows) pull9<WALLS, ST_F32>(rf, a.plane, nx, ny, y + 1, xc, xm, xp, fnext);
-    s_phi[(y + 2) & 7][j] = phi_at(y + 2, xc, xm, xp);
-    if (hl) s_phi[(y + 2) & 7][hj] = phi_at(y + 2, hc, hm, hp);
+    // g of row y+2 first (needed before the barrier), then f of row y (needed after
+    // it): the wait for g leaves f in flight across the stage-2 work, and f is used in
+    // the same row, so no load is outstanding when the loop branches back
+    float gn[9], ghn[9], fpop[9];
+    __builtin_amdgcn_sched_barrier(0);
+    pull_g(y + 2, xc, xm, xp, gn);
+    if (hwave) pull_g(y + 2, hvc, hvm, hvp, ghn);
+    __builtin_amdgcn_sched_barrier(0);
+    pull9<WALLS, ST_F32>(rf, a.plane, nx, ny, y, xc, xm, xp, fpop);
+    __builtin_amdgcn_sched_barrier(0);
+    s_phi[(y + 2) & 7][j] = sum9(gn);
+    if (hwave) {
+      const float ph = sum9(ghn);
+      if (hl) s_phi[(y + 2) & 7][hj] = ph;
+    }
     __syncthreads();
     stage2(y + 1, j);
     if (t < 2) stage2(y + 1, j2);
@@ -517,8 +547,6 @@ __global__ void __launch_bounds__(TX) k_ns_step(const NsArgs a) {
         }
       }
     }
-#pragma unroll
-    for (int i = 0; i < 9; ++i) fpop[i] = fnext[i];
   }
 }
 
