@@ -9,6 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblbm_ch.so")
 SOURCES = [os.path.join(HERE, "csrc", "lbm_ch_step.hip"),
+           os.path.join(HERE, "csrc", "lbm_ch_ns.hip"),
            os.path.join(HERE, "csrc", "lbm_ch_aux.hip"),
            os.path.join(HERE, "csrc", "lbm_ch_api.cpp")]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -1,5 +1,5 @@
 // Internal interface between the host ABI (lbm_ch_api.cpp) and the gfx950 kernels
-// (lbm_ch_step.hip, lbm_ch_aux.hip).  Not installed; the public interface is
+// (lbm_ch_step.hip, lbm_ch_ns.hip, lbm_ch_aux.hip).  Not installed; the public interface is
 // include/lbm_ch.h.
 #pragma once
 
