@@ -229,7 +229,7 @@ def rt_leg(lbm, torch, steps=500, warm=50):
     w = workloads.rayleigh_taylor_case(256, 1024, steps=steps + warm)
     out = {"workload": "rayleigh_taylor 256x1024 (coupled NS + phase field, walls)"}
     for name, st, bytes_lu in (("f32", 0, 204), ("f16", 1, 156)):
-        s = lbm.solver_for(w, storage=st)
+        s = lbm.solver_for(w, walls=1, storage=st)
         s.step(warm)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()

@@ -25,7 +25,7 @@ def _case(mode):
     phys = dict(workloads.PRESCRIBED, model=2)
     if mode == "rt":
         w = workloads.rayleigh_taylor_case(64, 128, steps=400)
-        kw = dict(w.phys)
+        kw = dict(w.phys, walls=1)
         kw["ns"] = True
         return w.nx, w.ny, w.phi0, kw
     if mode in ("separable", "separable-tf"):
