@@ -180,13 +180,14 @@ def adjoint_leg(lbm, torch, reps=3):
         s.close()
         return dt
 
-    def fwd_bwd():
+    def fwd_bwd(store=False):
         phi0 = torch.tensor(case.phi0, dtype=torch.float32, device=dev, requires_grad=True)
         theta = torch.tensor(case.theta, dtype=torch.float32, device=dev, requires_grad=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         uv = case.scale * torch.tensordot(theta, basis, dims=1)
-        phi = evolve(phi0, uv[0], uv[1], steps, tiles=tiles, **case.phys)
+        phi = evolve(phi0, uv[0], uv[1], steps, tiles=tiles, store_trajectory=store,
+                     **case.phys)
         loss = ((phi - target) ** 2).sum()
         loss.backward()
         torch.cuda.synchronize()
@@ -201,6 +202,10 @@ def adjoint_leg(lbm, torch, reps=3):
     t_plain_g = min(plain(True) for _ in range(reps))
     runs = [fwd_bwd() for _ in range(reps)]
     t_adj = min(r[0] for r in runs)
+    fwd_bwd(True)
+    stored = [fwd_bwd(True) for _ in range(reps)]
+    t_store = min(r[0] for r in stored)
+    same = bool(np.array_equal(stored[0][2], runs[0][2]) and np.array_equal(stored[0][3], runs[0][3]))
     _, loss, gt, gp = runs[0]
     ref_t, ref_p = g["grad_theta"], g["grad_phi0"]
     return {"workload": "adjoint256: 256^2, %d steps, 16 stream-function coefficients" % steps,
@@ -209,6 +214,9 @@ def adjoint_leg(lbm, torch, reps=3):
             "ratio_to_plain_forward": round(t_adj / t_plain, 2),
             "forward_ms_plain_graphs": round(t_plain_g * 1e3, 2),
             "ratio_to_plain_forward_graphs": round(t_adj / t_plain_g, 2),
+            "adjoint_ms_stored_trajectory": round(t_store * 1e3, 2),
+            "stored_trajectory_MiB": round(steps * case.n * case.n * 4 / 2 ** 20, 1),
+            "stored_trajectory_grads_bitwise_equal": same,
 
             "checkpoints": -(-steps // (int(np.ceil(np.sqrt(steps))))),
             "tiles": {"tx": tiles[0], "ty": tiles[1]},

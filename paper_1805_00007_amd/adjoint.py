@@ -25,7 +25,7 @@ from . import Solver
 
 class _Evolve(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, phi0, U, V, steps, segment, tf, params, tune, graphs):
+    def forward(ctx, phi0, U, V, steps, segment, tf, params, tune, graphs, store):
         ny, nx = phi0.shape
         s = Solver(nx, ny, phi0.detach(), field=(U.detach(), V.detach()), tf=tf,
                    device=phi0.device, **params)
@@ -35,6 +35,17 @@ class _Evolve(torch.autograd.Function):
             s.set_tiles(*tune)
         elif tune:
             s.autotune(trial_steps=tune)
+        ctx.traj = None
+        if store:
+            # the whole trajectory phi^0 .. phi^{N-1} (N nx ny floats) instead of
+            # checkpoints: the backward pass then needs no recomputation
+            traj = torch.empty((steps, s.ny, s.nx), dtype=torch.float32, device=s.device)
+            if steps:
+                s.record(steps, traj)
+            phi = s.phi()
+            torch.cuda.current_stream(phi0.device).wait_stream(s.stream)
+            ctx.solver, ctx.ckpts, ctx.seg, ctx.traj = s, [], steps, traj
+            return phi
         seg = int(segment) if segment else max(1, math.isqrt(max(steps - 1, 0)) + 1)
         ckpts = []
         n = 0
@@ -59,18 +70,22 @@ class _Evolve(torch.autograd.Function):
             want_u = ctx.needs_input_grad[1] or ctx.needs_input_grad[2]
             gu = torch.zeros_like(lam) if want_u else None
             gv = torch.zeros_like(lam) if want_u else None
-            traj = torch.empty((ctx.seg, s.ny, s.nx), dtype=torch.float32, device=dev)
             scratch = torch.empty(s.adjoint_scratch_bytes(), dtype=torch.uint8, device=dev)
-            for n0, k, buf in reversed(ctx.ckpts):
-                s.load_state(buf, n0)
-                s.record(k, traj)
-                s.adjoint(n0 + k, k, traj, lam, gu, gv, scratch)
+            if ctx.traj is not None:
+                if ctx.seg:
+                    s.adjoint(ctx.seg, ctx.seg, ctx.traj, lam, gu, gv, scratch)
+            else:
+                traj = torch.empty((ctx.seg, s.ny, s.nx), dtype=torch.float32, device=dev)
+                for n0, k, buf in reversed(ctx.ckpts):
+                    s.load_state(buf, n0)
+                    s.record(k, traj)
+                    s.adjoint(n0 + k, k, traj, lam, gu, gv, scratch)
         torch.cuda.current_stream(dev).wait_stream(s.stream)
-        return lam, gu, gv, None, None, None, None, None, None
+        return lam, gu, gv, None, None, None, None, None, None, None
 
 
 def evolve(phi0, U, V, steps, *, tf=None, segment=None, autotune=0, tiles=None, graphs=False,
-           **params):
+           store_trajectory=False, **params):
     """phi after ``steps`` steps from ``phi0`` (ny, nx) in the velocity field tf[n] (U, V),
     differentiable in phi0, U and V.  ``params`` are those of ``lbm_ch_params``; the
     derivative needs tau_g = 1, periodic boundaries and a prescribed velocity.
@@ -78,8 +93,12 @@ def evolve(phi0, U, V, steps, *, tf=None, segment=None, autotune=0, tiles=None, 
     times that many trial steps per tile shape first (the state is restored; the
     forward run and its recomputation then use the fastest shape).  ``graphs``: replay
     the repeated segment launches as captured hipGraphs (``lbm_ch_set_graphs``; same
-    results; at 256^2 the captures a pass needs cost about what the replays save)."""
+    results; at 256^2 the captures a pass needs cost about what the replays save).
+    ``store_trajectory``: keep phi of every step (steps * nx * ny floats of device memory)
+    instead of sqrt(N) checkpoints, so the backward pass recomputes nothing (same
+    gradients)."""
     if float(params.get("tau_g", 1.0)) != 1.0 or params.get("walls", 0):
         raise ValueError("the discrete adjoint covers tau_g = 1 on a periodic lattice")
     tune = tuple(int(t) for t in tiles) if tiles is not None else int(autotune)
-    return _Evolve.apply(phi0, U, V, int(steps), segment, tf, dict(params), tune, bool(graphs))
+    return _Evolve.apply(phi0, U, V, int(steps), segment, tf, dict(params), tune, bool(graphs),
+                         bool(store_trajectory))

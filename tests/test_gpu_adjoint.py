@@ -163,14 +163,14 @@ def test_adjoint_separable_time_dependent_velocity(lbm):
 
 def test_checkpoint_segments_agree(lbm):
     """sqrt(N) checkpointing recomputes the same trajectory: gradients with segment
-    lengths 1, 7, sqrt(N) and N, and with other or autotuned tile shapes, agree
-    bitwise."""
+    lengths 1, 7, sqrt(N) and N, with the whole trajectory stored instead of
+    checkpoints, and with other or autotuned tile shapes, agree bitwise."""
     n, steps = 32, 50
     case = workloads.adjoint_case(n, steps)
     target = np.zeros((n, n))
     ref = None
-    for seg, kw in ((None, {}), (1, {}), (7, {}), (steps, {}), (None, dict(tiles=(64, 4))),
-                    (None, dict(autotune=2))):
+    for seg, kw in ((None, {}), (1, {}), (7, {}), (steps, {}), (None, dict(store_trajectory=True)),
+                    (None, dict(tiles=(64, 4))), (None, dict(autotune=2))):
         _, gt, gp = _gpu_grads(lbm, case, target, steps, segment=seg, **kw)
         if ref is None:
             ref = (gt, gp)
@@ -182,6 +182,8 @@ def test_adjoint_zero_steps_is_identity(lbm):
     n = 24
     case = workloads.adjoint_case(n, 0)
     _, gt, gp = _gpu_grads(lbm, case, np.zeros((n, n)), 0)
+    _, gt2, gp2 = _gpu_grads(lbm, case, np.zeros((n, n)), 0, store_trajectory=True)
+    assert np.array_equal(gt, gt2) and np.array_equal(gp, gp2)
     assert np.all(gt == 0)
     assert np.allclose(gp, 2 * case.phi0.astype(np.float32), rtol=0, atol=1e-6)
 
