@@ -230,8 +230,11 @@ size_t lbm_ch_adjoint_scratch_bytes(const lbm_ch_params* p);
 /* Enqueue nsteps steps exactly as lbm_ch_step does, and before each step n write the
  * order parameter phi^n into phi_traj + (n - n0) nx ny (n0: the step counter at the
  * call; phi_traj holds nsteps * nx * ny floats): the forward trajectory that
- * lbm_ch_adjoint reads.  Any mode.  Errors: LBM_CH_EINVAL for nsteps < 0 or a NULL or
- * unaligned phi_traj when nsteps > 0. */
+ * lbm_ch_adjoint reads.  Any mode; for periodic float32 lattices with a prescribed
+ * velocity and model 1 or 2 the step kernel writes phi^n itself (the phi it sums from
+ * the pulled populations), otherwise a separate launch does before each step; the
+ * populations are those of lbm_ch_step either way.  Errors: LBM_CH_EINVAL for
+ * nsteps < 0 or a NULL or unaligned phi_traj when nsteps > 0. */
 int lbm_ch_record(lbm_ch_ctx* ctx, int64_t nsteps, float* phi_traj, hipStream_t stream);
 
 /* Enqueue the reverse steps n = n_end - 1 down to n_end - nsteps.  phi_traj holds
