@@ -9,6 +9,7 @@ the final extrema.
     python tests/golden/make_golden.py vortex512      # 512^2, one period T = 20000
     python tests/golden/make_golden.py rt256          # 256x1024 Rayleigh-Taylor, 1000 steps
     python tests/golden/make_golden.py rt256_4000     # the same after 4000 steps (0.44 T)
+    python tests/golden/make_golden.py rtpaper25_40000  # At 0.25, Re 400 (Sec. III.E), 40000 steps
     python tests/golden/make_golden.py adjoint256     # 256^2, 2000 steps: target + FD gradients
 
 The adjoint case stores the target field phi_target (the oracle run with the held-out
@@ -33,6 +34,9 @@ CASES = {
     "vortex512": (lambda: workloads.vortex(512, period=20000), 20000, 0),
     "rt256": (lambda: workloads.rayleigh_taylor_case(256, 1024, steps=1000), 1000, 1),
     "rt256_4000": (lambda: workloads.rayleigh_taylor_case(256, 1024, steps=4000), 4000, 1),
+    "rtpaper25_40000": (lambda: workloads.rayleigh_taylor_case(256, 1024, steps=40000,
+                                                               reynolds=400.0, atwood=0.25),
+                        40000, 1),
 }
 
 

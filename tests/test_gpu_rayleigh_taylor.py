@@ -6,7 +6,8 @@ At = 0.5, Re = 3000, W = 4, Pe = 1000, sqrt(gL) = 0.04 (time unit T = sqrt(L/(At
   parity tests: relative L2 <= 1e-4, mass drift <= 1e-6);
 * through t = T the run stays finite with the same mass bound and bounded extrema, and
   the heavy fluid's spike and the light fluid's bubble move down and up;
-* the paper's own parameters (Re = 400, At = 0.1 and 0.25) for the full 40000 steps;
+* the paper's own parameters (Re = 400, At = 0.1 and 0.25) for the full 40000 steps,
+  At = 0.25 also against stored FP64 oracle samples after those 40000 steps;
 * 16-bit population storage (the f populations stay float32) against the float32 run.
 """
 import math
@@ -117,6 +118,33 @@ def test_rayleigh_taylor_paper_parameters_full_length(lbm, atwood):
         assert abs(d["mass"] - m0) / abs0 <= 1e-6
         assert d["max"] < 1.6 and d["min"] > -1.6
     assert spike < spike0 - 50 and bubble > bubble0 + 20
+
+
+def test_rayleigh_taylor_paper_parameters_against_stored_oracle(lbm):
+    """At = 0.25, Re = 400 for the full 40000 steps (4.4 time units, the spike and bubble
+    well developed) against stored FP64 oracle samples: the FP32-vs-FP64 error at the
+    configuration's full length.  Rounding differences of ~1e-7 per step are carried by
+    the instability as it grows, so the gate is looser than the 1e-4 of the short runs;
+    mass is held to the same 1e-6."""
+    path = os.path.join(HERE, "golden", "rtpaper25_oracle_40000.npz")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle samples missing: run tests/golden/make_golden.py")
+    g = np.load(path)
+    steps = int(g["steps"])
+    w = workloads.rayleigh_taylor_case(256, 1024, steps=steps, reynolds=400.0, atwood=0.25)
+    s = lbm.solver_for(w, walls=1)
+    s.step(steps)
+    d = s.diagnostics()
+    phi = s.phi().double().cpu().numpy().ravel()
+    s.close()
+    idx, ref = g["index"], g["phi"]
+    rel = float(np.sqrt(((phi[idx] - ref) ** 2).sum() / (ref ** 2).sum()))
+    drift = abs(d["mass"] - float(g["mass0"])) / float(g["abs_mass0"])
+    print("At 0.25, Re 400, %d steps: sampled rel_l2 %.3e max %.3e drift %.3e extrema "
+          "%.4f/%.4f (oracle %.4f/%.4f)" % (steps, rel, np.abs(phi[idx] - ref).max(), drift,
+                                            d["max"], d["min"], float(g["max"]), float(g["min"])))
+    assert rel <= 1e-2
+    assert drift <= 1e-6
 
 
 @pytest.mark.parametrize("storage,tol", [(1, 2e-2), (2, 0.3)])
