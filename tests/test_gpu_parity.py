@@ -89,6 +89,13 @@ def test_translation_128_model1_and_model2(lbm):
         _compare(lbm, workloads.translation(128, 1000, model=model), 1000)
 
 
+@pytest.mark.parametrize("model", [1, 2])
+def test_translation_128_full_period(lbm, model):
+    """The translation at its full length: one period, 3200 steps, the circle back at its
+    start."""
+    _compare(lbm, workloads.translation(128, 3200, model=model), 3200)
+
+
 def test_vortex_512_1000_steps(lbm):
     _compare(lbm, workloads.vortex(512, period=20000, steps=1000), 1000)
 
