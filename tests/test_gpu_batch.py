@@ -146,6 +146,39 @@ def test_full_batch_against_single_and_oracle(lbm):
         assert err <= 1e-4
 
 
+def test_full_batch_full_length(lbm):
+    """The 64-lattice workload at its full length: 5000 batched steps in one graph
+    launch, bitwise equal to single stepping for every lattice, and against the FP64
+    oracle for one lattice of side 64 and one of side 128 (the larger ones take the
+    oracle minutes at this length)."""
+    steps = 5000
+    ws = workloads.batch_case(steps=steps)
+    sol = _solvers(lbm, ws)
+    b = lbm.Batch(sol)
+    b.step(steps, graph=True)
+    got = _phis(sol)
+    b.close()
+    _close(sol)
+    for i, w in enumerate(ws):
+        s = lbm.solver_for(w)
+        s.step(steps)
+        ph = s.phi().cpu().numpy()
+        s.close()
+        assert np.array_equal(got[i], ph), w.name
+    seen = set()
+    for i, w in enumerate(ws):
+        if w.nx in seen or w.nx not in (64, 128):
+            continue
+        seen.add(w.nx)
+        p = oracle.Params(nx=w.nx, ny=w.ny, **w.phys)
+        o = oracle.State(p, w.phi0, *w.field).run(steps)
+        err = oracle.rel_l2(got[i].astype(np.float64), o.phi)
+        drift = abs(got[i].astype(np.float64).sum() - w.phi0.sum()) / np.abs(w.phi0).sum()
+        print(w.name, "after %d steps: rel L2 vs oracle %.3e, drift %.2e" % (steps, err, drift))
+        assert err <= 1e-4
+        assert drift <= 1e-6
+
+
 def test_batch_autotune_restores_state(lbm):
     ws = _small_case(6, seed=12)
     sol = _solvers(lbm, ws)
