@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(256) k_velocity(int vmode, int nx, int ny, con
                                                   const float* uy, float tf, float* u,
                                                   float* v) {
   const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
-  if (x >= nx) return;
+  if (x >= nx || y >= ny) return;
   const uint32_t k = (uint32_t)y * nx + x;
   if (vmode == VEL_SEP) {
     if (u) u[k] = tf * ax[x] * ay[y];
@@ -202,7 +202,7 @@ __global__ void __launch_bounds__(DIAG_THREADS) k_diag_partial(const Coef c,
   for (int q = 0; q < NDIAG; ++q) sh[q][threadIdx.x] = acc[q];
   __syncthreads();
   for (int s = DIAG_THREADS / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
+    if ((int)threadIdx.x < s) {
 #pragma unroll
       for (int q = 0; q < NDIAG; ++q) {
         const double o = sh[q][threadIdx.x + s];
@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(DIAG_THREADS) k_diag_final(const double* __res
   for (int q = 0; q < NDIAG; ++q) sh[q][threadIdx.x] = acc[q];
   __syncthreads();
   for (int s = DIAG_THREADS / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
+    if ((int)threadIdx.x < s) {
 #pragma unroll
       for (int q = 0; q < NDIAG; ++q) {
         const double o = sh[q][threadIdx.x + s];
