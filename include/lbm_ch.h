@@ -43,12 +43,14 @@
  *
  * Memory and ownership
  * --------------------
- * The library never allocates device memory.  The caller supplies one device
+ * The library never allocates device memory for data: the caller supplies one device
  * workspace of lbm_ch_workspace_bytes() bytes (256-byte aligned) and keeps it,
  * and every device array it passes to lbm_ch_init, alive until lbm_ch_destroy.
  * Device arrays are float32, row-major (index y*nx + x), unless stated.  Host
  * arrays are copied during the call.  The context itself is host memory owned by
- * the library.
+ * the library.  Graph replay (lbm_ch_set_graphs, lbm_ch_batch_step with use_graph)
+ * has the HIP runtime create a capture stream and instantiate graphs, which the
+ * runtime holds until the context or batch is destroyed or the graphs are dropped.
  *
  * Streams and errors
  * ------------------
