@@ -48,9 +48,10 @@
  * and every device array it passes to lbm_ch_init, alive until lbm_ch_destroy.
  * Device arrays are float32, row-major (index y*nx + x), unless stated.  Host
  * arrays are copied during the call.  The context itself is host memory owned by
- * the library.  Graph replay (lbm_ch_set_graphs, lbm_ch_batch_step with use_graph)
- * has the HIP runtime create a capture stream and instantiate graphs, which the
- * runtime holds until the context or batch is destroyed or the graphs are dropped.
+ * the library.  A batch (lbm_ch_batch_create) and a context's first graph capture
+ * (lbm_ch_set_graphs) create a capture stream, and graph replay instantiates graphs;
+ * the HIP runtime holds these until the batch or context is destroyed (or, for a
+ * context, its graphs are dropped).
  *
  * Streams and errors
  * ------------------
