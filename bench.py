@@ -320,7 +320,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--cpu-steps", type=int, default=100,
+    ap.add_argument("--cpu-steps", type=int, default=160,
                     help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
