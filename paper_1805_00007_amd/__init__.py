@@ -362,7 +362,13 @@ class Batch:
     def _s(self):
         return ctypes.c_void_p(self.stream.cuda_stream)
 
+    def _members_open(self):
+        # the library keeps the contexts' addresses: a closed member must not be reached
+        if any(getattr(s, "ctx", None) is None for s in self.solvers):
+            raise LbmChError(ESTATE, "Batch: a member Solver was closed before the batch")
+
     def step(self, n=1, graph=False):
+        self._members_open()
         _check(lib().lbm_ch_batch_step(self.b, int(n), 1 if graph else 0, self._s()),
                "lbm_ch_batch_step")
         return self
@@ -390,6 +396,7 @@ class Batch:
     def autotune(self, trial_steps=5):
         """Time every schedule and tile policy; returns ((tx, ty), us per step) and leaves
         the fastest set (see ``persistent``)."""
+        self._members_open()
         t = self.torch
         n = lib().lbm_ch_batch_state_bytes(self.b)
         backup = t.empty(n, dtype=t.uint8, device=self.device)

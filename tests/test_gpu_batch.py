@@ -179,6 +179,20 @@ def test_full_batch_full_length(lbm):
         assert drift <= 1e-6
 
 
+def test_closed_member_is_refused(lbm):
+    """Closing a member Solver before its batch is refused from Python (the library
+    keeps the contexts' addresses) instead of reaching a destroyed context."""
+    ws = _small_case(3, seed=13)
+    sol = _solvers(lbm, ws)
+    b = lbm.Batch(sol)
+    b.step(2)
+    sol[1].close()
+    with pytest.raises(lbm.LbmChError):
+        b.step(1)
+    b.close()
+    _close(sol)
+
+
 def test_batch_autotune_restores_state(lbm):
     ws = _small_case(6, seed=12)
     sol = _solvers(lbm, ws)
