@@ -281,14 +281,22 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
   // branch and fetches nothing extra, and its stage 1 is skipped (a scalar branch), so
   // the block does not wait for it.
   const int last_needed = y0 + (rows + 1) * d;
+  // On tall tiles (bandwidth-bound marches) a wave raises its issue priority while it
+  // puts its row's pull in flight, so waves about to load go before waves in their
+  // compute stages (2048^2: 0.8 % faster with float32, ~6 % with 16-bit storage).  Short
+  // tiles are latency-bound chains, where it costs a few per cent, and keep priority 0.
+  const bool prio = a.ty >= 8;
 #pragma unroll 1
   for (int k = 0; k < rows; ++k) {
     const int y = y0 + k * d;
     const int ynext = k + 1 < rows ? y + 3 * d : last_needed;
     __builtin_amdgcn_sched_barrier(0);
+    if (prio) __builtin_amdgcn_s_setprio(2);
     if (hwave) issue(ynext, hvc, hvm, hvp, H0, false);
     __builtin_amdgcn_sched_barrier(0);
     issue(ynext, vc, vm, vp, N);
+    __builtin_amdgcn_sched_barrier(0);
+    if (prio) __builtin_amdgcn_s_setprio(0);
     __builtin_amdgcn_sched_barrier(0);
     __syncthreads();
     stage2(y + d, j);
