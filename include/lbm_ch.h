@@ -103,7 +103,8 @@ enum {
  * populations of the Navier-Stokes coupling are always float32. */
 
 typedef struct {
-  int32_t nx, ny;         /* lattice nodes; 4 <= nx, ny and 9*nx*ny < 2^31          */
+  int32_t nx, ny;         /* lattice nodes; 4 <= nx, ny and 36*nx*ny < 2^31 (one
+                             buffer of nine float32 planes stays under 2 GiB)     */
   int32_t walls;          /* 0: periodic in y; 1: no-slip walls (see above)         */
   int32_t model;          /* 1: F = F1 (Model-I); 2: F = F1 + F2 of Eq. mark3 (Model-II);
                              3: F = F1 + F2 of Eq. F2-1 (see below; LBM_CH_STORE_F32) */
@@ -140,7 +141,7 @@ size_t lbm_ch_workspace_bytes(const lbm_ch_params* p);
  * term (and f_i = f_i^eq(p = 0, rho(phi0), u0) with NS).  phi0 is a device array of
  * nx*ny floats; it is read during the call's device work only.  *out receives the
  * context.  Errors: LBM_CH_EINVAL for tau_g <= 1/2, tau_f <= 1/2 (NS), sizes out of
- * range, phi_a == phi_b, rho_a or rho_b <= 0, model not 1 or 2, a NULL or unaligned
+ * range, phi_a == phi_b, rho_a or rho_b <= 0, model not 1, 2 or 3, a NULL or unaligned
  * (4-byte) array the mode needs, a workspace smaller than lbm_ch_workspace_bytes or
  * not 256-byte aligned, or a storage mode outside LBM_CH_STORE_*; LBM_CH_EUNSUPPORTED
  * for model 3 with 16-bit storage. */
