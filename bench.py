@@ -343,7 +343,7 @@ def main():
                           round(2 * src.numel() * 4 / (ms * 1e-3) / 1e9, 1)}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only; the multi-GPU domain "
+        print("bench.py: measures one GPU only; the multi-GPU domain "
               "decomposition is a design, not a runnable path (--gpus must be 1)",
               file=sys.stderr)
         sys.exit(2)
