@@ -132,3 +132,22 @@ def test_model3_workspace_holds_the_history():
     a = L.lbm_ch_workspace_bytes(ctypes.byref(lbm.make_params(256, 256, model=2)))
     b = L.lbm_ch_workspace_bytes(ctypes.byref(lbm.make_params(256, 256, model=3)))
     assert b - a == 2 * 4 * 256 * 256
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """With no built library every call into the package raises: there is no fallback."""
+    import subprocess
+    import sys
+    code = ("import paper_1805_00007_amd as lbm\n"
+            "try:\n"
+            "    lbm.lib()\n"
+            "except RuntimeError as e:\n"
+            "    print('raised:', e)\n"
+            "else:\n"
+            "    raise SystemExit('loaded')\n")
+    env = dict(os.environ, LBM_CH_LIB=str(tmp_path / "absent.so"))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], env=env, cwd=root, capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert "raised: liblbm_ch.so is not built" in r.stdout
