@@ -136,7 +136,9 @@ def storage_variant(lbm, torch, storage, steps):
 
 def adjoint_leg(lbm, torch, reps=3):
     """One forward plus backward pass of the 256^2, 2000-step interface-matching problem
-    (16 stream-function coefficients, sqrt(N) checkpointing), against the plain forward
+    (16 stream-function coefficients, sqrt(N) checkpointing; each segment's recomputation
+    beside the reverse steps of the next on a second stream, and for comparison one after
+    the other, and with the whole trajectory stored), against the plain forward
     run of the same workload (one call of N plain launches; also its segments replayed
     from captured hipGraphs), and its gradients against stored FP64 central differences.
     Both run on the tile shape the autotuner picks for this lattice (tuned once, not
@@ -180,14 +182,14 @@ def adjoint_leg(lbm, torch, reps=3):
         s.close()
         return dt
 
-    def fwd_bwd(store=False):
+    def fwd_bwd(store=False, overlap=True):
         phi0 = torch.tensor(case.phi0, dtype=torch.float32, device=dev, requires_grad=True)
         theta = torch.tensor(case.theta, dtype=torch.float32, device=dev, requires_grad=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         uv = case.scale * torch.tensordot(theta, basis, dims=1)
         phi = evolve(phi0, uv[0], uv[1], steps, tiles=tiles, store_trajectory=store,
-                     **case.phys)
+                     overlap=overlap, **case.phys)
         loss = ((phi - target) ** 2).sum()
         loss.backward()
         torch.cuda.synchronize()
@@ -206,6 +208,11 @@ def adjoint_leg(lbm, torch, reps=3):
     stored = [fwd_bwd(True) for _ in range(reps)]
     t_store = min(r[0] for r in stored)
     same = bool(np.array_equal(stored[0][2], runs[0][2]) and np.array_equal(stored[0][3], runs[0][3]))
+    fwd_bwd(overlap=False)
+    serial = [fwd_bwd(overlap=False) for _ in range(reps)]
+    t_serial = min(r[0] for r in serial)
+    same_serial = bool(np.array_equal(serial[0][2], runs[0][2])
+                       and np.array_equal(serial[0][3], runs[0][3]))
     _, loss, gt, gp = runs[0]
     ref_t, ref_p = g["grad_theta"], g["grad_phi0"]
     return {"workload": "adjoint256: 256^2, %d steps, 16 stream-function coefficients" % steps,
@@ -214,6 +221,8 @@ def adjoint_leg(lbm, torch, reps=3):
             "ratio_to_plain_forward": round(t_adj / t_plain, 2),
             "forward_ms_plain_graphs": round(t_plain_g * 1e3, 2),
             "ratio_to_plain_forward_graphs": round(t_adj / t_plain_g, 2),
+            "adjoint_ms_serial_backward": round(t_serial * 1e3, 2),
+            "serial_backward_grads_bitwise_equal": same_serial,
             "adjoint_ms_stored_trajectory": round(t_store * 1e3, 2),
             "stored_trajectory_MiB": round(steps * case.n * case.n * 4 / 2 ** 20, 1),
             "stored_trajectory_grads_bitwise_equal": same,

@@ -308,10 +308,13 @@ class Solver:
                "lbm_ch_record")
         return self
 
-    def adjoint(self, n_end, nsteps, phi_traj, lam, grad_u=None, grad_v=None, scratch=None):
+    def adjoint(self, n_end, nsteps, phi_traj, lam, grad_u=None, grad_v=None, scratch=None,
+                stream=None):
         """Reverse steps n_end-1 .. n_end-nsteps of the tau_g = 1 map: ``lam`` holds
         dL/dphi^{n_end} and becomes dL/dphi^{n_end-nsteps}; ``grad_u``/``grad_v``
-        accumulate the derivative with respect to the base velocity field."""
+        accumulate the derivative with respect to the base velocity field.  ``stream``
+        (default: the solver's) may differ from the solver's stream: the reverse steps
+        read none of the state that steps and records advance."""
         t = self.torch
         for a in (phi_traj, lam, grad_u, grad_v):
             assert a is None or (a.is_contiguous() and a.dtype == t.float32)
@@ -321,7 +324,9 @@ class Solver:
             scratch = t.empty(nbytes, dtype=t.uint8, device=self.device)
         _check(lib().lbm_ch_adjoint(self.ctx, int(n_end), int(nsteps), _ptr(phi_traj), _ptr(lam),
                                     _ptr(grad_u), _ptr(grad_v), _ptr(scratch),
-                                    scratch.numel() * scratch.element_size(), self._s()),
+                                    scratch.numel() * scratch.element_size(),
+                                    self._s() if stream is None
+                                    else ctypes.c_void_p(stream.cuda_stream)),
                "lbm_ch_adjoint")
         return lam
 

@@ -10,9 +10,12 @@ Forward: the solver runs N steps on the GPU and keeps its state every S = ceil(s
 steps (``lbm_ch_save_state``); with ``graphs=True`` the repeated segment launches are
 replayed as captured hipGraphs.  Backward: for each segment from the last, the state is
 reloaded, the segment re-run with ``lbm_ch_record`` (phi^n of every step), and
-``lbm_ch_adjoint`` carries dL/dphi back over it while accumulating dL/d(U, V).  Memory:
-ceil(N/S) states plus S phi fields.  All derivative arithmetic runs in the library's
-kernels; this module only orders the calls.
+``lbm_ch_adjoint`` carries dL/dphi back over it while accumulating dL/d(U, V).  The
+reverse steps read none of the solver state, so the re-run of one segment (on the
+solver's stream) overlaps the reverse steps of the segment after it (on a second
+stream), with two trajectory buffers taken in turn and events ordering each buffer's
+writer after its previous reader.  Memory: ceil(N/S) states plus 2 S phi fields.  All
+derivative arithmetic runs in the library's kernels; this module only orders the calls.
 """
 from __future__ import annotations
 
@@ -25,7 +28,7 @@ from . import Solver
 
 class _Evolve(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, phi0, U, V, steps, segment, tf, params, tune, graphs, store):
+    def forward(ctx, phi0, U, V, steps, segment, tf, params, tune, graphs, store, overlap):
         ny, nx = phi0.shape
         s = Solver(nx, ny, phi0.detach(), field=(U.detach(), V.detach()), tf=tf,
                    device=phi0.device, **params)
@@ -45,6 +48,7 @@ class _Evolve(torch.autograd.Function):
             phi = s.phi()
             torch.cuda.current_stream(phi0.device).wait_stream(s.stream)
             ctx.solver, ctx.ckpts, ctx.seg, ctx.traj = s, [], steps, traj
+            ctx.overlap = False
             return phi
         seg = int(segment) if segment else max(1, math.isqrt(max(steps - 1, 0)) + 1)
         ckpts = []
@@ -57,7 +61,7 @@ class _Evolve(torch.autograd.Function):
             n += k
         phi = s.phi()
         torch.cuda.current_stream(phi0.device).wait_stream(s.stream)
-        ctx.solver, ctx.ckpts, ctx.seg = s, ckpts, seg
+        ctx.solver, ctx.ckpts, ctx.seg, ctx.overlap = s, ckpts, seg, overlap
         return phi
 
     @staticmethod
@@ -74,18 +78,37 @@ class _Evolve(torch.autograd.Function):
             if ctx.traj is not None:
                 if ctx.seg:
                     s.adjoint(ctx.seg, ctx.seg, ctx.traj, lam, gu, gv, scratch)
-            else:
+            elif not ctx.overlap:
                 traj = torch.empty((ctx.seg, s.ny, s.nx), dtype=torch.float32, device=dev)
                 for n0, k, buf in reversed(ctx.ckpts):
                     s.load_state(buf, n0)
                     s.record(k, traj)
                     s.adjoint(n0 + k, k, traj, lam, gu, gv, scratch)
+            else:
+                rs = torch.cuda.Stream(device=dev)
+                rs.wait_stream(s.stream)  # lam, gu, gv and the scratch are initialised
+                trajs = [torch.empty((ctx.seg, s.ny, s.nx), dtype=torch.float32, device=dev)
+                         for _ in range(2)]
+                read = [None, None]  # event after the last reverse steps that read buffer b
+                for i, (n0, k, buf) in enumerate(reversed(ctx.ckpts)):
+                    b = i & 1
+                    if read[b] is not None:
+                        s.stream.wait_event(read[b])
+                    s.load_state(buf, n0)
+                    s.record(k, trajs[b])
+                    written = torch.cuda.Event()
+                    written.record(s.stream)
+                    rs.wait_event(written)
+                    s.adjoint(n0 + k, k, trajs[b], lam, gu, gv, scratch, stream=rs)
+                    read[b] = torch.cuda.Event()
+                    read[b].record(rs)
+                s.stream.wait_stream(rs)
         torch.cuda.current_stream(dev).wait_stream(s.stream)
-        return lam, gu, gv, None, None, None, None, None, None, None
+        return lam, gu, gv, None, None, None, None, None, None, None, None
 
 
 def evolve(phi0, U, V, steps, *, tf=None, segment=None, autotune=0, tiles=None, graphs=False,
-           store_trajectory=False, **params):
+           store_trajectory=False, overlap=True, **params):
     """phi after ``steps`` steps from ``phi0`` (ny, nx) in the velocity field tf[n] (U, V),
     differentiable in phi0, U and V.  ``params`` are those of ``lbm_ch_params``; the
     derivative needs tau_g = 1, periodic boundaries and a prescribed velocity.
@@ -96,9 +119,11 @@ def evolve(phi0, U, V, steps, *, tf=None, segment=None, autotune=0, tiles=None, 
     results; at 256^2 the captures a pass needs cost about what the replays save).
     ``store_trajectory``: keep phi of every step (steps * nx * ny floats of device memory)
     instead of sqrt(N) checkpoints, so the backward pass recomputes nothing (same
-    gradients)."""
+    gradients).  ``overlap``: with checkpoints, run each segment's recomputation beside
+    the reverse steps of the segment after it on a second stream (same gradients, bitwise;
+    one more segment of phi fields)."""
     if float(params.get("tau_g", 1.0)) != 1.0 or params.get("walls", 0):
         raise ValueError("the discrete adjoint covers tau_g = 1 on a periodic lattice")
     tune = tuple(int(t) for t in tiles) if tiles is not None else int(autotune)
     return _Evolve.apply(phi0, U, V, int(steps), segment, tf, dict(params), tune, bool(graphs),
-                         bool(store_trajectory))
+                         bool(store_trajectory), bool(overlap))

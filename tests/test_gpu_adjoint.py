@@ -163,13 +163,17 @@ def test_adjoint_separable_time_dependent_velocity(lbm):
 
 def test_checkpoint_segments_agree(lbm):
     """sqrt(N) checkpointing recomputes the same trajectory: gradients with segment
-    lengths 1, 7, sqrt(N) and N, with the whole trajectory stored instead of
-    checkpoints, and with other or autotuned tile shapes, agree bitwise."""
+    lengths 1, 7, sqrt(N) and N, with each segment's recomputation overlapping the
+    reverse steps of the next (the default) or not, with graph replay, with the whole
+    trajectory stored instead of checkpoints, and with other or autotuned tile shapes,
+    agree bitwise."""
     n, steps = 32, 50
     case = workloads.adjoint_case(n, steps)
     target = np.zeros((n, n))
     ref = None
-    for seg, kw in ((None, {}), (1, {}), (7, {}), (steps, {}), (None, dict(store_trajectory=True)),
+    for seg, kw in ((None, {}), (1, {}), (7, {}), (steps, {}), (None, dict(overlap=False)),
+                    (1, dict(overlap=False)), (7, dict(graphs=True)),
+                    (None, dict(store_trajectory=True)),
                     (None, dict(tiles=(64, 4))), (None, dict(autotune=2))):
         _, gt, gp = _gpu_grads(lbm, case, target, steps, segment=seg, **kw)
         if ref is None:
