@@ -250,7 +250,10 @@ int lbm_ch_record(lbm_ch_ctx* ctx, int64_t nsteps, float* phi_traj, hipStream_t 
  * with LBM_CH_VEL_FIELD; the products ax[x] ay[y] and bx[x] by[y] with
  * LBM_CH_VEL_SEPARABLE).  scratch: at least lbm_ch_adjoint_scratch_bytes device bytes,
  * 4-byte aligned, contents undefined afterwards.  The context's state and step counter
- * are not changed.  Errors: LBM_CH_EUNSUPPORTED unless tau_g == 1, walls == 0, model
+ * are not changed, and its device work reads no population state, only the velocity
+ * inputs bound at lbm_ch_init: it may run on another stream at the same time as steps,
+ * records or state loads of the same context (the calls themselves still come from one
+ * host thread).  Errors: LBM_CH_EUNSUPPORTED unless tau_g == 1, walls == 0, model
  * is 1 or 2 and the velocity is prescribed; LBM_CH_EINVAL for nsteps < 0, n_end < nsteps, NULL or
  * unaligned arrays, or too little scratch. */
 int lbm_ch_adjoint(lbm_ch_ctx* ctx, int64_t n_end, int64_t nsteps, const float* phi_traj,

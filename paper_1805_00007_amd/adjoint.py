@@ -11,11 +11,14 @@ steps (``lbm_ch_save_state``); with ``graphs=True`` the repeated segment launche
 replayed as captured hipGraphs.  Backward: for each segment from the last, the state is
 reloaded, the segment re-run with ``lbm_ch_record`` (phi^n of every step), and
 ``lbm_ch_adjoint`` carries dL/dphi back over it while accumulating dL/d(U, V).  The
-reverse steps read none of the solver state, so the re-run of one segment (on the
-solver's stream) overlaps the reverse steps of the segment after it (on a second
-stream), with two trajectory buffers taken in turn and events ordering each buffer's
-writer after its previous reader.  Memory: ceil(N/S) states plus 2 S phi fields.  All
-derivative arithmetic runs in the library's kernels; this module only orders the calls.
+reverse steps read none of the solver state, and the re-runs of different segments are
+independent, so by default two solvers (the forward one and a second one with the same
+parameters, each on its own stream) re-run alternate segments while a third stream runs
+the reverse steps, which then form the critical path; three trajectory buffers are
+taken in turn, and events order each buffer's writer after its previous reader and each
+segment's reverse steps after its re-run.  Memory: ceil(N/S) states, 3 S phi fields and
+the second solver's state.  All derivative arithmetic runs in the library's kernels;
+this module only orders the calls.
 """
 from __future__ import annotations
 
@@ -62,6 +65,7 @@ class _Evolve(torch.autograd.Function):
         phi = s.phi()
         torch.cuda.current_stream(phi0.device).wait_stream(s.stream)
         ctx.solver, ctx.ckpts, ctx.seg, ctx.overlap = s, ckpts, seg, overlap
+        ctx.remake = (tf, params, graphs)
         return phi
 
     @staticmethod
@@ -87,22 +91,36 @@ class _Evolve(torch.autograd.Function):
             else:
                 rs = torch.cuda.Stream(device=dev)
                 rs.wait_stream(s.stream)  # lam, gu, gv and the scratch are initialised
+                solvers = [s]
+                if len(ctx.ckpts) > 1:
+                    tf, params, graphs = ctx.remake
+                    s2 = Solver(s.nx, s.ny, torch.zeros((s.ny, s.nx), device=dev),
+                                field=tuple(s._keep[:2]), tf=tf, device=dev,
+                                stream=torch.cuda.Stream(device=dev), **params)
+                    s2.set_graphs(graphs).set_tiles(*s.tiles)
+                    s2.stream.wait_stream(s.stream)
+                    solvers.append(s2)
+                nb = len(solvers) + 1
                 trajs = [torch.empty((ctx.seg, s.ny, s.nx), dtype=torch.float32, device=dev)
-                         for _ in range(2)]
-                read = [None, None]  # event after the last reverse steps that read buffer b
+                         for _ in range(nb)]
+                read = [None] * nb  # event after the last reverse steps that read buffer b
                 for i, (n0, k, buf) in enumerate(reversed(ctx.ckpts)):
-                    b = i & 1
+                    b = i % nb
+                    sv = solvers[i % len(solvers)]
                     if read[b] is not None:
-                        s.stream.wait_event(read[b])
-                    s.load_state(buf, n0)
-                    s.record(k, trajs[b])
+                        sv.stream.wait_event(read[b])
+                    sv.load_state(buf, n0)
+                    sv.record(k, trajs[b])
                     written = torch.cuda.Event()
-                    written.record(s.stream)
+                    written.record(sv.stream)
                     rs.wait_event(written)
                     s.adjoint(n0 + k, k, trajs[b], lam, gu, gv, scratch, stream=rs)
                     read[b] = torch.cuda.Event()
                     read[b].record(rs)
                 s.stream.wait_stream(rs)
+                for sv in solvers[1:]:
+                    s.stream.wait_stream(sv.stream)
+                    sv.close()
         torch.cuda.current_stream(dev).wait_stream(s.stream)
         return lam, gu, gv, None, None, None, None, None, None, None, None
 
@@ -119,9 +137,10 @@ def evolve(phi0, U, V, steps, *, tf=None, segment=None, autotune=0, tiles=None, 
     results; at 256^2 the captures a pass needs cost about what the replays save).
     ``store_trajectory``: keep phi of every step (steps * nx * ny floats of device memory)
     instead of sqrt(N) checkpoints, so the backward pass recomputes nothing (same
-    gradients).  ``overlap``: with checkpoints, run each segment's recomputation beside
-    the reverse steps of the segment after it on a second stream (same gradients, bitwise;
-    one more segment of phi fields)."""
+    gradients).  ``overlap``: with checkpoints, re-run the segments on two solvers beside
+    the reverse steps on a third stream (same gradients, bitwise; a second solver's
+    state and two more segments of phi fields); ``False`` runs them one after the other
+    on the forward solver's stream."""
     if float(params.get("tau_g", 1.0)) != 1.0 or params.get("walls", 0):
         raise ValueError("the discrete adjoint covers tau_g = 1 on a periodic lattice")
     tune = tuple(int(t) for t in tiles) if tiles is not None else int(autotune)

@@ -163,8 +163,8 @@ def test_adjoint_separable_time_dependent_velocity(lbm):
 
 def test_checkpoint_segments_agree(lbm):
     """sqrt(N) checkpointing recomputes the same trajectory: gradients with segment
-    lengths 1, 7, sqrt(N) and N, with each segment's recomputation overlapping the
-    reverse steps of the next (the default) or not, with graph replay, with the whole
+    lengths 1, 7, sqrt(N) and N, with the segments re-run on two solvers beside the
+    reverse steps (the default) or all in order on one stream, with graph replay, with the whole
     trajectory stored instead of checkpoints, and with other or autotuned tile shapes,
     agree bitwise."""
     n, steps = 32, 50
