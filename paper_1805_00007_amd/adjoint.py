@@ -89,38 +89,46 @@ class _Evolve(torch.autograd.Function):
                     s.record(k, traj)
                     s.adjoint(n0 + k, k, traj, lam, gu, gv, scratch)
             else:
-                rs = torch.cuda.Stream(device=dev)
-                rs.wait_stream(s.stream)  # lam, gu, gv and the scratch are initialised
+                # three streams of their own (consecutive pool streams), none of them the
+                # stream the caller works on
+                home = s.stream
+                sa, sb, rs = (torch.cuda.Stream(device=dev) for _ in range(3))
+                for st in (sa, sb, rs):
+                    st.wait_stream(home)  # lam, gu, gv and the scratch are initialised
+                s.stream = sa
                 solvers = [s]
                 if len(ctx.ckpts) > 1:
                     tf, params, graphs = ctx.remake
-                    s2 = Solver(s.nx, s.ny, torch.zeros((s.ny, s.nx), device=dev),
-                                field=tuple(s._keep[:2]), tf=tf, device=dev,
-                                stream=torch.cuda.Stream(device=dev), **params)
+                    with torch.cuda.stream(sb):  # its memory belongs to its own stream
+                        z = torch.zeros((s.ny, s.nx), dtype=torch.float32, device=dev)
+                        s2 = Solver(s.nx, s.ny, z, field=tuple(s._keep[:2]), tf=tf,
+                                    device=dev, stream=sb, **params)
                     s2.set_graphs(graphs).set_tiles(*s.tiles)
-                    s2.stream.wait_stream(s.stream)
                     solvers.append(s2)
                 nb = len(solvers) + 1
                 trajs = [torch.empty((ctx.seg, s.ny, s.nx), dtype=torch.float32, device=dev)
                          for _ in range(nb)]
                 read = [None] * nb  # event after the last reverse steps that read buffer b
-                for i, (n0, k, buf) in enumerate(reversed(ctx.ckpts)):
-                    b = i % nb
-                    sv = solvers[i % len(solvers)]
-                    if read[b] is not None:
-                        sv.stream.wait_event(read[b])
-                    sv.load_state(buf, n0)
-                    sv.record(k, trajs[b])
-                    written = torch.cuda.Event()
-                    written.record(sv.stream)
-                    rs.wait_event(written)
-                    s.adjoint(n0 + k, k, trajs[b], lam, gu, gv, scratch, stream=rs)
-                    read[b] = torch.cuda.Event()
-                    read[b].record(rs)
-                s.stream.wait_stream(rs)
-                for sv in solvers[1:]:
-                    s.stream.wait_stream(sv.stream)
-                    sv.close()
+                try:
+                    for i, (n0, k, buf) in enumerate(reversed(ctx.ckpts)):
+                        b = i % nb
+                        sv = solvers[i % len(solvers)]
+                        if read[b] is not None:
+                            sv.stream.wait_event(read[b])
+                        sv.load_state(buf, n0)
+                        sv.record(k, trajs[b])
+                        written = torch.cuda.Event()
+                        written.record(sv.stream)
+                        rs.wait_event(written)
+                        s.adjoint(n0 + k, k, trajs[b], lam, gu, gv, scratch, stream=rs)
+                        read[b] = torch.cuda.Event()
+                        read[b].record(rs)
+                finally:
+                    for st in (sa, sb, rs):
+                        home.wait_stream(st)
+                    s.stream = home
+                    for sv in solvers[1:]:
+                        sv.close()
         torch.cuda.current_stream(dev).wait_stream(s.stream)
         return lam, gu, gv, None, None, None, None, None, None, None, None
 
