@@ -303,6 +303,10 @@ __global__ void __launch_bounds__(ATW * ATH) k_adjoint(const AdjArgs a) {
   __shared__ float sp[P2H][P2W];
   __shared__ float slfx[P2H][P2W], slfy[P2H][P2W], swfx[P2H][P2W], swfy[P2H][P2W];
   __shared__ float smu[Q1H][Q1W], slmu[Q1H][Q1W], sld[Q1H][Q1W];
+  // When recording steps of other segments run beside the reverse steps (on other
+  // streams), the chain of reverse steps is what the backward pass waits for: its
+  // waves take issue priority over theirs (adjoint256: about 5 % faster).
+  __builtin_amdgcn_s_setprio(3);
   const Coef& c = a.c;
   const int nx = a.nx, ny = a.ny;
   const int t = threadIdx.x;
