@@ -163,15 +163,16 @@ def test_adjoint_separable_time_dependent_velocity(lbm):
 
 def test_checkpoint_segments_agree(lbm):
     """sqrt(N) checkpointing recomputes the same trajectory: gradients with segment
-    lengths 1, 7, sqrt(N) and N, with the segments re-run on two solvers beside the
-    reverse steps (the default) or all in order on one stream, with graph replay, with the whole
-    trajectory stored instead of checkpoints, and with other or autotuned tile shapes,
-    agree bitwise."""
+    lengths 1, 7, 17, 25 (three and two segments), sqrt(N) and N, with the segments
+    re-run on two solvers beside the reverse steps (the default) or all in order on one
+    stream, with graph replay, with the whole trajectory stored instead of checkpoints,
+    and with other or autotuned tile shapes, agree bitwise."""
     n, steps = 32, 50
     case = workloads.adjoint_case(n, steps)
     target = np.zeros((n, n))
     ref = None
-    for seg, kw in ((None, {}), (1, {}), (7, {}), (steps, {}), (None, dict(overlap=False)),
+    for seg, kw in ((None, {}), (1, {}), (7, {}), (17, {}), (25, {}), (steps, {}),
+                    (None, dict(overlap=False)),
                     (1, dict(overlap=False)), (7, dict(graphs=True)),
                     (None, dict(store_trajectory=True)),
                     (None, dict(tiles=(64, 4))), (None, dict(autotune=2))):
