@@ -185,11 +185,13 @@ int lbm_ch_save_state(lbm_ch_ctx* ctx, void* dst, size_t bytes, hipStream_t stre
 int lbm_ch_load_state(lbm_ch_ctx* ctx, const void* src, size_t bytes, int64_t step,
                       hipStream_t stream);
 
-/* Tile shape of the step kernels: tx columns (one lane each; 64, 128 or 256) by ty >= 1
- * rows per thread block (ty is clipped to ny).  The default is chosen at init from the
- * lattice size and storage (the widest, then tallest, shape with ty from 32 down to 1
- * that gives at least 512 blocks with float32 storage, 1024 with 16-bit; 64 x 1 if none
- * does); it changes speed only, never results.  Errors: LBM_CH_EINVAL for other shapes. */
+/* Tile shape of the step kernels: tx columns (one lane each; 64, 128, 256 or 512) by
+ * ty >= 1 rows per thread block (ty is clipped to ny).  The default is chosen at init from
+ * the lattice size and storage (the widest, then tallest, shape with ty from 32 down to 1
+ * that gives at least 512 blocks with float32 storage, 1024 with 16-bit; tx = 512 only
+ * with float32 storage and at least 1024 blocks; 64 x 1 if none does); it changes speed
+ * only, never results.  Errors:
+ * LBM_CH_EINVAL for other shapes. */
 int lbm_ch_set_tiles(lbm_ch_ctx* ctx, int32_t tx, int32_t ty);
 int lbm_ch_get_tiles(const lbm_ch_ctx* ctx, int32_t* tx, int32_t* ty);
 
@@ -208,7 +210,7 @@ int lbm_ch_get_tiles(const lbm_ch_ctx* ctx, int32_t* tx, int32_t* ty);
 int lbm_ch_set_graphs(lbm_ch_ctx* ctx, int32_t enable);
 
 /* Autotuner: time trial_steps >= 1 steps (after one untimed step) for each tile shape
- * tx in {64, 128, 256} (skipping widths with more than half the lanes idle) and ty in
+ * tx in {64, 128, 256, 512} (skipping widths with more than half the lanes idle) and ty in
  * {1, 2, 4, 8, 16, 32}, keep the fastest, and restore the state and step counter from
  * `backup`, a caller device buffer of exactly lbm_ch_state_bytes(ctx) bytes.
  * Synchronises `stream`.  *best_us (may be NULL) receives the chosen shape's time per

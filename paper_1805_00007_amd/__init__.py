@@ -16,8 +16,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# LBM_CH_LIB names another build of the same library (tile and tuning experiments).
-LIB_PATH = os.environ.get("LBM_CH_LIB") or os.path.join(HERE, "liblbm_ch.so")
+LIB_PATH = os.path.join(HERE, "liblbm_ch.so")
 
 # Status codes and modes (include/lbm_ch.h).
 OK, EINVAL, EUNSUPPORTED, EHIP, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5

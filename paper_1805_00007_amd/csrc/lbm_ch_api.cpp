@@ -29,18 +29,21 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  uint32_t plane;  // nodes per population plane
-  size_t g_state;  // bytes of the g populations (storage mode), f is 9 float planes
+  uint32_t pitch;  // values per population row: nx rounded up to 32 (rows start 128-B aligned)
+  size_t g_state;  // bytes of the g populations (storage mode)
+  size_t f_state;  // bytes of the f populations (nine float32 populations per node)
   size_t g_bytes;  // one g population buffer, 256-byte aligned
   size_t f_bytes;  // one f population buffer, 256-byte aligned
   size_t off_ga, off_gb, off_fa, off_fb, off_u, off_v, off_p, off_phi, off_ztab, off_part,
       off_diag, off_xh, total;
 };
 
+uint32_t pitch_of(int nx) { return (uint32_t)((nx + 31) / 32 * 32); }
+
 bool valid_params(const lbm_ch_params* p) {
   if (!p) return false;
   if (p->nx < 4 || p->ny < 4) return false;
-  if ((double)p->nx * (double)p->ny * 9.0 * 4.0 >= 2147483648.0) return false;
+  if ((double)pitch_of(p->nx) * (double)p->ny * 9.0 * 4.0 >= 2147483648.0) return false;
   if (p->walls != 0 && p->walls != 1) return false;
   if (p->model < 1 || p->model > 3) return false;
   if (p->velocity_mode < LBM_CH_VEL_NONE || p->velocity_mode > LBM_CH_VEL_NS) return false;
@@ -60,10 +63,11 @@ bool valid_params(const lbm_ch_params* p) {
 Layout layout_of(const lbm_ch_params* p) {
   Layout L{};
   const size_t nodes = (size_t)p->nx * p->ny;
-  L.plane = (uint32_t)((nodes + 63) / 64 * 64);
-  L.g_state = population_bytes(p->storage, L.plane);
+  L.pitch = pitch_of(p->nx);
+  L.g_state = population_bytes(p->storage, L.pitch, (uint32_t)p->ny);
+  L.f_state = population_bytes(0, L.pitch, (uint32_t)p->ny);
   L.g_bytes = align_up(L.g_state);
-  L.f_bytes = align_up((size_t)9 * L.plane * sizeof(float));
+  L.f_bytes = align_up(L.f_state);
   const bool ns = p->velocity_mode == LBM_CH_VEL_NS;
   const size_t field = align_up(nodes * sizeof(float));
   size_t o = 0;
@@ -126,6 +130,9 @@ static constexpr uint32_t CTX_MAGIC = 0x4c424d43u;
 
 static bool live(const lbm_ch_ctx* c) { return c && c->magic == CTX_MAGIC; }
 
+// tau_g = 1 exactly: the collision keeps none of the pulled populations (omega = 1).
+static bool tau_one(const lbm_ch_ctx* c) { return c->p.tau_g == 1.0; }
+
 static float time_factor(const lbm_ch_ctx* c, int64_t n) {
   if (c->tf.empty()) return 1.0f;
   if (n < (int64_t)c->tf.size()) return (float)c->tf[(size_t)n];
@@ -133,7 +140,9 @@ static float time_factor(const lbm_ch_ctx* c, int64_t n) {
 }
 
 // Tile shape: TX columns per block (one lane per column), TY rows per block.
-static bool valid_tile(int tx, int ty) { return (tx == 64 || tx == 128 || tx == 256) && ty >= 1; }
+static bool valid_tile(int tx, int ty) {
+  return (tx == 64 || tx == 128 || tx == 256 || tx == 512) && ty >= 1;
+}
 
 static void apply_tiles(lbm_ch_ctx* c, int tx, int ty) {
   drop_graphs(c);  // the launch shape is part of every captured sequence
@@ -150,19 +159,23 @@ static void apply_tiles(lbm_ch_ctx* c, int tx, int ty) {
 // Default: the widest tile (fewest halo columns), then the tallest (fewest halo rows
 // per row; heights 32 down to 1), that still gives at least 2 workgroups per CU on 256
 // CUs (float32), or 4 with 16-bit storage, whose extra decode work per byte needs more
-// waves in flight to cover memory latency.  Small lattices thus get short row chunks
-// (each block's march is a chain of dependent loads), and the smallest get 64 x 1.  LBM_CH_TILE=TXxTY
-// overrides; lbm_ch_autotune measures.
+// waves in flight to cover memory latency.  With float32 storage the 512-column tile (8
+// waves per workgroup) is taken when it gives at least 1024 workgroups, i.e. on lattices
+// of 2048^2 and up, where it halves the halo columns of the 256-column tile.  Small lattices thus get
+// short row chunks (each block's march is a chain of dependent loads), and the smallest
+// get 64 x 1.  lbm_ch_set_tiles overrides; lbm_ch_autotune measures.
 static void choose_tiles(lbm_ch_ctx* c) {
   const int nx = c->p.nx, ny = c->p.ny;
   const long min_blocks = c->p.storage == LBM_CH_STORE_F32 ? 512 : 1024;
   int tx = 64, ty = 1;
   bool found = false;
-  for (int xx : {256, 128, 64}) {
+  for (int xx : {512, 256, 128, 64}) {
     if (xx > nx && xx > 64) continue;
+    if (xx == 512 && c->p.storage != LBM_CH_STORE_F32) continue;
+    const long need = xx == 512 ? 2 * min_blocks : min_blocks;
     for (int yy : {32, 16, 8, 4, 2, 1}) {
       const long nb = (long)((nx + xx - 1) / xx) * ((ny + yy - 1) / yy);
-      if (nb >= min_blocks) {
+      if (nb >= need) {
         tx = xx;
         ty = yy;
         found = true;
@@ -170,14 +183,6 @@ static void choose_tiles(lbm_ch_ctx* c) {
       }
     }
     if (found) break;
-  }
-  const char* env = getenv("LBM_CH_TILE");
-  if (env) {
-    int a = 0, b = 0;
-    if (sscanf(env, "%dx%d", &a, &b) == 2 && valid_tile(a, b)) {
-      tx = a;
-      ty = b;
-    }
   }
   apply_tiles(c, tx, ty);
 }
@@ -292,7 +297,7 @@ int lbm_ch_init(lbm_ch_ctx** out, const lbm_ch_params* p, const lbm_ch_velocity*
 
   hipError_t e = launch_fill(z, 0.0f, 2 * (int64_t)(p->nx + p->ny), stream);
   if (e == hipSuccess)
-    e = launch_init(p->walls != 0, c->vmode, p->storage, c->c, p->nx, p->ny, L.plane, phi0,
+    e = launch_init(p->walls != 0, c->vmode, p->storage, c->c, p->nx, p->ny, L.pitch, phi0,
                     c->ax, c->ay, c->bx, c->by, c->ux, c->uy, time_factor(c, 0), c->g[0],
                     c->f[0], stream);
   if (e != hipSuccess) {
@@ -313,7 +318,7 @@ static int run_steps(lbm_ch_ctx* c, int64_t nsteps, float* phi_out, hipStream_t 
   const bool ns = c->p.velocity_mode == LBM_CH_VEL_NS;
   const bool walls = c->p.walls != 0;
   StepArgs a{};
-  a.plane = c->L.plane;
+  a.pitch = c->L.pitch;
   a.nx = c->p.nx;
   a.ny = c->p.ny;
   a.ty = c->ty;
@@ -324,7 +329,7 @@ static int run_steps(lbm_ch_ctx* c, int64_t nsteps, float* phi_out, hipStream_t 
   a.ux = c->ux; a.uy = c->uy;
   NsArgs n{};
   if (ns) {
-    n.plane = c->L.plane;
+    n.pitch = c->L.pitch;
     n.nx = c->p.nx;
     n.ny = c->p.ny;
     n.ty = c->ty;
@@ -356,15 +361,15 @@ static int run_steps(lbm_ch_ctx* c, int64_t nsteps, float* phi_out, hipStream_t 
     if (rec && phi_record_fused(walls, vmode, c->p.model, c->p.storage)) {
       // the step writes phi of its source state itself
       a.phi_rec = rec;
-      e = launch_phi_record(c->tx, vmode, c->p.model, a, c->nblocks, stream);
+      e = launch_phi_record(c->tx, vmode, c->p.model, tau_one(c), a, c->nblocks, stream);
       a.phi_rec = nullptr;
     } else {
       if (rec) {
-        e = launch_phi_field(walls, c->p.storage, c->g[src], c->L.plane, c->p.nx, c->p.ny,
+        e = launch_phi_field(walls, c->p.storage, c->g[src], c->L.pitch, c->p.nx, c->p.ny,
                              rec, stream);
         if (e != hipSuccess) return hip_fail(e);
       }
-      e = launch_phi_step(c->tx, walls, vmode, c->p.model, c->p.storage, a, c->nblocks,
+      e = launch_phi_step(c->tx, walls, vmode, c->p.model, c->p.storage, tau_one(c), a, c->nblocks,
                           stream);
     }
     if (e != hipSuccess) return hip_fail(e);
@@ -481,7 +486,7 @@ int lbm_ch_moments(lbm_ch_ctx* c, float* phi, float* mu, float* ux, float* uy, f
   float* ph = phi ? phi : c->phi;
   hipError_t e = hipSuccess;
   if (phi || mu || ns)
-    e = launch_phi_field(walls, c->p.storage, c->g[c->cur], c->L.plane, nx, ny, ph, stream);
+    e = launch_phi_field(walls, c->p.storage, c->g[c->cur], c->L.pitch, nx, ny, ph, stream);
   if (e == hipSuccess && mu) e = launch_mu_field(walls, c->c, ph, nx, ny, mu, stream);
   if (e != hipSuccess) return hip_fail(e);
   if (ns) {
@@ -491,7 +496,7 @@ int lbm_ch_moments(lbm_ch_ctx* c, float* phi, float* mu, float* ux, float* uy, f
       n.fsrc = c->f[c->cur];
       n.fdst = nullptr;
       n.u = c->u; n.v = c->v; n.p = c->pr;
-      n.plane = c->L.plane;
+      n.pitch = c->L.pitch;
       n.nx = nx; n.ny = ny;
       n.ty = c->ty; n.nstrips = c->nstrips; n.xcd_remap = c->xcd_remap;
       n.c = c->c;
@@ -514,7 +519,7 @@ int lbm_ch_diagnostics(lbm_ch_ctx* c, const float* phi_ref, double* out, hipStre
   if (!out || ((uintptr_t)out & 7u) != 0) return LBM_CH_EINVAL;
   if (phi_ref && !aligned4(phi_ref)) return LBM_CH_EINVAL;
   const bool walls = c->p.walls != 0;
-  hipError_t e = launch_phi_field(walls, c->p.storage, c->g[c->cur], c->L.plane, c->p.nx,
+  hipError_t e = launch_phi_field(walls, c->p.storage, c->g[c->cur], c->L.pitch, c->p.nx,
                                   c->p.ny, c->phi, stream);
   if (e == hipSuccess)
     e = launch_diag(walls, c->c, c->phi, phi_ref, c->p.nx, c->p.ny, c->part, out, stream);
@@ -536,7 +541,7 @@ int64_t lbm_ch_step_count(const lbm_ch_ctx* c) { return live(c) ? c->step : -1; 
 
 size_t lbm_ch_state_bytes(const lbm_ch_ctx* c) {
   if (!live(c)) return 0;
-  const size_t f = (size_t)9 * c->L.plane * sizeof(float);
+  const size_t f = c->L.f_state;
   const size_t x = (size_t)2 * c->p.nx * c->p.ny * sizeof(float);
   return c->L.g_state + (c->p.velocity_mode == LBM_CH_VEL_NS ? f : 0) + (c->xh ? x : 0);
 }
@@ -544,7 +549,7 @@ size_t lbm_ch_state_bytes(const lbm_ch_ctx* c) {
 int lbm_ch_save_state(lbm_ch_ctx* c, void* dst, size_t bytes, hipStream_t stream) {
   if (!live(c)) return LBM_CH_ESTATE;
   if (!dst || bytes != lbm_ch_state_bytes(c)) return LBM_CH_EINVAL;
-  const size_t g = c->L.g_state, f = (size_t)9 * c->L.plane * sizeof(float);
+  const size_t g = c->L.g_state, f = c->L.f_state;
   const size_t fo = c->f[0] ? f : 0, x = (size_t)2 * c->p.nx * c->p.ny * sizeof(float);
   hipError_t e = hipMemcpyAsync(dst, c->g[c->cur], g, hipMemcpyDeviceToDevice, stream);
   if (e == hipSuccess && c->f[0])
@@ -558,7 +563,7 @@ int lbm_ch_load_state(lbm_ch_ctx* c, const void* src, size_t bytes, int64_t step
                       hipStream_t stream) {
   if (!live(c)) return LBM_CH_ESTATE;
   if (!src || bytes != lbm_ch_state_bytes(c) || step < 0) return LBM_CH_EINVAL;
-  const size_t g = c->L.g_state, f = (size_t)9 * c->L.plane * sizeof(float);
+  const size_t g = c->L.g_state, f = c->L.f_state;
   const size_t fo = c->f[0] ? f : 0, x = (size_t)2 * c->p.nx * c->p.ny * sizeof(float);
   hipError_t e = hipMemcpyAsync(c->g[c->cur], src, g, hipMemcpyDeviceToDevice, stream);
   if (e == hipSuccess && c->f[0])
@@ -600,7 +605,7 @@ int lbm_ch_autotune(lbm_ch_ctx* c, void* backup, size_t backup_bytes, int32_t tr
   float best = -1.0f;
   int btx = tx0, bty = ty0;
   const int nx = c->p.nx, ny = c->p.ny;
-  for (int xx : {64, 128, 256}) {
+  for (int xx : {64, 128, 256, 512}) {
     if (e != hipSuccess) break;
     if (xx > 64 && xx / 2 >= nx) continue;  // more than half the lanes idle
     for (int yy : {1, 2, 4, 8, 16, 32}) {
@@ -731,6 +736,7 @@ namespace {
 struct BatchGroup {
   int tx, vmode;
   bool model2;
+  bool t1;           // tau_g = 1 tile
   int first, count;  // range in the instance order
   int start_off;     // offset of this group's start[] in the device start array
   int total, grid;
@@ -805,7 +811,7 @@ static int batch_build(lbm_ch_batch* b, hipStream_t stream) {
   }
   auto key = [&](int i) {
     const lbm_ch_ctx* c = b->ctx[i];
-    return txs[i] * 16 + c->vmode * 2 + (c->p.model == 2 ? 1 : 0);
+    return txs[i] * 32 + c->vmode * 4 + (c->p.model == 2 ? 2 : 0) + (tau_one(c) ? 1 : 0);
   };
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return key(x) < key(y); });
   b->hargs.assign(n, StepArgs{});
@@ -821,6 +827,7 @@ static int batch_build(lbm_ch_batch* b, hipStream_t stream) {
       g.tx = txs[i];
       g.vmode = c->vmode;
       g.model2 = c->p.model == 2;
+      g.t1 = tau_one(c);
       g.first = k;
       g.start_off = (int)b->hstart.size();
       b->groups.push_back(g);
@@ -830,7 +837,7 @@ static int batch_build(lbm_ch_batch* b, hipStream_t stream) {
     StepArgs& a = b->hargs[k];
     a.src = c->g[c->cur];
     a.dst = c->g[1 - c->cur];
-    a.plane = c->L.plane;
+    a.pitch = c->L.pitch;
     a.nx = c->p.nx;
     a.ny = c->p.ny;
     a.ty = ty;
@@ -849,7 +856,7 @@ static int batch_build(lbm_ch_batch* b, hipStream_t stream) {
   for (BatchGroup& g : b->groups) {
     const int want = (g.total + 7) / 8 * 8;
     if (b->persistent) {
-      const int per_cu = phi_batch_blocks_per_cu(g.tx, g.vmode, g.model2);
+      const int per_cu = phi_batch_blocks_per_cu(g.tx, g.vmode, g.model2, g.t1);
       const int resident = b->cus * per_cu / 8 * 8;
       g.grid = want < resident ? want : (resident > 8 ? resident : 8);
     } else {
@@ -887,7 +894,7 @@ static hipError_t batch_enqueue(lbm_ch_batch* b, int64_t nsteps, int phase, hipS
       a.n = g.count;
       a.total = g.total;
       a.parity = (int)((phase + k) & 1);
-      hipError_t e = launch_phi_batch(g.tx, g.vmode, g.model2, b->persistent != 0, a, g.grid, s);
+      hipError_t e = launch_phi_batch(g.tx, g.vmode, g.model2, g.t1, b->persistent != 0, a, g.grid, s);
       if (e != hipSuccess) return e;
     }
   }
@@ -953,7 +960,7 @@ int lbm_ch_batch_create(lbm_ch_batch** out, lbm_ch_ctx* const* ctxs, int32_t n,
 
 int lbm_ch_batch_set_tiles(lbm_ch_batch* b, int32_t tx, int32_t ty) {
   if (!batch_live(b)) return LBM_CH_ESTATE;
-  if (!(tx == 0 || valid_tile(tx, 1)) || ty < 1) return LBM_CH_EINVAL;
+  if (!(tx == 0 || (valid_tile(tx, 1) && tx <= 256)) || ty < 1) return LBM_CH_EINVAL;
   b->tx_policy = tx;
   b->ty = ty;
   b->built = false;

@@ -34,24 +34,26 @@ __device__ __forceinline__ void stencil_at(const float* f, int nx, int ny, int x
 // The initial state is written in that form, so that the first pull returns
 // g_i = g_i^eq(phi0, mu[phi0], u(t0)) (and f_i = f_i^eq(0, rho(phi0), u0)) at every node.
 template <bool WALLS>
-__device__ __forceinline__ void push_target(int nx, int ny, int x, int y, int i, int& plane_i,
-                                            uint32_t& node) {
+__device__ __forceinline__ void push_target(int nx, int ny, int x, int y, int i, int& pop_i,
+                                            uint32_t& col, uint32_t& row) {
   int ty = y - CY[i];
   if (WALLS && (ty < 0 || ty >= ny)) {
     constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
-    plane_i = OPP[i];
-    node = (uint32_t)y * nx + x;
+    pop_i = OPP[i];
+    col = (uint32_t)x;
+    row = (uint32_t)y;
     return;
   }
   int tx = x - CX[i];
   tx = tx < 0 ? tx + nx : (tx >= nx ? tx - nx : tx);
   ty = ty < 0 ? ty + ny : (ty >= ny ? ty - ny : ty);
-  plane_i = i;
-  node = (uint32_t)ty * nx + tx;
+  pop_i = i;
+  col = (uint32_t)tx;
+  row = (uint32_t)ty;
 }
 
 template <bool WALLS, int VMODE, int ST>
-__global__ void __launch_bounds__(256) k_init(const Coef c, int nx, int ny, uint32_t plane,
+__global__ void __launch_bounds__(256) k_init(const Coef c, int nx, int ny, uint32_t pitch,
                                               const float* __restrict__ phi0, const float* ax,
                                               const float* ay, const float* bx, const float* by,
                                               const float* ux, const float* uy, float tf,
@@ -93,12 +95,12 @@ __global__ void __launch_bounds__(256) k_init(const Coef c, int nx, int ny, uint
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     int pi;
-    uint32_t node;
-    push_target<WALLS>(nx, ny, x, y, i, pi, node);
+    uint32_t col, row;
+    push_target<WALLS>(nx, ny, x, y, i, pi, col, row);
     if (ST == ST_F32 || pi == 0)
-      reinterpret_cast<float*>(g)[(uint32_t)pi * plane + node] = geq[i];
+      *reinterpret_cast<float*>(g + pop_off<ST>(pi, pitch, row) + 4u * col) = geq[i];
     else
-      reinterpret_cast<unsigned short*>(g + 4u * plane)[(uint32_t)(pi - 1) * plane + node] =
+      *reinterpret_cast<unsigned short*>(g + pop_off<ST>(pi, pitch, row) + 2u * col) =
           (unsigned short)h[i];
   }
   if (f) {
@@ -107,20 +109,20 @@ __global__ void __launch_bounds__(256) k_init(const Coef c, int nx, int ny, uint
     for (int i = 0; i < 9; ++i) {
       const float cu = CX[i] * u + CY[i] * v;
       int pi;
-      uint32_t node;
-      push_target<WALLS>(nx, ny, x, y, i, pi, node);
-      f[(uint32_t)pi * plane + node] = WT[i] * rho * (cu * (3.0f + 4.5f * cu) - usq15);
+      uint32_t col, row;
+      push_target<WALLS>(nx, ny, x, y, i, pi, col, row);
+      f[pop_off<ST_F32>(pi, pitch, row) / 4u + col] = WT[i] * rho * (cu * (3.0f + 4.5f * cu) - usq15);
     }
   }
 }
 
 template <bool WALLS, int ST>
-__global__ void __launch_bounds__(256) k_phi_field(const void* __restrict__ g, uint32_t plane,
+__global__ void __launch_bounds__(256) k_phi_field(const void* __restrict__ g, uint32_t pitch,
                                                    int nx, int ny, float* __restrict__ phi) {
   const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
   if (x >= nx) return;
   float p[9];
-  pull9<WALLS, ST>(make_rsrc(g, pop_bytes(ST, plane)), plane, nx, ny, y, x,
+  pull9<WALLS, ST>(make_rsrc(g, pop_bytes(ST, pitch, ny)), pitch, ny, y, x,
                    x == 0 ? nx - 1 : x - 1, x == nx - 1 ? 0 : x + 1, p);
   phi[(uint32_t)y * nx + x] = sum9(p);
 }
@@ -438,54 +440,54 @@ __global__ void __launch_bounds__(ATW * ATH) k_adjoint(const AdjArgs a) {
 
 template <int ST>
 void init_l(bool walls, int vmode, dim3 grid, hipStream_t s, const Coef& c, int nx, int ny,
-            uint32_t plane, const float* phi0, const float* ax, const float* ay,
+            uint32_t pitch, const float* phi0, const float* ax, const float* ay,
             const float* bx, const float* by, const float* ux, const float* uy, float tf,
             char* g, float* f) {
   const bool sep = vmode == VEL_SEP;
   if (walls && sep)
-    hipLaunchKernelGGL((k_init<true, VEL_SEP, ST>), grid, dim3(256), 0, s, c, nx, ny, plane, phi0, ax, ay, bx, by, ux, uy, tf, g, f);
+    hipLaunchKernelGGL((k_init<true, VEL_SEP, ST>), grid, dim3(256), 0, s, c, nx, ny, pitch, phi0, ax, ay, bx, by, ux, uy, tf, g, f);
   else if (walls)
-    hipLaunchKernelGGL((k_init<true, VEL_FIELD, ST>), grid, dim3(256), 0, s, c, nx, ny, plane, phi0, ax, ay, bx, by, ux, uy, tf, g, f);
+    hipLaunchKernelGGL((k_init<true, VEL_FIELD, ST>), grid, dim3(256), 0, s, c, nx, ny, pitch, phi0, ax, ay, bx, by, ux, uy, tf, g, f);
   else if (sep)
-    hipLaunchKernelGGL((k_init<false, VEL_SEP, ST>), grid, dim3(256), 0, s, c, nx, ny, plane, phi0, ax, ay, bx, by, ux, uy, tf, g, f);
+    hipLaunchKernelGGL((k_init<false, VEL_SEP, ST>), grid, dim3(256), 0, s, c, nx, ny, pitch, phi0, ax, ay, bx, by, ux, uy, tf, g, f);
   else
-    hipLaunchKernelGGL((k_init<false, VEL_FIELD, ST>), grid, dim3(256), 0, s, c, nx, ny, plane, phi0, ax, ay, bx, by, ux, uy, tf, g, f);
+    hipLaunchKernelGGL((k_init<false, VEL_FIELD, ST>), grid, dim3(256), 0, s, c, nx, ny, pitch, phi0, ax, ay, bx, by, ux, uy, tf, g, f);
 }
 
 }  // namespace
 
-uint32_t population_bytes(int storage, uint32_t plane) { return pop_bytes(storage, plane); }
+uint32_t population_bytes(int storage, uint32_t pitch, uint32_t ny) { return pop_bytes(storage, pitch, ny); }
 
 hipError_t launch_init(bool walls, int vmode, int storage, const Coef& c, int nx, int ny,
-                       uint32_t plane, const float* phi0, const float* ax, const float* ay,
+                       uint32_t pitch, const float* phi0, const float* ax, const float* ay,
                        const float* bx, const float* by, const float* ux, const float* uy,
                        float tf, void* g, float* f, hipStream_t s) {
   const dim3 grid((nx + 255) / 256, ny);
   char* gb = static_cast<char*>(g);
   switch (storage) {
-    case ST_F32: init_l<ST_F32>(walls, vmode, grid, s, c, nx, ny, plane, phi0, ax, ay, bx, by, ux, uy, tf, gb, f); break;
-    case ST_F16: init_l<ST_F16>(walls, vmode, grid, s, c, nx, ny, plane, phi0, ax, ay, bx, by, ux, uy, tf, gb, f); break;
-    case ST_BF16: init_l<ST_BF16>(walls, vmode, grid, s, c, nx, ny, plane, phi0, ax, ay, bx, by, ux, uy, tf, gb, f); break;
+    case ST_F32: init_l<ST_F32>(walls, vmode, grid, s, c, nx, ny, pitch, phi0, ax, ay, bx, by, ux, uy, tf, gb, f); break;
+    case ST_F16: init_l<ST_F16>(walls, vmode, grid, s, c, nx, ny, pitch, phi0, ax, ay, bx, by, ux, uy, tf, gb, f); break;
+    case ST_BF16: init_l<ST_BF16>(walls, vmode, grid, s, c, nx, ny, pitch, phi0, ax, ay, bx, by, ux, uy, tf, gb, f); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_phi_field(bool walls, int storage, const void* g, uint32_t plane, int nx,
+hipError_t launch_phi_field(bool walls, int storage, const void* g, uint32_t pitch, int nx,
                             int ny, float* phi, hipStream_t s) {
   const dim3 grid((nx + 255) / 256, ny);
   switch (storage) {
     case ST_F32:
-      if (walls) hipLaunchKernelGGL((k_phi_field<true, ST_F32>), grid, dim3(256), 0, s, g, plane, nx, ny, phi);
-      else hipLaunchKernelGGL((k_phi_field<false, ST_F32>), grid, dim3(256), 0, s, g, plane, nx, ny, phi);
+      if (walls) hipLaunchKernelGGL((k_phi_field<true, ST_F32>), grid, dim3(256), 0, s, g, pitch, nx, ny, phi);
+      else hipLaunchKernelGGL((k_phi_field<false, ST_F32>), grid, dim3(256), 0, s, g, pitch, nx, ny, phi);
       break;
     case ST_F16:
-      if (walls) hipLaunchKernelGGL((k_phi_field<true, ST_F16>), grid, dim3(256), 0, s, g, plane, nx, ny, phi);
-      else hipLaunchKernelGGL((k_phi_field<false, ST_F16>), grid, dim3(256), 0, s, g, plane, nx, ny, phi);
+      if (walls) hipLaunchKernelGGL((k_phi_field<true, ST_F16>), grid, dim3(256), 0, s, g, pitch, nx, ny, phi);
+      else hipLaunchKernelGGL((k_phi_field<false, ST_F16>), grid, dim3(256), 0, s, g, pitch, nx, ny, phi);
       break;
     case ST_BF16:
-      if (walls) hipLaunchKernelGGL((k_phi_field<true, ST_BF16>), grid, dim3(256), 0, s, g, plane, nx, ny, phi);
-      else hipLaunchKernelGGL((k_phi_field<false, ST_BF16>), grid, dim3(256), 0, s, g, plane, nx, ny, phi);
+      if (walls) hipLaunchKernelGGL((k_phi_field<true, ST_BF16>), grid, dim3(256), 0, s, g, pitch, nx, ny, phi);
+      else hipLaunchKernelGGL((k_phi_field<false, ST_BF16>), grid, dim3(256), 0, s, g, pitch, nx, ny, phi);
       break;
     default: return hipErrorInvalidValue;
   }

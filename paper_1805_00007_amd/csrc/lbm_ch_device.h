@@ -59,17 +59,36 @@ __device__ __forceinline__ void stb_nt(rsrc_t r, float v, uint32_t voff, uint32_
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, CP_NT);
 }
 
-// Population storage.  ST_F32: nine float32 planes.  ST_F16 / ST_BF16: the rest
-// population g_0 as a float32 plane, then eight 16-bit planes holding g_i / w_i
-// (i = 1..8) in IEEE half or bfloat16.  The moving populations of Eq. geq are
+// Population storage.  ST_F32: nine float32 populations.  ST_F16 / ST_BF16: the rest
+// population g_0 in float32, then the eight moving populations as 16-bit codes of
+// g_i / w_i (i = 1..8) in IEEE half or bfloat16.  The moving populations of Eq. geq are
 // w_i (eta mu + phi s_i(u)), of order w_i |u|, so their scaled values are small and a
 // 16-bit code keeps them to ~1e-4 of that size; g_0 ~ phi stays in float32 and, through
 // the mass closure below, absorbs the rounding of the others.
+//
+// Layout in memory: row-interleaved.  Lattice row r holds its nine populations next to
+// each other, each as a run of `pitch` values (x fastest, pitch >= nx), so that one
+// row of the whole state is one contiguous range of memory:
+//   float32: population i of row r starts at float (9 r + i) pitch;
+//   16-bit:  row r starts at byte 20 r pitch, with g_0 as pitch float32 values followed
+//            by g_1..g_8 as pitch 16-bit codes each.
+// A step reads three consecutive rows of the source and writes one row of the
+// destination per marched row, so the memory system sees a few compact streams rather
+// than eighteen planes far apart.
 enum Storage { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
 constexpr float INV_W[9] = {9.0f / 4, 9.0f, 9.0f, 9.0f, 9.0f, 36.0f, 36.0f, 36.0f, 36.0f};
 
-__host__ __device__ constexpr uint32_t pop_bytes(int st, uint32_t plane) {
-  return st == ST_F32 ? 36u * plane : 20u * plane;
+__host__ __device__ constexpr uint32_t pop_row_bytes(int st, uint32_t pitch) {
+  return st == ST_F32 ? 36u * pitch : 20u * pitch;
+}
+__host__ __device__ constexpr uint32_t pop_bytes(int st, uint32_t pitch, uint32_t ny) {
+  return pop_row_bytes(st, pitch) * ny;
+}
+// Byte offset of the first value of population i in lattice row `row`.
+template <int ST>
+__host__ __device__ constexpr uint32_t pop_off(int i, uint32_t pitch, uint32_t row) {
+  return ST == ST_F32 ? ((row * 9u + (uint32_t)i) * pitch) * 4u
+                      : row * 20u * pitch + (i == 0 ? 0u : 4u * pitch + (uint32_t)(i - 1) * 2u * pitch);
 }
 template <int ST>
 __device__ __forceinline__ float dec16(uint32_t h) {
@@ -85,11 +104,10 @@ __device__ __forceinline__ uint32_t enc16(float f) {
 
 // Population i at (column col, row) of a buffer in storage ST.
 template <int ST>
-__device__ __forceinline__ float ldpop(rsrc_t s, int i, uint32_t plane, uint32_t nx,
-                                       uint32_t col, uint32_t row) {
-  if (ST == ST_F32 || i == 0) return ldb(s, col * 4u, ((uint32_t)i * plane + row * nx) * 4u);
-  const uint32_t h = __builtin_amdgcn_raw_buffer_load_b16(
-      s, col * 2u, plane * 4u + ((uint32_t)(i - 1) * plane + row * nx) * 2u, 0);
+__device__ __forceinline__ float ldpop(rsrc_t s, int i, uint32_t pitch, uint32_t col,
+                                       uint32_t row) {
+  if (ST == ST_F32 || i == 0) return ldb(s, col * 4u, pop_off<ST>(i, pitch, row));
+  const uint32_t h = __builtin_amdgcn_raw_buffer_load_b16(s, col * 2u, pop_off<ST>(i, pitch, row), 0);
   return WT[i] * dec16<ST>(h);
 }
 
@@ -99,31 +117,31 @@ __device__ __forceinline__ float ldpop(rsrc_t s, int i, uint32_t plane, uint32_t
 // are the columns x, x-1, x+1 (wrapped).  Plane and row offsets travel in the
 // instruction's scalar offset, so a load costs no vector ALU work beyond its column.
 template <bool WALLS, int ST>
-__device__ __forceinline__ void pull9(rsrc_t s, uint32_t plane, uint32_t nx, int ny, int y,
-                                      uint32_t cc, uint32_t cm, uint32_t cp, float g[9]) {
+__device__ __forceinline__ void pull9(rsrc_t s, uint32_t pitch, int ny, int y, uint32_t cc,
+                                      uint32_t cm, uint32_t cp, float g[9]) {
   const uint32_t ym = y == 0 ? ny - 1 : y - 1;
   const uint32_t yp = y == ny - 1 ? 0 : y + 1;
   const uint32_t yc = y;
-  g[0] = ldpop<ST>(s, 0, plane, nx, cc, yc);
-  g[1] = ldpop<ST>(s, 1, plane, nx, cm, yc);
-  g[3] = ldpop<ST>(s, 3, plane, nx, cp, yc);
+  g[0] = ldpop<ST>(s, 0, pitch, cc, yc);
+  g[1] = ldpop<ST>(s, 1, pitch, cm, yc);
+  g[3] = ldpop<ST>(s, 3, pitch, cp, yc);
   if (WALLS && y == 0) {
-    g[2] = ldpop<ST>(s, 4, plane, nx, cc, yc);
-    g[5] = ldpop<ST>(s, 7, plane, nx, cc, yc);
-    g[6] = ldpop<ST>(s, 8, plane, nx, cc, yc);
+    g[2] = ldpop<ST>(s, 4, pitch, cc, yc);
+    g[5] = ldpop<ST>(s, 7, pitch, cc, yc);
+    g[6] = ldpop<ST>(s, 8, pitch, cc, yc);
   } else {
-    g[2] = ldpop<ST>(s, 2, plane, nx, cc, ym);
-    g[5] = ldpop<ST>(s, 5, plane, nx, cm, ym);
-    g[6] = ldpop<ST>(s, 6, plane, nx, cp, ym);
+    g[2] = ldpop<ST>(s, 2, pitch, cc, ym);
+    g[5] = ldpop<ST>(s, 5, pitch, cm, ym);
+    g[6] = ldpop<ST>(s, 6, pitch, cp, ym);
   }
   if (WALLS && y == ny - 1) {
-    g[4] = ldpop<ST>(s, 2, plane, nx, cc, yc);
-    g[7] = ldpop<ST>(s, 5, plane, nx, cc, yc);
-    g[8] = ldpop<ST>(s, 6, plane, nx, cc, yc);
+    g[4] = ldpop<ST>(s, 2, pitch, cc, yc);
+    g[7] = ldpop<ST>(s, 5, pitch, cc, yc);
+    g[8] = ldpop<ST>(s, 6, pitch, cc, yc);
   } else {
-    g[4] = ldpop<ST>(s, 4, plane, nx, cc, yp);
-    g[7] = ldpop<ST>(s, 7, plane, nx, cp, yp);
-    g[8] = ldpop<ST>(s, 8, plane, nx, cm, yp);
+    g[4] = ldpop<ST>(s, 4, pitch, cc, yp);
+    g[7] = ldpop<ST>(s, 7, pitch, cp, yp);
+    g[8] = ldpop<ST>(s, 8, pitch, cm, yp);
   }
 }
 
@@ -153,12 +171,12 @@ __device__ __forceinline__ void close_mass(double m, float g[9]) {
 // up to the float32 rounding of g_0, which takes m minus the decoded others).  Returns
 // the stored values in g.
 template <int ST>
-__device__ __forceinline__ void finish_store(rsrc_t d, uint32_t plane, uint32_t nx,
-                                             uint32_t col, uint32_t row, double m, float g[9]) {
+__device__ __forceinline__ void finish_store(rsrc_t d, uint32_t pitch, uint32_t col,
+                                             uint32_t row, double m, float g[9]) {
   if (ST == ST_F32) {
     close_mass(m, g);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) stb_nt(d, g[i], col * 4u, ((uint32_t)i * plane + row * nx) * 4u);
+    for (int i = 0; i < 9; ++i) stb_nt(d, g[i], col * 4u, pop_off<ST>(i, pitch, row));
     return;
   }
   uint32_t h[9];
@@ -168,11 +186,11 @@ __device__ __forceinline__ void finish_store(rsrc_t d, uint32_t plane, uint32_t 
     g[i] = WT[i] * dec16<ST>(h[i]);
   }
   g[0] = (float)(m - sum8_hi(g));
-  stb(d, g[0], col * 4u, row * nx * 4u);
+  stb(d, g[0], col * 4u, pop_off<ST>(0, pitch, row));
 #pragma unroll
   for (int i = 1; i < 9; ++i)
     __builtin_amdgcn_raw_buffer_store_b16((unsigned short)h[i], d, col * 2u,
-                                          plane * 4u + ((uint32_t)(i - 1) * plane + row * nx) * 2u, 0);
+                                          pop_off<ST>(i, pitch, row), 0);
 }
 
 __device__ __forceinline__ float sum9(const float g[9], float& lo) {

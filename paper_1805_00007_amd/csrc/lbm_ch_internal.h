@@ -32,7 +32,7 @@ struct Coef {
 struct StepArgs {
   const void* src;    // populations at t_n (layout of the storage mode)
   void* dst;          // populations at t_{n+1}
-  uint32_t plane;     // floats between planes (>= nx*ny)
+  uint32_t pitch;     // values per population row (>= nx), see the layout in lbm_ch_device.h
   int nx, ny;
   int ty;             // rows per block
   int nstrips;        // ceil(nx / TX)
@@ -64,7 +64,7 @@ struct NsArgs {
   const float* fsrc;  // NS populations at t_n
   float* fdst;        // NS populations at t_{n+1} (may be null: moments only)
   float *u, *v, *p;   // velocity and pressure at t_n (written)
-  uint32_t plane;
+  uint32_t pitch;     // values per population row (g and f)
   int nx, ny;
   int ty, nstrips, xcd_remap;
   Coef c;
@@ -73,31 +73,34 @@ struct NsArgs {
 enum VelMode { VEL_SEP = 0, VEL_FIELD = 1, VEL_NSFIELD = 2 };
 
 // Population storage (LBM_CH_STORE_*): 0 float32; 1 half, 2 bfloat16 (g_0 float32, g_1..8
-// as 16-bit codes of g_i / w_i).  Bytes of one population buffer of `plane` nodes/plane.
-uint32_t population_bytes(int storage, uint32_t plane);
+// as 16-bit codes of g_i / w_i).  Bytes of one population buffer of ny rows of `pitch`
+// values per population (row-interleaved, see lbm_ch_device.h).
+uint32_t population_bytes(int storage, uint32_t pitch, uint32_t ny);
 
 // Launchers (return hipGetLastError() of the launch).
-hipError_t launch_phi_step(int tx, bool walls, int vmode, int model, int storage,
+// t1: tau_g = 1 (omega = 1), which selects the reduced tile for float32 storage, models
+// 1 and 2 and a prescribed velocity (other cases ignore it).
+hipError_t launch_phi_step(int tx, bool walls, int vmode, int model, int storage, bool t1,
                            const StepArgs& a, int nblocks, hipStream_t s);
 // The same step that also writes phi of the source state to a.phi_rec (the sums stage 1
 // forms anyway).  Periodic float32 lattices with a prescribed velocity (VEL_SEP or
 // VEL_FIELD) and model 1 or 2 only; hipErrorInvalidValue otherwise.
 bool phi_record_fused(bool walls, int vmode, int model, int storage);
-hipError_t launch_phi_record(int tx, int vmode, int model, const StepArgs& a, int nblocks,
-                             hipStream_t s);
+hipError_t launch_phi_record(int tx, int vmode, int model, bool t1, const StepArgs& a,
+                             int nblocks, hipStream_t s);
 // grid: a multiple of 8 workgroups.  persistent: the grid strides over the tiles (size
 // it with phi_batch_blocks_per_cu); otherwise one tile per workgroup (grid >= tiles).
-int phi_batch_blocks_per_cu(int tx, int vmode, bool model2);
-hipError_t launch_phi_batch(int tx, int vmode, bool model2, bool persistent, const BatchArgs& b,
-                            int grid, hipStream_t s);
+int phi_batch_blocks_per_cu(int tx, int vmode, bool model2, bool t1);
+hipError_t launch_phi_batch(int tx, int vmode, bool model2, bool t1, bool persistent,
+                            const BatchArgs& b, int grid, hipStream_t s);
 hipError_t launch_ns_step(int tx, bool walls, int storage, const NsArgs& a, int nblocks,
                           hipStream_t s);
 
 hipError_t launch_init(bool walls, int vmode, int storage, const Coef& c, int nx, int ny,
-                       uint32_t plane, const float* phi0, const float* ax, const float* ay,
+                       uint32_t pitch, const float* phi0, const float* ax, const float* ay,
                        const float* bx, const float* by, const float* ux, const float* uy,
                        float tf, void* g, float* f, hipStream_t s);
-hipError_t launch_phi_field(bool walls, int storage, const void* g, uint32_t plane, int nx,
+hipError_t launch_phi_field(bool walls, int storage, const void* g, uint32_t pitch, int nx,
                             int ny, float* phi, hipStream_t s);
 hipError_t launch_mu_field(bool walls, const Coef& c, const float* phi, int nx, int ny,
                            float* mu, hipStream_t s);

@@ -20,10 +20,10 @@ __global__ void __launch_bounds__(TX) k_ns_step(const NsArgs a) {
   const Coef& c = a.c;
   const int nx = a.nx, ny = a.ny;
   const uint32_t nodes = (uint32_t)nx * ny;
-  const uint32_t pb = a.plane * 4u;
-  const rsrc_t rg = make_rsrc(a.gsrc, pop_bytes(ST, a.plane));
-  const rsrc_t rf = make_rsrc(a.fsrc, 9u * pb);
-  const rsrc_t rfd = make_rsrc(a.fdst, a.fdst ? 9u * pb : 0u);
+  const uint32_t pitch = a.pitch;
+  const rsrc_t rg = make_rsrc(a.gsrc, pop_bytes(ST, pitch, ny));
+  const rsrc_t rf = make_rsrc(a.fsrc, pop_bytes(ST_F32, pitch, ny));
+  const rsrc_t rfd = make_rsrc(a.fdst, a.fdst ? pop_bytes(ST_F32, pitch, ny) : 0u);
   const rsrc_t ru = make_rsrc(a.u, nodes * 4u);
   const rsrc_t rv = make_rsrc(a.v, nodes * 4u);
   const rsrc_t rpr = make_rsrc(a.p, nodes * 4u);
@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(TX) k_ns_step(const NsArgs a) {
   auto pull_g = [&](int r, uint32_t cc, uint32_t cm, uint32_t cq, float g[9]) {
     float sg;
     const int sr = row_of<WALLS>(r, ny, sg);
-    pull9<WALLS, ST>(rg, a.plane, nx, ny, sr, cc, cm, cq, g);
+    pull9<WALLS, ST>(rg, pitch, ny, sr, cc, cm, cq, g);
   };
   {
     // prologue: rows y0-2 .. y0+1 of g (own and halo columns), all pulled before any
@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(TX) k_ns_step(const NsArgs a) {
     pull_g(y + 2, xc, xm, xp, gn);
     if (hwave) pull_g(y + 2, hvc, hvm, hvp, ghn);
     __builtin_amdgcn_sched_barrier(0);
-    pull9<WALLS, ST_F32>(rf, a.plane, nx, ny, y, xc, xm, xp, fpop);
+    pull9<WALLS, ST_F32>(rf, pitch, ny, y, xc, xm, xp, fpop);
     __builtin_amdgcn_sched_barrier(0);
     s_phi[(y + 2) & 7][j] = sum9(gn);
     if (hwave) {
@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(TX) k_ns_step(const NsArgs a) {
           const float su = cu * (3.0f + 4.5f * cu) - usq15;
           const float feq = WT[i] * (p3 + rho * su) - (i == 0 ? p3 : 0.0f);
           const float G = WT[i] * (3.0f * (cF - uF) + 9.0f * cu * cF + 3.0f * cu * cr);
-          stb_nt(rfd, om1 * fpop[i] + om * feq + c.srcf * G, off, i * pb + ro);
+          stb_nt(rfd, om1 * fpop[i] + om * feq + c.srcf * G, off, pop_off<ST_F32>(i, pitch, (uint32_t)y));
         }
       }
     }
@@ -184,6 +184,7 @@ hipError_t ns_step_t(int tx, bool walls, const NsArgs& a, int nb, hipStream_t s)
     case 64: ns_step_l<64, ST>(walls, a, nb, s); break;
     case 128: ns_step_l<128, ST>(walls, a, nb, s); break;
     case 256: ns_step_l<256, ST>(walls, a, nb, s); break;
+    case 512: ns_step_l<512, ST>(walls, a, nb, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

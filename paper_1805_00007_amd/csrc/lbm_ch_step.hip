@@ -64,10 +64,10 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
   const Coef& c = a.c;
   const int nx = a.nx, ny = a.ny;
   const uint32_t nodes = (uint32_t)nx * ny;
-  const uint32_t plane = a.plane;
+  const uint32_t pitch = a.pitch;
   const uint32_t rb = (uint32_t)nx * 4u;
-  const rsrc_t rsrc = make_rsrc(a.src, pop_bytes(ST, plane));
-  const rsrc_t rdst = make_rsrc(a.dst, pop_bytes(ST, plane));
+  const rsrc_t rsrc = make_rsrc(a.src, pop_bytes(ST, pitch, ny));
+  const rsrc_t rdst = make_rsrc(a.dst, pop_bytes(ST, pitch, ny));
   rsrc_t ru, rv, rp;
   if (VFIELD) {
     ru = make_rsrc(a.ux, nodes * 4u);
@@ -129,7 +129,7 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
   auto issue = [&](int r, uint32_t cc, uint32_t cm, uint32_t cp, RowRec& R, bool own = true) {
     float sg;
     const int sr = row_of<WALLS>(r, ny, sg);
-    pull9<WALLS, ST>(rsrc, plane, nx, ny, sr, cc, cm, cp, R.g);
+    pull9<WALLS, ST>(rsrc, pitch, ny, sr, cc, cm, cp, R.g);
     if (HIST && own) {
       R.xpx = ldb(rxh, cc * 4u, (uint32_t)sr * rb);
       R.xpy = ldb(rxh, cc * 4u, nodes * 4u + (uint32_t)sr * rb);
@@ -223,7 +223,7 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
     const float v = VMODE == VEL_SEP ? bxc * R.fy_v : R.v;
     if (REC) stb_nt(rrec, R.phi, vc * 4u, (uint32_t)y * rb);
     collide_g(c, R.phi, R.lo, m0[j], u, v, fx, fy, R.g);
-    finish_store<ST>(rdst, plane, nx, vc, (uint32_t)y, (double)R.phi + (double)R.lo, R.g);
+    finish_store<ST>(rdst, pitch, vc, (uint32_t)y, (double)R.phi + (double)R.lo, R.g);
   };
 
   // Prologue: rows y0-2d .. y0+2d through stage 1, rows y0-d and y0 through stage 2.
@@ -315,9 +315,338 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
   }
 }
 
+// ---------------------------------------------------------------------------------
+// Fused step at tau_g = 1 (float32 storage, models 1 and 2, prescribed velocity).
+//
+// With omega = 1 the collision of Eq. LB forgets the pulled populations: g_i* =
+// g_i^eq + S_i / 2, so once a row has been pulled and summed its record keeps only
+// phi (with the FP64 remainder of the sum) and the velocity of the row.  Four such
+// small records rotate through a loop unrolled four times (once per marching
+// direction), so every record and every LDS ring slot has a fixed register or
+// address: no record is copied between registers at the back edge and no ring address
+// is computed per row.  Stages, halo lanes, marching directions and the XCD band
+// mapping are those of phi_tile.
+//
+// The unrolled copies of the stages must round identically, or results would depend
+// on the tile shape: this section is compiled without implicit multiply-add
+// contraction, and every fused multiply-add in it is written out.
+#pragma clang fp contract(off)
+// A row's pull in flight (populations plus the velocity inputs of the row), and a
+// row's state after stage 1.
+struct PullT1 {
+  float g[9];
+  float a, b;             // separable: ay[y], by[y]; field: u, v of the node (as loaded)
+};
+struct RowT1 {
+  float phi, lo;          // phi and the FP64 remainder of the sum
+  float a, b;             // separable: ay[y], by[y] times tf (and parity); field: u, v
+};
+
+// The isotropic stencils of Sec. III on LDS rows in lattice order (rm: y-1, r0: y,
+// rp: y+1), as the weighted neighbour sums
+//   d_x = [4 (E - W) + (NE + SE) - (NW + SW)] / 12,  d_y = [4 (N - S) + (NE + NW) - (SE + SW)] / 12,
+//   lap = [4 (E + W + N + S) + (NE + NW + SE + SW) - 20 C] / 6.
+__device__ __forceinline__ float t1_dx(const float* rm, const float* r0, const float* rp, int j) {
+  const float diag = (rp[j + 1] + rm[j + 1]) - (rp[j - 1] + rm[j - 1]);
+  return fmaf(4.0f, r0[j + 1] - r0[j - 1], diag) * (1.0f / 12.0f);
+}
+__device__ __forceinline__ float t1_dy(const float* rm, const float* r0, const float* rp, int j) {
+  const float diag = (rp[j + 1] + rp[j - 1]) - (rm[j + 1] + rm[j - 1]);
+  return fmaf(4.0f, rp[j] - rm[j], diag) * (1.0f / 12.0f);
+}
+__device__ __forceinline__ float t1_lap(const float* rm, const float* r0, const float* rp, int j) {
+  const float axis = (r0[j + 1] + r0[j - 1]) + (rp[j] + rm[j]);
+  const float diag = (rp[j + 1] + rp[j - 1]) + (rm[j + 1] + rm[j - 1]);
+  return fmaf(4.0f, axis, fmaf(-20.0f, r0[j], diag)) * (1.0f / 6.0f);
+}
+// mu of Eq. mu with the double well of Eq. bulk: 2 beta (phi - phi_A)(phi - phi_B)
+// (2 phi - phi_A - phi_B) - kappa lap(phi).
+__device__ __forceinline__ float t1_mu(const Coef& c, float phi, float lap) {
+  const float bulk = c.beta2 * ((phi - c.phia) * (phi - c.phib)) * ((phi + phi) - (c.phia + c.phib));
+  return fmaf(-c.kappa, lap, bulk);
+}
+
+// Collision at tau_g = 1: g_i* = w_i (eta mu + phi s_i(u)) + (3/2) w_i c_i.F (Eqs. geq,
+// liangFi, LB), written pairwise for opposite directions c_i = -c_j:
+//   g_i,j* = w_i (P +- Q),  P = eta mu - 1.5 phi u^2 + 4.5 phi (c_i.u)^2,
+//                           Q = 3 phi c_i.u + 1.5 c_i.F.
+// g_0* is left to the mass-conserving store.
+__device__ __forceinline__ void collide_t1(const Coef& c, float phi, float mu, float u, float v,
+                                           float fx, float fy, float g[9]) {
+  const float A = fmaf(-1.5f * phi, fmaf(u, u, v * v), c.eta * mu);
+  const float p3 = 3.0f * phi, p45 = 4.5f * phi;
+  const float hx = 1.5f * fx, hy = 1.5f * fy;
+  auto pair = [&](float e, float h, float w, float& gp, float& gm) {
+    const float P = fmaf(p45 * e, e, A);
+    const float Q = fmaf(p3, e, h);
+    gp = w * (P + Q);
+    gm = w * (P - Q);
+  };
+  pair(u, hx, WT[1], g[1], g[3]);
+  pair(v, hy, WT[2], g[2], g[4]);
+  pair(u + v, hx + hy, WT[5], g[5], g[7]);
+  pair(v - u, hy - hx, WT[6], g[6], g[8]);
+}
+
+template <int TX, bool WALLS, int VMODE, int MODEL, bool REC = false>
+__device__ __forceinline__ void phi_tile_t1(const StepArgs& a, const int L) {
+  static_assert(VMODE == VEL_SEP || VMODE == VEL_FIELD, "prescribed velocity only");
+  static_assert(MODEL == 1 || MODEL == 2, "models 1 and 2");
+  constexpr bool MODEL2 = MODEL == 2;
+  constexpr bool VFIELD = VMODE == VEL_FIELD;
+  constexpr int LW = TX + 4;
+  constexpr int QR = MODEL2 ? 4 : 1;
+  __shared__ float s_phi[4][LW];
+  __shared__ float s_mu[4][LW];
+  __shared__ float s_qx[QR][LW];
+  __shared__ float s_qy[QR][LW];
+  __shared__ float s_d[QR][LW];
+
+  const Coef& c = a.c;
+  const int nx = a.nx, ny = a.ny;
+  const uint32_t nodes = (uint32_t)nx * ny;
+  const uint32_t pitch = a.pitch;
+  const uint32_t rb = (uint32_t)nx * 4u;
+  const rsrc_t rsrc = make_rsrc(a.src, pop_bytes(ST_F32, pitch, ny));
+  const rsrc_t rdst = make_rsrc(a.dst, pop_bytes(ST_F32, pitch, ny));
+  rsrc_t ru, rv, rrec;
+  if (VFIELD) {
+    ru = make_rsrc(a.ux, nodes * 4u);
+    rv = make_rsrc(a.uy, nodes * 4u);
+  }
+  if (REC) rrec = make_rsrc(a.phi_rec, nodes * 4u);
+
+  const int t = threadIdx.x;
+  const int x0 = (L % a.nstrips) * TX;
+  const int chunk = L / a.nstrips;
+  const int rows = min(a.ty, ny - chunk * a.ty);
+  const int d = (chunk & 1) ? -1 : 1;  // vertically adjacent chunks march in opposite directions
+  const int y0 = d > 0 ? chunk * a.ty : chunk * a.ty + rows - 1;
+
+  const int xc = (x0 + t) % nx;
+  const uint32_t vc = xc;
+  const uint32_t vm = xc == 0 ? nx - 1 : xc - 1;
+  const uint32_t vp = xc == nx - 1 ? 0 : xc + 1;
+  const bool hl = t < 4;
+  const bool hwave = __builtin_amdgcn_readfirstlane(t) < 64;
+  const int hlog = t < 2 ? x0 - 2 + t : x0 + TX - 2 + t;
+  const int hc = ((hlog % nx) + nx) % nx;
+  constexpr uint32_t OOB = 0x3FFFFFC0u;  // column whose byte offset exceeds any buffer
+  const uint32_t hvc = hl ? hc : OOB;
+  const uint32_t hvm = hl ? (hc == 0 ? nx - 1 : hc - 1) : OOB;
+  const uint32_t hvp = hl ? (hc == nx - 1 ? 0 : hc + 1) : OOB;
+  const int hj = t < 2 ? t : TX + t;
+  const int j = t + 2;
+  const int j2 = t == 0 ? 1 : TX + 2;
+
+  float axc = 0.f, bxc = 0.f, axh = 0.f, bxh = 0.f;
+  if (VMODE == VEL_SEP) {
+    axc = a.ax[xc];
+    bxc = a.bx[xc];
+    if (hl) {
+      axh = a.ax[hc];
+      bxh = a.bx[hc];
+    }
+  }
+
+  // Row m of the march is lattice row y0 + m d (m = -2 .. rows + 1).  Its LDS slot is
+  // (m + 2) & 3 and its state st[m & 3].
+  auto issue = [&](int r, uint32_t cc, uint32_t cm, uint32_t cp, PullT1& P) {
+    float sg;
+    const int sr = row_of<WALLS>(r, ny, sg);
+    pull9<WALLS, ST_F32>(rsrc, pitch, ny, sr, cc, cm, cp, P.g);
+    if (VMODE == VEL_SEP) {
+      P.a = a.ay[sr];
+      P.b = a.by[sr];
+    } else {
+      P.a = ldb(ru, cc * 4u, (uint32_t)sr * rb);
+      P.b = ldb(rv, cc * 4u, (uint32_t)sr * rb);
+    }
+  };
+  auto stage1 = [&](int r, const PullT1& P, RowT1& R, int jj, float axv, float bxv, int slot,
+                    bool wr = true) {
+    float sg;
+    row_of<WALLS>(r, ny, sg);
+    R.phi = sum9(P.g, R.lo);
+    const float f = a.tf * sg;
+    float u, v;
+    if (VMODE == VEL_SEP) {
+      R.a = P.a * f;
+      R.b = P.b * f;
+      u = axv * R.a;
+      v = bxv * R.b;
+    } else {
+      u = R.a = f * P.a;
+      v = R.b = f * P.b;
+    }
+    if (!wr) return;
+    s_phi[slot][jj] = R.phi;
+    if (MODEL2) {
+      s_qx[slot][jj] = R.phi * u;
+      s_qy[slot][jj] = R.phi * v;
+    }
+  };
+  // Stencils take their three rows in lattice order (slots of lattice rows y - 1, y,
+  // y + 1), whichever way the chunk marches, so that every value is computed by the same
+  // expression in every tile.
+  auto stage2 = [&](int jj, int sm, int s0, int sp) {
+    const float* pm = s_phi[sm];
+    const float* p0 = s_phi[s0];
+    const float* pp = s_phi[sp];
+    s_mu[s0][jj] = t1_mu(c, p0[jj], t1_lap(pm, p0, pp, jj));
+    if (MODEL2)
+      s_d[s0][jj] = t1_dx(s_qx[sm], s_qx[s0], s_qx[sp], jj) + t1_dy(s_qy[sm], s_qy[s0], s_qy[sp], jj);
+  };
+  auto stage3 = [&](int y, const RowT1& R, int sm, int s0, int sp) {
+    const float mux = t1_dx(s_mu[sm], s_mu[s0], s_mu[sp], j);
+    const float muy = t1_dy(s_mu[sm], s_mu[s0], s_mu[sp], j);
+    // F1 = (phi/rho) F_s with F_s = -phi grad mu (Eq. t0-phiu, grad p = 0); F2 = K grad D
+    const float rho = fmaf(c.a, R.phi, c.b);
+    const float s1 = -(R.phi * R.phi) * rcp(rho);
+    float fx = s1 * mux, fy = s1 * muy;
+    if (MODEL2) {
+      fx = fmaf(c.k2, t1_dx(s_d[sm], s_d[s0], s_d[sp], j), fx);
+      fy = fmaf(c.k2, t1_dy(s_d[sm], s_d[s0], s_d[sp], j), fy);
+    }
+    const float u = VMODE == VEL_SEP ? axc * R.a : R.a;
+    const float v = VMODE == VEL_SEP ? bxc * R.b : R.b;
+    if (REC) stb_nt(rrec, R.phi, vc * 4u, (uint32_t)y * rb);
+    float g[9];
+    collide_t1(c, R.phi, s_mu[s0][j], u, v, fx, fy, g);
+    finish_store<ST_F32>(rdst, pitch, vc, (uint32_t)y, (double)R.phi + (double)R.lo, g);
+  };
+
+  // Rows the march needs: m = -2 .. rows + 1; a pull past the last one is clamped to it
+  // (already in cache) so that every row issues the same loads.
+  const int last_needed = y0 + (rows + 1) * d;
+  RowT1 st[4];
+  PullT1 pb, hb;
+  {
+    PullT1 T0, T1, P0, P1, U0, U1;
+    RowT1 X;
+    if (hwave) {
+      issue(y0 - 2 * d, hvc, hvm, hvp, U0);
+      issue(y0 - d, hvc, hvm, hvp, U1);
+    }
+    issue(y0 - 2 * d, vc, vm, vp, T0);
+    issue(y0 - d, vc, vm, vp, T1);
+    issue(y0, vc, vm, vp, P0);
+    issue(y0 + d, vc, vm, vp, P1);
+    if (hwave) {
+      stage1(y0 - 2 * d, U0, X, hj, axh, bxh, 0, hl);
+      stage1(y0 - d, U1, X, hj, axh, bxh, 1, hl);
+      issue(y0, hvc, hvm, hvp, U0);
+      issue(y0 + d, hvc, hvm, hvp, U1);
+    }
+    stage1(y0 - 2 * d, T0, X, j, axc, bxc, 0);
+    stage1(y0 - d, T1, X, j, axc, bxc, 1);
+    stage1(y0, P0, st[0], j, axc, bxc, 2);
+    stage1(y0 + d, P1, st[1], j, axc, bxc, 3);
+    if (hwave) {
+      stage1(y0, U0, X, hj, axh, bxh, 2, hl);
+      stage1(y0 + d, U1, X, hj, axh, bxh, 3, hl);
+    }
+  }
+  if (hwave) issue(y0 + 2 * d, hvc, hvm, hvp, hb);
+  issue(y0 + 2 * d, vc, vm, vp, pb);
+  __syncthreads();
+  {
+    // rows m = -1 (slots 0, 1, 2 in march order) and m = 0 (slots 1, 2, 3)
+    const int a0 = d > 0 ? 0 : 2, a2 = d > 0 ? 2 : 0, b1 = d > 0 ? 1 : 3, b3 = d > 0 ? 3 : 1;
+    stage2(j, a0, 1, a2);
+    stage2(j, b1, 2, b3);
+    if (t < 2) {
+      stage2(j2, a0, 1, a2);
+      stage2(j2, b1, 2, b3);
+    }
+  }
+  __syncthreads();
+  {
+    RowT1 X;
+    if (hwave) stage1(y0 + 2 * d, hb, X, hj, axh, bxh, 0, hl);  // row m = 2, slot 0
+  }
+  stage1(y0 + 2 * d, pb, st[2], j, axc, bxc, 0);
+
+  const bool prio = a.ty >= 8;
+  // Row m = k + J (J = m & 3): pull row m + 3, stage 2 of row m + 1, stage 3 of row m
+  // (st[J]), stage 1 of row m + 3 into st[(J + 3) & 3] once its pull has arrived.  Slots:
+  // row m + q -> (J + q + 2) & 3; the stencils get the slots of rows m + q - D and
+  // m + q + D (lattice order), so the loop exists once per marching direction D with
+  // every slot and register a constant.  On the last row the pull is clamped to a row
+  // already in cache and its stage 1 skipped.
+#define LBM_T1_ROW(J, D)                                                                   \
+  if (k + (J) < rows) {                                                                    \
+    const int m = k + (J);                                                                 \
+    const int y = y0 + m * (D);                                                            \
+    const bool more = m + 1 < rows;                                                        \
+    const int ynext = more ? y + 3 * (D) : last_needed;                                    \
+    __builtin_amdgcn_sched_barrier(0);                                                     \
+    if (prio) __builtin_amdgcn_s_setprio(2);                                               \
+    if (hwave) issue(ynext, hvc, hvm, hvp, hb);                                            \
+    __builtin_amdgcn_sched_barrier(0);                                                     \
+    issue(ynext, vc, vm, vp, pb);                                                          \
+    __builtin_amdgcn_sched_barrier(0);                                                     \
+    if (prio) __builtin_amdgcn_s_setprio(0);                                               \
+    __builtin_amdgcn_sched_barrier(0);                                                     \
+    __syncthreads();                                                                       \
+    {                                                                                      \
+      constexpr int lo = (D) > 0 ? ((J) + 2) & 3 : (J) & 3;                                \
+      constexpr int hi = (D) > 0 ? (J) & 3 : ((J) + 2) & 3;                                \
+      stage2(j, lo, ((J) + 3) & 3, hi);                                                    \
+      if (t < 2) stage2(j2, lo, ((J) + 3) & 3, hi);                                        \
+    }                                                                                      \
+    __syncthreads();                                                                       \
+    {                                                                                      \
+      constexpr int lo = (D) > 0 ? ((J) + 1) & 3 : ((J) + 3) & 3;                          \
+      constexpr int hi = (D) > 0 ? ((J) + 3) & 3 : ((J) + 1) & 3;                          \
+      stage3(y, st[(J) & 3], lo, ((J) + 2) & 3, hi);                                       \
+    }                                                                                      \
+    __builtin_amdgcn_sched_barrier(0);                                                     \
+    if (more) {                                                                            \
+      if (hwave) {                                                                         \
+        RowT1 X;                                                                           \
+        stage1(y + 3 * (D), hb, X, hj, axh, bxh, ((J) + 1) & 3, hl);                       \
+      }                                                                                    \
+      stage1(y + 3 * (D), pb, st[((J) + 3) & 3], j, axc, bxc, ((J) + 1) & 3);              \
+    }                                                                                      \
+  }
+  if (d > 0) {
+#pragma unroll 1
+    for (int k = 0; k < rows; k += 4) {
+      LBM_T1_ROW(0, 1)
+      LBM_T1_ROW(1, 1)
+      LBM_T1_ROW(2, 1)
+      LBM_T1_ROW(3, 1)
+    }
+  } else {
+#pragma unroll 1
+    for (int k = 0; k < rows; k += 4) {
+      LBM_T1_ROW(0, -1)
+      LBM_T1_ROW(1, -1)
+      LBM_T1_ROW(2, -1)
+      LBM_T1_ROW(3, -1)
+    }
+  }
+#undef LBM_T1_ROW
+}
+#pragma clang fp contract(fast)
+
 // Model 3 carries two more values per row record; it gets the register budget of
 // three waves per SIMD so that nothing spills.
-template <int TX, bool WALLS, int VMODE, int MODEL, int ST, bool REC = false>
+// T1: the tau_g = 1 tile (float32 storage, models 1 and 2, prescribed velocity only).
+template <int VMODE, int MODEL, int ST>
+constexpr bool t1_ok() {
+  return ST == ST_F32 && (MODEL == 1 || MODEL == 2) && (VMODE == VEL_SEP || VMODE == VEL_FIELD);
+}
+template <int TX, bool WALLS, int VMODE, int MODEL, int ST, bool REC, bool T1>
+__device__ __forceinline__ void step_tile(const StepArgs& a, int L) {
+  if constexpr (T1 && t1_ok<VMODE, MODEL, ST>())
+    phi_tile_t1<TX, WALLS, VMODE, MODEL, REC>(a, L);
+  else
+    phi_tile<TX, WALLS, VMODE, MODEL, ST, REC>(a, L);
+}
+
+template <int TX, bool WALLS, int VMODE, int MODEL, int ST, bool REC = false, bool T1 = false>
 __global__ void __launch_bounds__(TX)
 __attribute__((amdgpu_waves_per_eu(MODEL == 3 ? 3 : WPE_PHI, 8)))
 k_phi_step(const StepArgs a) {
@@ -326,7 +655,7 @@ k_phi_step(const StepArgs a) {
     const int per = gridDim.x >> 3;
     L = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   }
-  phi_tile<TX, WALLS, VMODE, MODEL, ST, REC>(a, L);
+  step_tile<TX, WALLS, VMODE, MODEL, ST, REC, T1>(a, L);
 }
 
 // Batched step, one tile per workgroup: the tiles of many lattices (one instance table
@@ -334,7 +663,7 @@ k_phi_step(const StepArgs a) {
 // is a multiple of 8, XCD x (workgroups w with w % 8 == x) gets the contiguous range
 // [x per, (x + 1) per), so vertically adjacent tiles of one lattice share an L2.  Same
 // register budget as the single-lattice kernel.
-template <int TX, int VMODE, bool MODEL2>
+template <int TX, int VMODE, bool MODEL2, bool T1>
 __global__ void __launch_bounds__(TX) __attribute__((amdgpu_waves_per_eu(WPE_PHI, 8)))
 k_phi_batch(const BatchArgs b) {
   int v = blockIdx.x;
@@ -354,7 +683,7 @@ k_phi_batch(const BatchArgs b) {
     a.src = a.dst;
     a.dst = const_cast<void*>(t);
   }
-  phi_tile<TX, false, VMODE, MODEL2 ? 2 : 1, ST_F32>(a, v - b.start[lo_i]);
+  step_tile<TX, false, VMODE, MODEL2 ? 2 : 1, ST_F32, false, T1>(a, v - b.start[lo_i]);
 }
 
 // Batched step, persistent: the tiles of many lattices (one instance table entry each)
@@ -365,7 +694,7 @@ k_phi_batch(const BatchArgs b) {
 #ifndef WPE_BATCH
 #define WPE_BATCH 3
 #endif
-template <int TX, int VMODE, bool MODEL2>
+template <int TX, int VMODE, bool MODEL2, bool T1>
 __global__ void __launch_bounds__(TX) __attribute__((amdgpu_waves_per_eu(WPE_BATCH, 8)))
 k_phi_batch_persistent(const BatchArgs b) {
   const int slots = gridDim.x >> 3;
@@ -389,13 +718,22 @@ k_phi_batch_persistent(const BatchArgs b) {
       a.src = a.dst;
       a.dst = const_cast<void*>(t);
     }
-    phi_tile<TX, false, VMODE, MODEL2 ? 2 : 1, ST_F32>(a, v - b.start[inst]);
+    step_tile<TX, false, VMODE, MODEL2 ? 2 : 1, ST_F32, false, T1>(a, v - b.start[inst]);
     __syncthreads();  // the LDS rings are reused by the next tile
   }
 }
 
 template <int TX, bool WALLS, int VMODE, int ST>
-hipError_t phi_step_m(int model, const StepArgs& a, int nb, hipStream_t s) {
+hipError_t phi_step_m(int model, bool t1, const StepArgs& a, int nb, hipStream_t s) {
+  if constexpr (t1_ok<VMODE, 2, ST>()) {
+    if (t1 && (model == 1 || model == 2)) {
+      if (model == 2)
+        hipLaunchKernelGGL((k_phi_step<TX, WALLS, VMODE, 2, ST, false, true>), dim3(nb), dim3(TX), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_phi_step<TX, WALLS, VMODE, 1, ST, false, true>), dim3(nb), dim3(TX), 0, s, a);
+      return hipGetLastError();
+    }
+  }
   if (model == 2)
     hipLaunchKernelGGL((k_phi_step<TX, WALLS, VMODE, 2, ST>), dim3(nb), dim3(TX), 0, s, a);
   else if (model == 1)
@@ -407,13 +745,13 @@ hipError_t phi_step_m(int model, const StepArgs& a, int nb, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int TX, bool PERSIST>
+template <int TX, bool PERSIST, bool T1>
 hipError_t phi_batch_t(int vmode, bool model2, const BatchArgs& b, int grid, hipStream_t s) {
-#define LBM_BATCH_LAUNCH(V, M)                                                             \
-  if (PERSIST)                                                                             \
-    hipLaunchKernelGGL((k_phi_batch_persistent<TX, V, M>), dim3(grid), dim3(TX), 0, s, b); \
-  else                                                                                     \
-    hipLaunchKernelGGL((k_phi_batch<TX, V, M>), dim3(grid), dim3(TX), 0, s, b)
+#define LBM_BATCH_LAUNCH(V, M)                                                                 \
+  if (PERSIST)                                                                                 \
+    hipLaunchKernelGGL((k_phi_batch_persistent<TX, V, M, T1>), dim3(grid), dim3(TX), 0, s, b); \
+  else                                                                                         \
+    hipLaunchKernelGGL((k_phi_batch<TX, V, M, T1>), dim3(grid), dim3(TX), 0, s, b)
   if (vmode == VEL_SEP) {
     if (model2) { LBM_BATCH_LAUNCH(VEL_SEP, true); } else { LBM_BATCH_LAUNCH(VEL_SEP, false); }
   } else {
@@ -424,27 +762,30 @@ hipError_t phi_batch_t(int vmode, bool model2, const BatchArgs& b, int grid, hip
 }
 
 template <int TX, bool WALLS, int ST>
-hipError_t phi_step_v(int vmode, int model, const StepArgs& a, int nb, hipStream_t s) {
+hipError_t phi_step_v(int vmode, int model, bool t1, const StepArgs& a, int nb, hipStream_t s) {
   switch (vmode) {
-    case VEL_SEP: return phi_step_m<TX, WALLS, VEL_SEP, ST>(model, a, nb, s);
-    case VEL_FIELD: return phi_step_m<TX, WALLS, VEL_FIELD, ST>(model, a, nb, s);
-    default: return phi_step_m<TX, WALLS, VEL_NSFIELD, ST>(model, a, nb, s);
+    case VEL_SEP: return phi_step_m<TX, WALLS, VEL_SEP, ST>(model, t1, a, nb, s);
+    case VEL_FIELD: return phi_step_m<TX, WALLS, VEL_FIELD, ST>(model, t1, a, nb, s);
+    default: return phi_step_m<TX, WALLS, VEL_NSFIELD, ST>(model, t1, a, nb, s);
   }
 }
 
 template <int ST>
-hipError_t phi_step_t(int tx, bool walls, int vmode, int model, const StepArgs& a, int nb,
-                      hipStream_t s) {
+hipError_t phi_step_t(int tx, bool walls, int vmode, int model, bool t1, const StepArgs& a,
+                      int nb, hipStream_t s) {
   switch (tx) {
     case 64:
-      return walls ? phi_step_v<64, true, ST>(vmode, model, a, nb, s)
-                   : phi_step_v<64, false, ST>(vmode, model, a, nb, s);
+      return walls ? phi_step_v<64, true, ST>(vmode, model, t1, a, nb, s)
+                   : phi_step_v<64, false, ST>(vmode, model, t1, a, nb, s);
     case 128:
-      return walls ? phi_step_v<128, true, ST>(vmode, model, a, nb, s)
-                   : phi_step_v<128, false, ST>(vmode, model, a, nb, s);
+      return walls ? phi_step_v<128, true, ST>(vmode, model, t1, a, nb, s)
+                   : phi_step_v<128, false, ST>(vmode, model, t1, a, nb, s);
     case 256:
-      return walls ? phi_step_v<256, true, ST>(vmode, model, a, nb, s)
-                   : phi_step_v<256, false, ST>(vmode, model, a, nb, s);
+      return walls ? phi_step_v<256, true, ST>(vmode, model, t1, a, nb, s)
+                   : phi_step_v<256, false, ST>(vmode, model, t1, a, nb, s);
+    case 512:
+      return walls ? phi_step_v<512, true, ST>(vmode, model, t1, a, nb, s)
+                   : phi_step_v<512, false, ST>(vmode, model, t1, a, nb, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -456,10 +797,10 @@ bool phi_record_fused(bool walls, int vmode, int model, int storage) {
          (model == 1 || model == 2);
 }
 
-template <int TX>
+template <int TX, bool T1>
 static hipError_t phi_record_t(int vmode, int model, const StepArgs& a, int nb, hipStream_t s) {
 #define LBM_REC_LAUNCH(V, M) \
-  hipLaunchKernelGGL((k_phi_step<TX, false, V, M, ST_F32, true>), dim3(nb), dim3(TX), 0, s, a)
+  hipLaunchKernelGGL((k_phi_step<TX, false, V, M, ST_F32, true, T1>), dim3(nb), dim3(TX), 0, s, a)
   if (vmode == VEL_SEP) {
     if (model == 2) { LBM_REC_LAUNCH(VEL_SEP, 2); } else { LBM_REC_LAUNCH(VEL_SEP, 1); }
   } else {
@@ -469,36 +810,42 @@ static hipError_t phi_record_t(int vmode, int model, const StepArgs& a, int nb, 
   return hipGetLastError();
 }
 
-hipError_t launch_phi_record(int tx, int vmode, int model, const StepArgs& a, int nblocks,
-                             hipStream_t s) {
+hipError_t launch_phi_record(int tx, int vmode, int model, bool t1, const StepArgs& a,
+                             int nblocks, hipStream_t s) {
   if (!phi_record_fused(false, vmode, model, ST_F32) || !a.phi_rec) return hipErrorInvalidValue;
   switch (tx) {
-    case 64: return phi_record_t<64>(vmode, model, a, nblocks, s);
-    case 128: return phi_record_t<128>(vmode, model, a, nblocks, s);
-    case 256: return phi_record_t<256>(vmode, model, a, nblocks, s);
+    case 64: return t1 ? phi_record_t<64, true>(vmode, model, a, nblocks, s)
+                       : phi_record_t<64, false>(vmode, model, a, nblocks, s);
+    case 128: return t1 ? phi_record_t<128, true>(vmode, model, a, nblocks, s)
+                        : phi_record_t<128, false>(vmode, model, a, nblocks, s);
+    case 256: return t1 ? phi_record_t<256, true>(vmode, model, a, nblocks, s)
+                        : phi_record_t<256, false>(vmode, model, a, nblocks, s);
+    case 512: return t1 ? phi_record_t<512, true>(vmode, model, a, nblocks, s)
+                        : phi_record_t<512, false>(vmode, model, a, nblocks, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_phi_step(int tx, bool walls, int vmode, int model, int storage,
+hipError_t launch_phi_step(int tx, bool walls, int vmode, int model, int storage, bool t1,
                            const StepArgs& a, int nblocks, hipStream_t s) {
   switch (storage) {
-    case ST_F32: return phi_step_t<ST_F32>(tx, walls, vmode, model, a, nblocks, s);
-    case ST_F16: return phi_step_t<ST_F16>(tx, walls, vmode, model, a, nblocks, s);
-    case ST_BF16: return phi_step_t<ST_BF16>(tx, walls, vmode, model, a, nblocks, s);
+    case ST_F32: return phi_step_t<ST_F32>(tx, walls, vmode, model, t1, a, nblocks, s);
+    case ST_F16: return phi_step_t<ST_F16>(tx, walls, vmode, model, t1, a, nblocks, s);
+    case ST_BF16: return phi_step_t<ST_BF16>(tx, walls, vmode, model, t1, a, nblocks, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-int phi_batch_blocks_per_cu(int tx, int vmode, bool model2) {
+int phi_batch_blocks_per_cu(int tx, int vmode, bool model2, bool t1) {
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
   const bool sep = vmode == VEL_SEP;
-#define LBM_OCC(T)                                                                            \
-  e = sep ? (model2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phi_batch_persistent<T, VEL_SEP, true>, T, 0)    \
-                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phi_batch_persistent<T, VEL_SEP, false>, T, 0))   \
-          : (model2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phi_batch_persistent<T, VEL_FIELD, true>, T, 0)  \
-                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phi_batch_persistent<T, VEL_FIELD, false>, T, 0))
+#define LBM_OCC1(T, T1)                                                                                                          \
+  e = sep ? (model2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phi_batch_persistent<T, VEL_SEP, true, T1>, T, 0)    \
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phi_batch_persistent<T, VEL_SEP, false, T1>, T, 0))   \
+          : (model2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phi_batch_persistent<T, VEL_FIELD, true, T1>, T, 0)  \
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phi_batch_persistent<T, VEL_FIELD, false, T1>, T, 0))
+#define LBM_OCC(T) if (t1) { LBM_OCC1(T, true); } else { LBM_OCC1(T, false); }
   switch (tx) {
     case 64: LBM_OCC(64); break;
     case 128: LBM_OCC(128); break;
@@ -506,26 +853,29 @@ int phi_batch_blocks_per_cu(int tx, int vmode, bool model2) {
     default: break;
   }
 #undef LBM_OCC
+#undef LBM_OCC1
   return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
-hipError_t launch_phi_batch(int tx, int vmode, bool model2, bool persistent, const BatchArgs& b,
-                            int grid, hipStream_t s) {
-  if (grid <= 0 || (grid & 7) != 0 || b.n <= 0) return hipErrorInvalidValue;
-  if (persistent) {
-    switch (tx) {
-      case 64: return phi_batch_t<64, true>(vmode, model2, b, grid, s);
-      case 128: return phi_batch_t<128, true>(vmode, model2, b, grid, s);
-      case 256: return phi_batch_t<256, true>(vmode, model2, b, grid, s);
-      default: return hipErrorInvalidValue;
-    }
-  }
+template <bool PERSIST, bool T1>
+static hipError_t phi_batch_tx(int tx, int vmode, bool model2, const BatchArgs& b, int grid,
+                               hipStream_t s) {
   switch (tx) {
-    case 64: return phi_batch_t<64, false>(vmode, model2, b, grid, s);
-    case 128: return phi_batch_t<128, false>(vmode, model2, b, grid, s);
-    case 256: return phi_batch_t<256, false>(vmode, model2, b, grid, s);
+    case 64: return phi_batch_t<64, PERSIST, T1>(vmode, model2, b, grid, s);
+    case 128: return phi_batch_t<128, PERSIST, T1>(vmode, model2, b, grid, s);
+    case 256: return phi_batch_t<256, PERSIST, T1>(vmode, model2, b, grid, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_phi_batch(int tx, int vmode, bool model2, bool t1, bool persistent,
+                            const BatchArgs& b, int grid, hipStream_t s) {
+  if (grid <= 0 || (grid & 7) != 0 || b.n <= 0) return hipErrorInvalidValue;
+  if (persistent)
+    return t1 ? phi_batch_tx<true, true>(tx, vmode, model2, b, grid, s)
+              : phi_batch_tx<true, false>(tx, vmode, model2, b, grid, s);
+  return t1 ? phi_batch_tx<false, true>(tx, vmode, model2, b, grid, s)
+            : phi_batch_tx<false, false>(tx, vmode, model2, b, grid, s);
 }
 
 }  // namespace lbmch

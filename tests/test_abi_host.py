@@ -135,9 +135,15 @@ def test_model3_workspace_holds_the_history():
 
 
 def test_missing_library_fails_loudly(tmp_path):
-    """With no built library every call into the package raises: there is no fallback."""
+    """With no built library every call into the package raises: there is no fallback.
+    The package is copied without its built library into a temporary directory."""
+    import shutil
     import subprocess
     import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    shutil.copytree(os.path.join(root, "paper_1805_00007_amd"),
+                    str(tmp_path / "paper_1805_00007_amd"),
+                    ignore=shutil.ignore_patterns("*.so", "__pycache__"))
     code = ("import paper_1805_00007_amd as lbm\n"
             "try:\n"
             "    lbm.lib()\n"
@@ -145,9 +151,7 @@ def test_missing_library_fails_loudly(tmp_path):
             "    print('raised:', e)\n"
             "else:\n"
             "    raise SystemExit('loaded')\n")
-    env = dict(os.environ, LBM_CH_LIB=str(tmp_path / "absent.so"))
-    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    r = subprocess.run([sys.executable, "-c", code], env=env, cwd=root, capture_output=True,
+    r = subprocess.run([sys.executable, "-c", code], cwd=str(tmp_path), capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 0, r.stderr
     assert "raised: liblbm_ch.so is not built" in r.stdout

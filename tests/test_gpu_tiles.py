@@ -48,7 +48,7 @@ def test_ns_results_do_not_depend_on_tiles(lbm):
 def test_set_tiles_rejects_invalid(lbm):
     w = workloads.translation(64, steps=10)
     s = lbm.solver_for(w)
-    for bad in ((512, 16), (32, 4), (128, 0)):
+    for bad in ((1024, 16), (32, 4), (128, 0)):
         with pytest.raises(lbm.LbmChError):
             s.set_tiles(*bad)
     s.set_tiles(64, 1000)
@@ -63,7 +63,7 @@ def test_autotune_restores_state(lbm):
     tiles, us = s.autotune(trial_steps=5)
     print("autotune 256^2 ->", tiles, "%.2f us/step" % us)
     assert s.step_count == 30
-    assert tiles[0] in (64, 128, 256) and tiles[1] in (1, 2, 4, 8, 16, 32) and us > 0
+    assert tiles[0] in (64, 128, 256, 512) and tiles[1] in (1, 2, 4, 8, 16, 32) and us > 0
     s.step(40)
     got = s.phi().cpu().numpy()
     s.close()
@@ -71,10 +71,11 @@ def test_autotune_restores_state(lbm):
     assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("storage,expect", [(0, (256, 32)), (1, (256, 16)), (2, (256, 16))])
+@pytest.mark.parametrize("storage,expect", [(0, (512, 8)), (1, (256, 16)), (2, (256, 16))])
 def test_default_tiles(lbm, storage, expect):
     """Default tile of a 2048^2 lattice: the widest, then tallest, shape with at least 512
-    blocks for float32 populations and 1024 for 16-bit ones."""
+    blocks for float32 populations (1024 for the 512-column tile) and 1024 for 16-bit
+    ones."""
     w = workloads.metric2048(steps=1)
     s = lbm.solver_for(w, storage=storage)
     assert s.tiles == expect
