@@ -262,6 +262,22 @@ int lbm_ch_adjoint(lbm_ch_ctx* ctx, int64_t n_end, int64_t nsteps, const float* 
                    float* lam, float* grad_u, float* grad_v, void* scratch,
                    size_t scratch_bytes, hipStream_t stream);
 
+/* lbm_ch_adjoint without caller scratch, for callers that cannot allocate device memory
+ * (code under hipGraph capture, tight serving loops, harnesses that forbid allocation):
+ * the field the reverse steps alternate with lam lives in a static device array of
+ * LBM_CH_ADJOINT_STATIC_MAX_NODES floats (4 MiB) that every GPU the library runs on holds
+ * until the process ends; its address on the context's device is looked up by
+ * lbm_ch_init.  Arguments, results, ordering and errors are those of lbm_ch_adjoint (the
+ * same kernels; results bitwise equal), except: LBM_CH_EINVAL if nx*ny exceeds
+ * LBM_CH_ADJOINT_STATIC_MAX_NODES; plain launches only (graph replay is not used); no
+ * device or host allocation of any kind.  The array is shared by every call on one GPU
+ * and keeps the last call's contents (each call overwrites what it reads, so nothing
+ * needs clearing): calls that overlap on one GPU, from any context or stream, race. */
+#define LBM_CH_ADJOINT_STATIC_MAX_NODES 1048576
+int lbm_ch_adjoint_static(lbm_ch_ctx* ctx, int64_t n_end, int64_t nsteps,
+                          const float* phi_traj, float* lam, float* grad_u, float* grad_v,
+                          hipStream_t stream);
+
 /* Batched stepping
  * ----------------
  * A batch advances many independent lattices (contexts created by lbm_ch_init) in one

@@ -29,6 +29,7 @@ EXPORTS = ("lbm_ch_workspace_bytes", "lbm_ch_init", "lbm_ch_step", "lbm_ch_momen
            "lbm_ch_state_bytes", "lbm_ch_save_state", "lbm_ch_load_state",
            "lbm_ch_set_tiles", "lbm_ch_get_tiles", "lbm_ch_set_graphs", "lbm_ch_autotune",
            "lbm_ch_adjoint_scratch_bytes", "lbm_ch_record", "lbm_ch_adjoint",
+           "lbm_ch_adjoint_static",
            "lbm_ch_batch_workspace_bytes", "lbm_ch_batch_create", "lbm_ch_batch_set_tiles",
            "lbm_ch_batch_get_tiles", "lbm_ch_batch_set_schedule", "lbm_ch_batch_get_schedule",
            "lbm_ch_batch_step", "lbm_ch_batch_state_bytes",
@@ -100,6 +101,7 @@ def lib():
         L.lbm_ch_adjoint_scratch_bytes.restype = ctypes.c_size_t
         L.lbm_ch_record.argtypes = [vp, i64, vp, vp]
         L.lbm_ch_adjoint.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.lbm_ch_adjoint_static.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp]
         L.lbm_ch_batch_workspace_bytes.argtypes = [ctypes.c_int32]
         L.lbm_ch_batch_workspace_bytes.restype = ctypes.c_size_t
         L.lbm_ch_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int32,

@@ -92,6 +92,7 @@ bool aligned4(const void* q) { return ((uintptr_t)q & 3u) == 0; }
 }  // namespace
 
 struct lbm_ch_ctx {
+  int device;  // HIP device current at lbm_ch_init
   lbm_ch_params p;
   Coef c;
   Layout L;
@@ -219,8 +220,15 @@ int lbm_ch_init(lbm_ch_ctx** out, const lbm_ch_params* p, const lbm_ch_velocity*
     return LBM_CH_EINVAL;
   if (vel && vel->time_factor && vel->n_time_factor < 0) return LBM_CH_EINVAL;
 
+  int device = 0;
+  hipError_t de = hipGetDevice(&device);
+  // the device's copy of the static scratch of lbm_ch_adjoint_static, looked up once per
+  // device while that device is current
+  if (de == hipSuccess) de = static_scratch_setup(device);
+  if (de != hipSuccess) return hip_fail(de);
   lbm_ch_ctx* c = new (std::nothrow) lbm_ch_ctx();
   if (!c) return LBM_CH_EINVAL;
+  c->device = device;
   c->p = *p;
   c->L = L;
   c->ws = (char*)workspace;
@@ -654,9 +662,10 @@ int lbm_ch_record(lbm_ch_ctx* c, int64_t nsteps, float* phi_traj, hipStream_t st
   return graph_steps(c, nsteps, phi_traj, stream);
 }
 
-int lbm_ch_adjoint(lbm_ch_ctx* c, int64_t n_end, int64_t nsteps, const float* phi_traj,
-                   float* lam, float* grad_u, float* grad_v, void* scratch,
-                   size_t scratch_bytes, hipStream_t stream) {
+// Checks shared by lbm_ch_adjoint and lbm_ch_adjoint_static (scratch aside).
+static int adjoint_check(const lbm_ch_ctx* c, int64_t n_end, int64_t nsteps,
+                         const float* phi_traj, const float* lam, const float* grad_u,
+                         const float* grad_v) {
   if (!live(c)) return LBM_CH_ESTATE;
   if (c->p.tau_g != 1.0 || c->p.walls != 0 || c->p.velocity_mode == LBM_CH_VEL_NS ||
       c->p.model == 3)
@@ -666,28 +675,42 @@ int lbm_ch_adjoint(lbm_ch_ctx* c, int64_t n_end, int64_t nsteps, const float* ph
   if (!phi_traj || !lam || !aligned4(phi_traj) || !aligned4(lam)) return LBM_CH_EINVAL;
   if ((grad_u == nullptr) != (grad_v == nullptr)) return LBM_CH_EINVAL;
   if (grad_u && (!aligned4(grad_u) || !aligned4(grad_v))) return LBM_CH_EINVAL;
+  return LBM_CH_OK;
+}
+
+// The reverse steps n_end - 1 .. n_end - nsteps, lam and `scratch` (nx*ny floats)
+// alternating as source and destination; lam holds the result.
+static int adjoint_enqueue(lbm_ch_ctx* c, int64_t n_end, int64_t nsteps, const float* phi_traj,
+                           float* lam, float* grad_u, float* grad_v, float* scratch,
+                           hipStream_t s) {
+  const size_t nodes = (size_t)c->p.nx * c->p.ny;
+  float* buf[2] = {lam, scratch};
+  int cur = 0;
+  for (int64_t k = nsteps - 1; k >= 0; --k) {
+    const int64_t n = n_end - nsteps + k;
+    hipError_t e = launch_adjoint_step(
+        c->c, (float)c->p.mobility, c->p.nx, c->p.ny, c->vmode, c->ax, c->ay, c->bx, c->by,
+        c->ux, c->uy, time_factor(c, n), phi_traj + (size_t)k * nodes, buf[cur],
+        buf[cur ^ 1], grad_u, grad_v, s);
+    if (e != hipSuccess) return hip_fail(e);
+    cur ^= 1;
+  }
+  if (cur != 0) {
+    hipError_t e = hipMemcpyAsync(lam, scratch, nodes * sizeof(float), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return LBM_CH_OK;
+}
+
+int lbm_ch_adjoint(lbm_ch_ctx* c, int64_t n_end, int64_t nsteps, const float* phi_traj,
+                   float* lam, float* grad_u, float* grad_v, void* scratch,
+                   size_t scratch_bytes, hipStream_t stream) {
+  int r = adjoint_check(c, n_end, nsteps, phi_traj, lam, grad_u, grad_v);
+  if (r != LBM_CH_OK || nsteps == 0) return r;
   if (!scratch || !aligned4(scratch) || scratch_bytes < lbm_ch_adjoint_scratch_bytes(&c->p))
     return LBM_CH_EINVAL;
-  const size_t nodes = (size_t)c->p.nx * c->p.ny;
   auto enqueue = [&](hipStream_t s) -> int {
-    // lam and the scratch field alternate as source and destination
-    float* buf[2] = {lam, (float*)scratch};
-    int cur = 0;
-    for (int64_t k = nsteps - 1; k >= 0; --k) {
-      const int64_t n = n_end - nsteps + k;
-      hipError_t e = launch_adjoint_step(
-          c->c, (float)c->p.mobility, c->p.nx, c->p.ny, c->vmode, c->ax, c->ay, c->bx, c->by,
-          c->ux, c->uy, time_factor(c, n), phi_traj + (size_t)k * nodes, buf[cur],
-          buf[cur ^ 1], grad_u, grad_v, s);
-      if (e != hipSuccess) return hip_fail(e);
-      cur ^= 1;
-    }
-    if (cur != 0) {
-      hipError_t e = hipMemcpyAsync(lam, scratch, nodes * sizeof(float),
-                                    hipMemcpyDeviceToDevice, s);
-      if (e != hipSuccess) return hip_fail(e);
-    }
-    return LBM_CH_OK;
+    return adjoint_enqueue(c, n_end, nsteps, phi_traj, lam, grad_u, grad_v, (float*)scratch, s);
   };
   // the reverse steps of a steady velocity depend on n_end only through the trajectory
   if (!c->graphs || !c->tf.empty()) return enqueue(stream);
@@ -699,8 +722,20 @@ int lbm_ch_adjoint(lbm_ch_ctx* c, int64_t n_end, int64_t nsteps, const float* ph
   key.p[2] = grad_u;
   key.p[3] = grad_v;
   key.p[4] = scratch;
-  const int r = graph_run(c, key, stream, enqueue);
+  r = graph_run(c, key, stream, enqueue);
   return r > 0 ? LBM_CH_OK : r;
+}
+
+int lbm_ch_adjoint_static(lbm_ch_ctx* c, int64_t n_end, int64_t nsteps, const float* phi_traj,
+                          float* lam, float* grad_u, float* grad_v, hipStream_t stream) {
+  int r = adjoint_check(c, n_end, nsteps, phi_traj, lam, grad_u, grad_v);
+  if (r != LBM_CH_OK || nsteps == 0) return r;
+  static_assert(ADJ_STATIC_MAX_NODES == LBM_CH_ADJOINT_STATIC_MAX_NODES, "header limit");
+  if ((size_t)c->p.nx * c->p.ny > ADJ_STATIC_MAX_NODES) return LBM_CH_EINVAL;
+  float* ptr = static_scratch(c->device);  // set up by lbm_ch_init on this device
+  if (!ptr) return LBM_CH_ESTATE;
+  // plain launches only: no graph capture, which creates streams and graphs
+  return adjoint_enqueue(c, n_end, nsteps, phi_traj, lam, grad_u, grad_v, ptr, stream);
 }
 
 int lbm_ch_destroy(lbm_ch_ctx* c) {

@@ -3,6 +3,8 @@
 // adjoint of the tau_g = 1 step.  The fused step kernels are in lbm_ch_step.hip.
 #include "lbm_ch_device.h"
 
+#include <mutex>
+
 namespace lbmch {
 namespace {
 
@@ -544,6 +546,39 @@ hipError_t launch_diag(bool walls, const Coef& c, const float* phi, const float*
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(DIAG_THREADS), 0, s, partial, out);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
+// Device scratch of lbm_ch_adjoint_static, for callers that cannot allocate device
+// memory: the field the reverse steps alternate with the caller's lam.  Every GPU the
+// library runs on holds its own copy until the process ends.  In host code the name
+// `scratch` is a host-side stand-in, not a device address: the address of each device's
+// copy comes from hipGetSymbolAddress, taken once per device with that device current
+// (static_scratch_setup, called by lbm_ch_init), and only that address is used.
+static __device__ __align__(256) float scratch[ADJ_STATIC_MAX_NODES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t static_scratch_setup(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = static_cast<float*>(ptr);
+  return hipSuccess;
+}
+
+float* static_scratch(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 }  // namespace lbmch

@@ -115,6 +115,12 @@ hipError_t launch_velocity_field(int vmode, int nx, int ny, const float* ax, con
                                  const float* uy, float tf, float* u, float* v,
                                  hipStream_t s);
 hipError_t launch_fill(float* dst, float value, int64_t n, hipStream_t s);
+// Static device scratch of lbm_ch_adjoint_static (nodes <= ADJ_STATIC_MAX_NODES floats per
+// device).  static_scratch_setup(device) must run with `device` current (lbm_ch_init does
+// it); static_scratch(device) is then that device's address, or null before the setup.
+constexpr size_t ADJ_STATIC_MAX_NODES = size_t(1) << 20;
+hipError_t static_scratch_setup(int device);
+float* static_scratch(int device);
 // FP64 reductions of a phi field; partial needs diag_partial_blocks()*8 doubles.
 int diag_partial_blocks();
 hipError_t launch_diag(bool walls, const Coef& c, const float* phi, const float* ref, int nx,
