@@ -48,7 +48,8 @@
  * and every device array it passes to lbm_ch_init, alive until lbm_ch_destroy.
  * Device arrays are float32, row-major (index y*nx + x), unless stated.  Host
  * arrays are copied during the call.  The context itself is host memory owned by
- * the library.  A batch (lbm_ch_batch_create) and a context's first graph capture
+ * the library, with 4 bytes of pinned host memory for its non-finite flag (see
+ * lbm_ch_step).  A batch (lbm_ch_batch_create) and a context's first graph capture
  * (lbm_ch_set_graphs) create a capture stream, and graph replay instantiates graphs;
  * the HIP runtime holds these until the batch or context is destroyed (or, for a
  * context, its graphs are dropped).
@@ -150,7 +151,14 @@ int lbm_ch_init(lbm_ch_ctx** out, const lbm_ch_params* p, const lbm_ch_velocity*
                 hipStream_t stream);
 
 /* Enqueue nsteps >= 0 time steps (Eq. LB plus streaming; with NS also the coupled
- * NS step) on `stream`.  The step counter n advances by nsteps. */
+ * NS step) on `stream`.  The step counter n advances by nsteps.  Non-finite values:
+ * every step kernel raises a flag of the context when a phi it sums from the
+ * populations is NaN or Inf; the flag lives in 4 bytes of pinned host memory mapped
+ * into the device (allocated by lbm_ch_init, freed by lbm_ch_destroy), so it lands on
+ * the host without any copy or synchronisation.  Once it has landed, this call (and
+ * lbm_ch_record, lbm_ch_batch_step for a batch holding the context) returns
+ * LBM_CH_ENONFINITE and enqueues nothing; lbm_ch_load_state clears it.  A flag raised
+ * by steps still in flight is reported by a later call (lbm_ch_check_finite waits). */
 int lbm_ch_step(lbm_ch_ctx* ctx, int64_t nsteps, hipStream_t stream);
 
 /* Enqueue the macroscopic fields of the current state into caller device arrays of

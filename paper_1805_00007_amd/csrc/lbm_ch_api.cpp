@@ -93,6 +93,10 @@ bool aligned4(const void* q) { return ((uintptr_t)q & 3u) == 0; }
 
 struct lbm_ch_ctx {
   int device;  // HIP device current at lbm_ch_init
+  // non-finite flag: pinned host memory mapped into the device, set by the step kernels
+  // when a phi they sum is NaN or Inf, read by the next lbm_ch_step / lbm_ch_record
+  int* nf_host;
+  int* nf_dev;
   lbm_ch_params p;
   Coef c;
   Layout L;
@@ -226,9 +230,23 @@ int lbm_ch_init(lbm_ch_ctx** out, const lbm_ch_params* p, const lbm_ch_velocity*
   // device while that device is current
   if (de == hipSuccess) de = static_scratch_setup(device);
   if (de != hipSuccess) return hip_fail(de);
+  int* nf_host = nullptr;
+  int* nf_dev = nullptr;
+  de = hipHostMalloc((void**)&nf_host, sizeof(int), hipHostMallocMapped);
+  if (de == hipSuccess) de = hipHostGetDevicePointer((void**)&nf_dev, nf_host, 0);
+  if (de != hipSuccess) {
+    if (nf_host) (void)hipHostFree(nf_host);
+    return hip_fail(de);
+  }
+  *nf_host = 0;
   lbm_ch_ctx* c = new (std::nothrow) lbm_ch_ctx();
-  if (!c) return LBM_CH_EINVAL;
+  if (!c) {
+    (void)hipHostFree(nf_host);
+    return LBM_CH_EINVAL;
+  }
   c->device = device;
+  c->nf_host = nf_host;
+  c->nf_dev = nf_dev;
   c->p = *p;
   c->L = L;
   c->ws = (char*)workspace;
@@ -310,6 +328,7 @@ int lbm_ch_init(lbm_ch_ctx** out, const lbm_ch_params* p, const lbm_ch_velocity*
                     c->f[0], stream);
   if (e != hipSuccess) {
     c->magic = 0;
+    (void)hipHostFree(c->nf_host);
     delete c;
     return hip_fail(e);
   }
@@ -335,6 +354,7 @@ static int run_steps(lbm_ch_ctx* c, int64_t nsteps, float* phi_out, hipStream_t 
   a.c = c->c;
   a.ax = c->ax; a.ay = c->ay; a.bx = c->bx; a.by = c->by;
   a.ux = c->ux; a.uy = c->uy;
+  a.nonfinite = c->nf_dev;
   NsArgs n{};
   if (ns) {
     n.pitch = c->L.pitch;
@@ -467,9 +487,16 @@ static int graph_steps(lbm_ch_ctx* c, int64_t nsteps, float* phi_out, hipStream_
 }
 }  // extern "C++"
 
+// The non-finite flag as the host sees it now (it lands some time after the kernel that
+// set it; nothing here waits for the device).
+static bool nonfinite_seen(const lbm_ch_ctx* c) {
+  return __atomic_load_n(c->nf_host, __ATOMIC_ACQUIRE) != 0;
+}
+
 int lbm_ch_step(lbm_ch_ctx* c, int64_t nsteps, hipStream_t stream) {
   if (!live(c)) return LBM_CH_ESTATE;
   if (nsteps < 0) return LBM_CH_EINVAL;
+  if (nonfinite_seen(c)) return LBM_CH_ENONFINITE;
   return graph_steps(c, nsteps, nullptr, stream);
 }
 
@@ -571,6 +598,7 @@ int lbm_ch_load_state(lbm_ch_ctx* c, const void* src, size_t bytes, int64_t step
                       hipStream_t stream) {
   if (!live(c)) return LBM_CH_ESTATE;
   if (!src || bytes != lbm_ch_state_bytes(c) || step < 0) return LBM_CH_EINVAL;
+  __atomic_store_n(c->nf_host, 0, __ATOMIC_RELEASE);  // a new state: forget earlier NaNs
   const size_t g = c->L.g_state, f = c->L.f_state;
   const size_t fo = c->f[0] ? f : 0, x = (size_t)2 * c->p.nx * c->p.ny * sizeof(float);
   hipError_t e = hipMemcpyAsync(c->g[c->cur], src, g, hipMemcpyDeviceToDevice, stream);
@@ -657,6 +685,7 @@ size_t lbm_ch_adjoint_scratch_bytes(const lbm_ch_params* p) {
 int lbm_ch_record(lbm_ch_ctx* c, int64_t nsteps, float* phi_traj, hipStream_t stream) {
   if (!live(c)) return LBM_CH_ESTATE;
   if (nsteps < 0) return LBM_CH_EINVAL;
+  if (nonfinite_seen(c)) return LBM_CH_ENONFINITE;
   if (nsteps == 0) return LBM_CH_OK;
   if (!phi_traj || !aligned4(phi_traj)) return LBM_CH_EINVAL;
   return graph_steps(c, nsteps, phi_traj, stream);
@@ -743,6 +772,7 @@ int lbm_ch_destroy(lbm_ch_ctx* c) {
   if (!live(c)) return LBM_CH_ESTATE;
   drop_graphs(c);
   if (c->cap) (void)hipStreamDestroy(c->cap);
+  (void)hipHostFree(c->nf_host);
   c->magic = 0;
   delete c;
   return LBM_CH_OK;
@@ -882,6 +912,7 @@ static int batch_build(lbm_ch_batch* b, hipStream_t stream) {
     a.ax = c->ax; a.ay = c->ay; a.bx = c->bx; a.by = c->by;
     a.ux = c->ux; a.uy = c->uy;
     a.tf = time_factor(c, c->step);
+    a.nonfinite = c->nf_dev;
     b->built_cur[i] = c->cur;
     b->hstart.push_back(g.total);
     g.total += a.nstrips * ((c->p.ny + ty - 1) / ty);
@@ -1025,6 +1056,8 @@ int lbm_ch_batch_get_tiles(const lbm_ch_batch* b, int32_t* tx, int32_t* ty) {
 int lbm_ch_batch_step(lbm_ch_batch* b, int64_t nsteps, int32_t use_graph, hipStream_t stream) {
   if (!batch_live(b)) return LBM_CH_ESTATE;
   if (nsteps < 0) return LBM_CH_EINVAL;
+  for (const lbm_ch_ctx* m : b->ctx)
+    if (live(m) && nonfinite_seen(m)) return LBM_CH_ENONFINITE;
   int r = batch_prepare(b, stream);
   if (r != LBM_CH_OK || nsteps == 0) return r;
   if (!use_graph) {

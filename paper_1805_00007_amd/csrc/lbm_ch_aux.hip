@@ -162,11 +162,62 @@ __global__ void __launch_bounds__(256) k_fill(float* d, float value, int64_t n) 
 }
 
 // ---------------------------------------------------------------------------------
-// FP64 diagnostics: a fixed grid of blocks, each thread a fixed strided set of nodes,
-// then a fixed-order tree in LDS and one final block: bitwise reproducible.
+// FP64 diagnostics: a fixed grid of blocks, each thread a fixed strided set of nodes;
+// each wavefront reduces its 64 lanes with cross-lane DPP moves (xor 1, xor 2 within
+// quads, then the mirrors of 8 and 16 lanes, which leave every lane of a row of 16 with
+// the row's value) and combines its four rows through readlane; the four wavefronts
+// of a block meet in LDS, and one final block reduces the block partials the same way.
+// Every combination happens in a fixed order: bitwise reproducible.
 constexpr int DIAG_BLOCKS = 512;
 constexpr int DIAG_THREADS = 256;
+constexpr int DIAG_WAVES = DIAG_THREADS / 64;
 constexpr int NDIAG = 8;
+
+// Reduction operator of diagnostic q: sums, except the maximum (q = 5) and minimum (6).
+__device__ __forceinline__ double diag_op(int q, double a, double b) {
+  return q == 5 ? fmax(a, b) : (q == 6 ? fmin(a, b) : a + b);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+// Value of diagnostic q over the 64 lanes of the calling wavefront (all lanes active).
+__device__ __forceinline__ double wave_reduce(int q, double v) {
+  v = diag_op(q, v, dpp_d<0xB1>(v));   // quad_perm [1, 0, 3, 2]
+  v = diag_op(q, v, dpp_d<0x4E>(v));   // quad_perm [2, 3, 0, 1]
+  v = diag_op(q, v, dpp_d<0x141>(v));  // row_half_mirror
+  v = diag_op(q, v, dpp_d<0x140>(v));  // row_mirror
+  return diag_op(q, diag_op(q, readlane_d(v, 0), readlane_d(v, 16)),
+                 diag_op(q, readlane_d(v, 32), readlane_d(v, 48)));
+}
+// Block reduction of acc[NDIAG] (every thread of a DIAG_THREADS block calls it): the
+// result is in threads 0 .. NDIAG-1 (thread q holds diagnostic q).
+__device__ __forceinline__ double block_reduce(double acc[NDIAG], double (*sh)[DIAG_WAVES]) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < NDIAG; ++q) {
+    const double w = wave_reduce(q, acc[q]);
+    if (lane == 0) sh[q][wave] = w;
+  }
+  __syncthreads();
+  double r = 0.0;
+  if ((int)threadIdx.x < NDIAG) {
+    const int q = threadIdx.x;
+    r = sh[q][0];
+#pragma unroll
+    for (int w = 1; w < DIAG_WAVES; ++w) r = diag_op(q, r, sh[q][w]);
+  }
+  return r;
+}
 
 template <bool WALLS>
 __global__ void __launch_bounds__(DIAG_THREADS) k_diag_partial(const Coef c,
@@ -174,7 +225,7 @@ __global__ void __launch_bounds__(DIAG_THREADS) k_diag_partial(const Coef c,
                                                                const float* __restrict__ ref,
                                                                int nx, int ny,
                                                                double* __restrict__ part) {
-  __shared__ double sh[NDIAG][DIAG_THREADS];
+  __shared__ double sh[NDIAG][DIAG_WAVES];
   double acc[NDIAG] = {0, 0, 0, 0, 0, -INFINITY, INFINITY, 0};
   const int64_t n = (int64_t)nx * ny;
   for (int64_t k = (int64_t)blockIdx.x * DIAG_THREADS + threadIdx.x; k < n;
@@ -202,49 +253,23 @@ __global__ void __launch_bounds__(DIAG_THREADS) k_diag_partial(const Coef c,
     acc[5] = fmax(acc[5], v);
     acc[6] = fmin(acc[6], v);
   }
-#pragma unroll
-  for (int q = 0; q < NDIAG; ++q) sh[q][threadIdx.x] = acc[q];
-  __syncthreads();
-  for (int s = DIAG_THREADS / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-#pragma unroll
-      for (int q = 0; q < NDIAG; ++q) {
-        const double o = sh[q][threadIdx.x + s];
-        double& m = sh[q][threadIdx.x];
-        m = q == 5 ? fmax(m, o) : (q == 6 ? fmin(m, o) : m + o);
-      }
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x < NDIAG) part[blockIdx.x * NDIAG + threadIdx.x] = sh[threadIdx.x][0];
+  const double r = block_reduce(acc, sh);
+  if (threadIdx.x < NDIAG) part[blockIdx.x * NDIAG + threadIdx.x] = r;
 }
 
 __global__ void __launch_bounds__(DIAG_THREADS) k_diag_final(const double* __restrict__ part,
                                                              double* __restrict__ out) {
-  __shared__ double sh[NDIAG][DIAG_THREADS];
+  __shared__ double sh[NDIAG][DIAG_WAVES];
   double acc[NDIAG] = {0, 0, 0, 0, 0, -INFINITY, INFINITY, 0};
   for (int b = threadIdx.x; b < DIAG_BLOCKS; b += DIAG_THREADS) {
 #pragma unroll
     for (int q = 0; q < NDIAG; ++q) {
       const double o = part[b * NDIAG + q];
-      acc[q] = q == 5 ? fmax(acc[q], o) : (q == 6 ? fmin(acc[q], o) : acc[q] + o);
+      acc[q] = diag_op(q, acc[q], o);
     }
   }
-#pragma unroll
-  for (int q = 0; q < NDIAG; ++q) sh[q][threadIdx.x] = acc[q];
-  __syncthreads();
-  for (int s = DIAG_THREADS / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-#pragma unroll
-      for (int q = 0; q < NDIAG; ++q) {
-        const double o = sh[q][threadIdx.x + s];
-        double& m = sh[q][threadIdx.x];
-        m = q == 5 ? fmax(m, o) : (q == 6 ? fmin(m, o) : m + o);
-      }
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x < NDIAG) out[threadIdx.x] = sh[threadIdx.x][0];
+  const double r = block_reduce(acc, sh);
+  if (threadIdx.x < NDIAG) out[threadIdx.x] = r;
 }
 
 // ---------------------------------------------------------------------------------

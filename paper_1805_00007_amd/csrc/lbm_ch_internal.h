@@ -46,6 +46,7 @@ struct StepArgs {
   float* xh;          // model 3: X of the previous step (2 planes of nx*ny), rewritten
   int xfirst;         // model 3: 1 on the first step (no earlier X: zero difference)
   float* phi_rec;     // launch_phi_record only: phi of the source state (nx*ny), written
+  int* nonfinite;     // set to 1 when a phi summed in stage 1 is NaN or Inf (may be null)
 };
 
 // Arguments of the batched step: one StepArgs per instance (src/dst as at parity 0),

@@ -151,6 +151,7 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
     float sg;
     row_of<WALLS>(r, ny, sg);
     R.phi = sum9(R.g, R.lo);
+    if (__builtin_expect(!__builtin_isfinite(R.phi), 0) && a.nonfinite) *a.nonfinite = 1;
     float u, v;
     if (VMODE == VEL_SEP) {
       R.fy_u *= a.tf * sg;
@@ -468,6 +469,7 @@ __device__ __forceinline__ void phi_tile_t1(const StepArgs& a, const int L) {
     float sg;
     row_of<WALLS>(r, ny, sg);
     R.phi = sum9(P.g, R.lo);
+    if (__builtin_expect(!__builtin_isfinite(R.phi), 0) && a.nonfinite) *a.nonfinite = 1;
     const float f = a.tf * sg;
     float u, v;
     if (VMODE == VEL_SEP) {

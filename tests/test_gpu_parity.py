@@ -168,8 +168,14 @@ def test_diagnostics_match_oracle(lbm):
 
 def test_nonfinite_is_reported(lbm):
     """A NaN in the initial field spreads through the stencils; the FP64 diagnostics
-    count the non-finite nodes and lbm_ch_check_finite reports LBM_CH_ENONFINITE."""
+    count the non-finite nodes and lbm_ch_check_finite reports LBM_CH_ENONFINITE.  The
+    step kernels also raise the context's flag, so once it has landed (check_finite
+    waited for the stream) lbm_ch_step itself returns LBM_CH_ENONFINITE and enqueues
+    nothing, until a finite state is loaded."""
     w = workloads.vortex(64, period=400, steps=20)
+    good = lbm.Solver(64, 64, w.phi0, velocity=w.velocity, **w.phys)
+    ckpt, n0 = good.save_state()
+    good.close()
     phi0 = np.array(w.phi0, dtype=np.float64)
     phi0[20, 30] = np.nan
     s = lbm.Solver(64, 64, phi0, velocity=w.velocity, **w.phys).step(5)
@@ -177,6 +183,13 @@ def test_nonfinite_is_reported(lbm):
     print("non-finite nodes after 5 steps:", d["nonfinite"])
     assert d["nonfinite"] > 1
     assert s.check_finite() == lbm.ENONFINITE
+    with pytest.raises(lbm.LbmChError) as err:
+        s.step(1)
+    assert err.value.status == lbm.ENONFINITE
+    assert s.step_count == 5
+    s.load_state(ckpt, n0).step(3)
+    assert s.check_finite() == lbm.OK
+    assert s.step_count == 3
     s.close()
 
 
