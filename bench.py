@@ -65,11 +65,24 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(w, steps):
+def cpu_model():
+    """CPU model name of the host (first 'model name' line of /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_mlups(w, steps, threads=None):
     import numpy as np
     import oracle
     import workloads
     oracle.build(force=False)
+    if threads is not None:
+        oracle.set_num_threads(threads)
     p = oracle.Params(nx=w.nx, ny=w.ny, **w.phys)
     U, V = workloads.separable_field(w.velocity)
     s = oracle.State(p, w.phi0, U, V, w.velocity["tf"])
@@ -77,10 +90,39 @@ def cpu_baseline(w, steps):
     s.run(steps)
     dt = time.perf_counter() - t0
     assert np.isfinite(s.g).all()
-    return {"value": round(w.nx * w.ny * steps / dt / 1e6, 3), "unit": "MLUPS",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "%d steps of the %dx%d workload (FP64, OpenMP over rows), %.1f s"
-                      % (steps, w.nx, w.ny, dt)}
+    return w.nx * w.ny * steps / dt / 1e6, dt, oracle.num_threads()
+
+
+def cpu_baseline(steps):
+    """The FP64 oracle on the host cores: the 2048^2 workload on a bounded number of steps
+    with every thread (the reported value), the same with one thread, the 128^2
+    translation (3200 steps, one period) in full, and the 512^2 vortex on a sample of
+    its 20000 steps (time extrapolated to the full run)."""
+    import oracle
+    import workloads
+    oracle.build(force=False)
+    nthreads = oracle.num_threads()
+    v, dt, cores = _oracle_mlups(workloads.metric2048(steps=steps), steps)
+    out = {"value": round(v, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+           "sample": "%d steps of the 2048x2048 workload (FP64, OpenMP over rows), %.1f s"
+                     % (steps, dt),
+           "cpu_model": cpu_model(), "host_threads": os.cpu_count()}
+    one_steps = max(2, steps // 40)
+    v1, dt1, _ = _oracle_mlups(workloads.metric2048(steps=one_steps), one_steps, threads=1)
+    out["one_thread"] = {"value": round(v1, 3), "unit": "MLUPS",
+                         "sample": "%d steps of the 2048x2048 workload, %.1f s" % (one_steps, dt1)}
+    oracle.set_num_threads(nthreads)
+    w1 = workloads.translation(128, steps=3200)
+    v1, dt1, _ = _oracle_mlups(w1, 3200)
+    out["translation128_full"] = {"value": round(v1, 3), "unit": "MLUPS", "steps": 3200,
+                                  "seconds": round(dt1, 2)}
+    n2 = 2000
+    w2 = workloads.vortex(512, period=20000, steps=n2)
+    v2, dt2, _ = _oracle_mlups(w2, n2)
+    out["vortex512_sample"] = {"value": round(v2, 3), "unit": "MLUPS", "steps": n2,
+                               "seconds": round(dt2, 2),
+                               "full_run_20000_steps_s_extrapolated": round(dt2 * 20000 / n2, 1)}
+    return out
 
 
 def accuracy(lbm, w, torch):
@@ -102,11 +144,22 @@ def accuracy(lbm, w, torch):
             "max_abs_err": float(np.abs(phi[idx] - ref).max()), "mass_drift": drift}
 
 
+def roofline(bytes_per_lu, nodes, us, kernel, profile):
+    """Roofline sub-object of a leg: algorithmic bytes of one launch over its duration,
+    against the 8 TB/s HBM peak."""
+    achieved = bytes_per_lu * nodes / (us * 1e-6) / 1e9
+    return {"bound": "hbm", "bytes_per_lu": bytes_per_lu, "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "kernel": kernel, "kernel_avg_us": round(us, 2), "profile": profile}
+
+
 def storage_variant(lbm, torch, storage, steps):
     """Same workload with 16-bit population storage (20 B per node update instead of 36
-    read and 36 written): throughput and phi at the stored 1000-step oracle samples."""
+    read and 36 written): throughput over at least 500 steps, and phi at the stored
+    1000-step oracle samples."""
     import numpy as np
     import workloads
+    steps = max(steps, 500)
     w = workloads.metric2048(steps=steps + 1100)
     s = lbm.solver_for(w, storage=storage)
     s.step(50)
@@ -119,7 +172,10 @@ def storage_variant(lbm, torch, storage, steps):
     ms = e0.elapsed_time(e1) / steps
     s.close()
     out = {"MLUPS": round(w.nx * w.ny / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 5),
-           "bytes_per_lu": 40, "effective_GBps": round(w.nx * w.ny * 40 / (ms * 1e-3) / 1e9, 1)}
+           "timed_steps": steps, "bytes_per_lu": 40,
+           "effective_GBps": round(w.nx * w.ny * 40 / (ms * 1e-3) / 1e9, 1),
+           "roofline": roofline(40, w.nx * w.ny, ms * 1e3, "k_phi_step (16-bit storage)",
+                                "profiles/phi_step_vortex2048_16bit_kernel_trace.md")}
     if os.path.exists(GOLDEN):
         g = np.load(GOLDEN)
         s = lbm.solver_for(workloads.metric2048(steps=1000), storage=storage)
@@ -213,6 +269,25 @@ def adjoint_leg(lbm, torch, reps=3):
     t_serial = min(r[0] for r in serial)
     same_serial = bool(np.array_equal(serial[0][2], runs[0][2])
                        and np.array_equal(serial[0][3], runs[0][3]))
+    # the reverse-step kernel alone: lbm_ch_adjoint over a stored trajectory of `nrev`
+    # steps (one launch of k_adjoint per step), timed with events on its stream
+    nrev = 200
+    s = lbm.Solver(case.n, case.n, case.phi0, field=(U, V), device=dev, **case.phys)
+    s.set_tiles(*tiles)
+    traj = torch.empty((nrev, case.n, case.n), dtype=torch.float32, device=dev)
+    s.record(nrev, traj)
+    lam = torch.ones((case.n, case.n), dtype=torch.float32, device=dev)
+    gu, gv = torch.zeros_like(lam), torch.zeros_like(lam)
+    scratch = torch.empty(case.n * case.n, dtype=torch.float32, device=dev)
+    s.adjoint(nrev, nrev, traj, lam, gu, gv, scratch)  # untimed
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s.stream)
+    s.adjoint(nrev, nrev, traj, lam, gu, gv, scratch)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    rev_us = e0.elapsed_time(e1) * 1e3 / nrev
+    s.close()
     _, loss, gt, gp = runs[0]
     ref_t, ref_p = g["grad_theta"], g["grad_phi0"]
     return {"workload": "adjoint256: 256^2, %d steps, 16 stream-function coefficients" % steps,
@@ -233,7 +308,12 @@ def adjoint_leg(lbm, torch, reps=3):
             "grad_theta_rel_err": float(np.linalg.norm(gt - ref_t) / np.linalg.norm(ref_t)),
             "grad_phi0_rel_err": float(np.linalg.norm(gp.ravel()[g["phi0_index"]] - ref_p)
                                        / np.linalg.norm(ref_p)),
-            "reference": "FP64 oracle central differences, h = %g" % float(g["h"])}
+            "reference": "FP64 oracle central differences, h = %g" % float(g["h"]),
+            # one reverse step per launch: phi^n and lam^{n+1} read, lam^n written, the two
+            # velocity gradients read and written: 28 B per node
+            "reverse_step_us": round(rev_us, 2),
+            "roofline": roofline(28, case.n * case.n, rev_us, "k_adjoint (one reverse step)",
+                                 "profiles/adjoint_adjoint256_kernel_trace.md")}
 
 
 def rt_leg(lbm, torch, steps=500, warm=50):
@@ -261,7 +341,10 @@ def rt_leg(lbm, torch, steps=500, warm=50):
         out[name] = {"MLUPS": round(lu / 1e6, 1), "us_per_step": round(ms * 1e3, 2),
                      "bytes_per_lu": bytes_lu,
                      "effective_GBps": round(lu * bytes_lu / 1e9, 1),
-                     "nonfinite": int(d["nonfinite"])}
+                     "nonfinite": int(d["nonfinite"]),
+                     "roofline": roofline(bytes_lu, w.nx * w.ny, ms * 1e3,
+                                          "coupled step (per step, all its launches)",
+                                          "profiles/ns_step_rt256x1024_kernel_trace.md")}
     return out
 
 
@@ -321,7 +404,9 @@ def batch_leg(lbm, torch, steps=5000, plain_steps=200, check_steps=100):
                                 "schedule": "persistent" if persistent else "tile per workgroup"},
             "bitwise_equal_to_plain_after_%d" % check_steps: bool(same),
             "nonfinite": int(nonfinite),
-            "bytes_per_lu": 80}
+            "bytes_per_lu": 80,
+            "roofline": roofline(80, nodes, t_batch * 1e6, "k_phi_batch (all 64 lattices)",
+                                 "profiles/phi_batch_batch64_kernel_trace.md")}
 
 
 def main():
@@ -439,8 +524,7 @@ def main():
         out["rayleigh_taylor"] = rt_leg(lbm, torch)
         out["batched"] = batch_leg(lbm, torch)
     if args.cpu_steps > 0:
-        out["cpu_baseline"] = cpu_baseline(workloads.metric2048(steps=args.cpu_steps),
-                                           args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(out), flush=True)
 
 

@@ -79,8 +79,8 @@ enum VelMode { VEL_SEP = 0, VEL_FIELD = 1, VEL_NSFIELD = 2 };
 uint32_t population_bytes(int storage, uint32_t pitch, uint32_t ny);
 
 // Launchers (return hipGetLastError() of the launch).
-// t1: tau_g = 1 (omega = 1), which selects the reduced tile for float32 storage, models
-// 1 and 2 and a prescribed velocity (other cases ignore it).
+// t1: tau_g = 1 (omega = 1), which selects the reduced tile for models 1 and 2 with a
+// prescribed velocity (other cases ignore it).
 hipError_t launch_phi_step(int tx, bool walls, int vmode, int model, int storage, bool t1,
                            const StepArgs& a, int nblocks, hipStream_t s);
 // The same step that also writes phi of the source state to a.phi_rec (the sums stage 1

@@ -317,7 +317,7 @@ __device__ __forceinline__ void phi_tile(const StepArgs& a, const int L) {
 }
 
 // ---------------------------------------------------------------------------------
-// Fused step at tau_g = 1 (float32 storage, models 1 and 2, prescribed velocity).
+// Fused step at tau_g = 1 (models 1 and 2, prescribed velocity; any storage).
 //
 // With omega = 1 the collision of Eq. LB forgets the pulled populations: g_i* =
 // g_i^eq + S_i / 2, so once a row has been pulled and summed its record keeps only
@@ -389,7 +389,7 @@ __device__ __forceinline__ void collide_t1(const Coef& c, float phi, float mu, f
   pair(v - u, hy - hx, WT[6], g[6], g[8]);
 }
 
-template <int TX, bool WALLS, int VMODE, int MODEL, bool REC = false>
+template <int TX, bool WALLS, int VMODE, int MODEL, int ST, bool REC = false>
 __device__ __forceinline__ void phi_tile_t1(const StepArgs& a, const int L) {
   static_assert(VMODE == VEL_SEP || VMODE == VEL_FIELD, "prescribed velocity only");
   static_assert(MODEL == 1 || MODEL == 2, "models 1 and 2");
@@ -408,8 +408,8 @@ __device__ __forceinline__ void phi_tile_t1(const StepArgs& a, const int L) {
   const uint32_t nodes = (uint32_t)nx * ny;
   const uint32_t pitch = a.pitch;
   const uint32_t rb = (uint32_t)nx * 4u;
-  const rsrc_t rsrc = make_rsrc(a.src, pop_bytes(ST_F32, pitch, ny));
-  const rsrc_t rdst = make_rsrc(a.dst, pop_bytes(ST_F32, pitch, ny));
+  const rsrc_t rsrc = make_rsrc(a.src, pop_bytes(ST, pitch, ny));
+  const rsrc_t rdst = make_rsrc(a.dst, pop_bytes(ST, pitch, ny));
   rsrc_t ru, rv, rrec;
   if (VFIELD) {
     ru = make_rsrc(a.ux, nodes * 4u);
@@ -455,7 +455,7 @@ __device__ __forceinline__ void phi_tile_t1(const StepArgs& a, const int L) {
   auto issue = [&](int r, uint32_t cc, uint32_t cm, uint32_t cp, PullT1& P) {
     float sg;
     const int sr = row_of<WALLS>(r, ny, sg);
-    pull9<WALLS, ST_F32>(rsrc, pitch, ny, sr, cc, cm, cp, P.g);
+    pull9<WALLS, ST>(rsrc, pitch, ny, sr, cc, cm, cp, P.g);
     if (VMODE == VEL_SEP) {
       P.a = a.ay[sr];
       P.b = a.by[sr];
@@ -515,7 +515,7 @@ __device__ __forceinline__ void phi_tile_t1(const StepArgs& a, const int L) {
     if (REC) stb_nt(rrec, R.phi, vc * 4u, (uint32_t)y * rb);
     float g[9];
     collide_t1(c, R.phi, s_mu[s0][j], u, v, fx, fy, g);
-    finish_store<ST_F32>(rdst, pitch, vc, (uint32_t)y, (double)R.phi + (double)R.lo, g);
+    finish_store<ST>(rdst, pitch, vc, (uint32_t)y, (double)R.phi + (double)R.lo, g);
   };
 
   // Rows the march needs: m = -2 .. rows + 1; a pull past the last one is clamped to it
@@ -635,15 +635,15 @@ __device__ __forceinline__ void phi_tile_t1(const StepArgs& a, const int L) {
 
 // Model 3 carries two more values per row record; it gets the register budget of
 // three waves per SIMD so that nothing spills.
-// T1: the tau_g = 1 tile (float32 storage, models 1 and 2, prescribed velocity only).
+// T1: the tau_g = 1 tile (models 1 and 2, prescribed velocity only).
 template <int VMODE, int MODEL, int ST>
 constexpr bool t1_ok() {
-  return ST == ST_F32 && (MODEL == 1 || MODEL == 2) && (VMODE == VEL_SEP || VMODE == VEL_FIELD);
+  return (MODEL == 1 || MODEL == 2) && (VMODE == VEL_SEP || VMODE == VEL_FIELD);
 }
 template <int TX, bool WALLS, int VMODE, int MODEL, int ST, bool REC, bool T1>
 __device__ __forceinline__ void step_tile(const StepArgs& a, int L) {
   if constexpr (T1 && t1_ok<VMODE, MODEL, ST>())
-    phi_tile_t1<TX, WALLS, VMODE, MODEL, REC>(a, L);
+    phi_tile_t1<TX, WALLS, VMODE, MODEL, ST, REC>(a, L);
   else
     phi_tile<TX, WALLS, VMODE, MODEL, ST, REC>(a, L);
 }
