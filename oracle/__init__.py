@@ -46,7 +46,8 @@ class _Params(ctypes.Structure):
                 ("phi_a", ctypes.c_double), ("phi_b", ctypes.c_double),
                 ("rho_a", ctypes.c_double), ("rho_b", ctypes.c_double),
                 ("tau_f", ctypes.c_double), ("gravity", ctypes.c_double),
-                ("accel_x", ctypes.c_double)]
+                ("accel_x", ctypes.c_double), ("f1_form", ctypes.c_int),
+                ("round_f32", ctypes.c_int)]
 
 
 class _Coeffs(ctypes.Structure):
@@ -72,6 +73,8 @@ class Params:
     tau_f: float = 1.0
     gravity: float = 0.0
     accel_x: float = 0.0
+    f1_form: int = 0  # 0: F1 = (phi/rho) F_s (grad p = 0); 1: F1 = phi Du/Dt of the prescribed u
+    round_f32: int = 0  # 1: round the populations to float32 after every step (sensitivity runs)
 
     def c(self) -> _Params:
         return _Params(*[getattr(self, f.name) for f in dataclasses.fields(self)])

@@ -213,6 +213,9 @@ static void stream(const orc_params* p, const double* post, double* out) {
 
 typedef struct {
   double *phi, *mu, *mux, *muy, *lapmu, *phx, *phy; /* order parameter and derived   */
+  double *gux, *guy, *gvx, *gvy;                    /* gradient of a prescribed u   */
+  const double *ux0, *uy0;                          /* base field of a prescribed u */
+  double dtf;                                       /* d/dt of its time factor      */
   double *u, *v, *pr, *px, *py;                     /* velocity and pressure         */
   double *qx, *qy, *dext;                           /* phi u and its divergence      */
   double *fx, *fy, *ftx, *fty;                      /* CH force F; NS total force    */
@@ -228,13 +231,15 @@ static void work_alloc(const orc_params* p, orc_work* w) {
   w->u = zalloc(n); w->v = zalloc(n); w->pr = zalloc(n); w->px = zalloc(n); w->py = zalloc(n);
   w->qx = zalloc(n); w->qy = zalloc(n); w->dext = zalloc((size_t)p->nx * (p->ny + 2));
   w->fx = zalloc(n); w->fy = zalloc(n); w->ftx = zalloc(n); w->fty = zalloc(n);
+  w->gux = zalloc(n); w->guy = zalloc(n); w->gvx = zalloc(n); w->gvy = zalloc(n);
+  w->ux0 = NULL; w->uy0 = NULL; w->dtf = 0.0;
   w->post = zalloc(9 * n);
 }
 
 static void work_free(orc_work* w) {
   double* all[] = {w->phi, w->mu, w->mux, w->muy, w->lapmu, w->phx, w->phy, w->u, w->v,
                    w->pr, w->px, w->py, w->qx, w->qy, w->dext, w->fx, w->fy, w->ftx,
-                   w->fty, w->post};
+                   w->fty, w->gux, w->guy, w->gvx, w->gvy, w->post};
   for (size_t i = 0; i < sizeof(all) / sizeof(all[0]); ++i) free(all[i]);
 }
 
@@ -316,6 +321,21 @@ static void ch_force(const orc_params* p, const orc_coeffs* c, orc_work* w, doub
   double rho_mean = 0.5 * (p->rho_a + p->rho_b);
   /* F1 = (phi/rho) (F_s + F_b - grad p), F_s = -phi grad mu.  With a prescribed
    * velocity there is no pressure field or body force: grad p = 0, F_b = 0. */
+  if (p->f1_form == 1 && !p->ns) {
+    /* F1 of Eq. cFi1 from the prescribed field: d_t(phi u) + div(phi u u)
+     * = u (d_t phi + div(phi u)) + phi (d_t u + u.grad u) = phi (d_t u + u.grad u) on the
+     * t1 scale, where d_t phi + div(phi u) = 0. */
+    orc_grad(p, w->u, -1, w->gux, w->guy);
+    orc_grad(p, w->v, -1, w->gvx, w->gvy);
+#pragma omp parallel for schedule(static)
+    for (size_t k = 0; k < n; ++k) {
+      double dtu = w->ux0 ? w->dtf * w->ux0[k] : 0.0, dtv = w->uy0 ? w->dtf * w->uy0[k] : 0.0;
+      double ax = dtu + w->u[k] * w->gux[k] + w->v[k] * w->guy[k];
+      double ay = dtv + w->u[k] * w->gvx[k] + w->v[k] * w->gvy[k];
+      w->fx[k] = w->phi[k] * ax;
+      w->fy[k] = w->phi[k] * ay;
+    }
+  } else {
 #pragma omp parallel for schedule(static)
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
@@ -331,6 +351,7 @@ static void ch_force(const orc_params* p, const orc_coeffs* c, orc_work* w, doub
       w->fx[k] = phi / rho * tx;
       w->fy[k] = phi / rho * ty;
     }
+  }
   if (p->model == 1) return;
   /* Eq. F2-1, model 3: the time derivatives of F1 and grad mu (taken on the whole time
    * scale, as Remarks I and II allow) as differences over the last step; zero on the
@@ -449,11 +470,24 @@ void orc_run(const orc_params* p, double* g, double* f, const double* ux, const 
   if (p->model == 3 && (!hist || !hist_valid)) return;
   orc_work w;
   work_alloc(p, &w);
+  w.ux0 = ux;
+  w.uy0 = uy;
   for (long s = 0; s < nsteps; ++s) {
     phase_fields(p, &c, g, &w);
     velocity_fields(p, &c, f, ux, uy, tf ? tf[s] : 1.0, &w);
+    /* d/dt of the time factor at step s: backward difference, forward on the first step
+     * of the call (the table given covers this call's steps) */
+    w.dtf = 0.0;
+    if (tf && s > 0) w.dtf = tf[s] - tf[s - 1];
+    else if (tf && nsteps > 1) w.dtf = tf[1] - tf[0];
     ch_force(p, &c, &w, hist, hist_valid);
     collide_stream(p, &c, g, f, &w);
+    if (p->round_f32) {
+      size_t n9 = 9 * nn(p);
+      for (size_t k = 0; k < n9; ++k) g[k] = (double)(float)g[k];
+      if (p->ns && f)
+        for (size_t k = 0; k < n9; ++k) f[k] = (double)(float)f[k];
+    }
   }
   work_free(&w);
 }

@@ -50,6 +50,16 @@ typedef struct {
   double tau_f;    /* NS relaxation time, nu = cs^2 (tau_f - 1/2)                      */
   double gravity;  /* NS: acceleration g along -y, applied as -(rho - rho_mean) g        */
   double accel_x;  /* NS: uniform acceleration along +x, applied as rho * accel_x        */
+  int f1_form;     /* reading of F1 with a prescribed velocity (ns = 0):
+                      0: Eq. t0-phiu with grad p = 0, F1 = (phi/rho) F_s = -(phi^2/rho) grad mu;
+                      1: Eq. cFi1 evaluated from the prescribed field, F1 = d_t(phi u) +
+                         div(phi u u) = phi (d_t u + u.grad u), using the t1-scale balance
+                         d_t phi + div(phi u) = 0 (Eq. moments0order a); d_t u from a
+                         one-step difference of the time factor                          */
+  int round_f32;   /* 0 normally.  1: after every step the populations are rounded to
+                      float32 (the storage precision of the GPU path), to measure how much
+                      the dynamics amplify perturbations of that size when deriving a
+                      long-run tolerance; the method itself is unchanged                */
 } orc_params;
 
 typedef struct {

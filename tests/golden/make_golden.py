@@ -1,14 +1,24 @@
 """Write stored FP64 oracle samples for workloads too large to run in a test.
 
 Calls only ``oracle`` and ``workloads``.  For each case it runs the oracle for the
-stated number of steps and stores phi at 4096 seeded sample nodes, the full-field
-relative L2 of phi against the initial field (Eq. err), the initial mass sums and
-the final extrema.
+stated number of steps and stores phi at seeded sample nodes, the full-field relative
+L2 of phi against the initial field (Eq. err), the initial mass sums and the final
+extrema.  The samples are stratified so that the interface, where the method does its
+work, is well represented: about half of them where |phi| < 0.95 at the end of the
+run, a uniform draw over the lattice, and one whole lattice row crossing the
+interface (the row holding most interface nodes).
+
+For the Rayleigh-Taylor cases the oracle also runs a second time with its populations
+rounded to float32 after every step (the GPU path's storage precision); the sampled
+relative L2 distance between the two runs (sens_rel_l2) measures how much the growing
+instability amplifies perturbations of that size, and the long-run GPU tolerance is
+derived from it.
 
     python tests/golden/make_golden.py vortex2048     # 2048^2, 1000 steps
     python tests/golden/make_golden.py vortex512      # 512^2, one period T = 20000
     python tests/golden/make_golden.py rt256          # 256x1024 Rayleigh-Taylor, 1000 steps
     python tests/golden/make_golden.py rt256_4000     # the same after 4000 steps (0.44 T)
+    python tests/golden/make_golden.py rt256_T        # the same through T = 9051 steps
     python tests/golden/make_golden.py rtpaper25_40000  # At 0.25, Re 400 (Sec. III.E), 40000 steps
     python tests/golden/make_golden.py adjoint256     # 256^2, 2000 steps: target + FD gradients
 
@@ -17,6 +27,7 @@ coefficients) and FP64 central finite differences (h = 1e-6) of the loss
 ||phi(N) - phi_target||^2 with respect to all 16 stream-function coefficients and phi0
 at 8 seeded nodes.
 """
+import dataclasses
 import os
 import sys
 import time
@@ -34,10 +45,33 @@ CASES = {
     "vortex512": (lambda: workloads.vortex(512, period=20000), 20000, 0),
     "rt256": (lambda: workloads.rayleigh_taylor_case(256, 1024, steps=1000), 1000, 1),
     "rt256_4000": (lambda: workloads.rayleigh_taylor_case(256, 1024, steps=4000), 4000, 1),
+    # T = sqrt(L / (At g)) = 9051 steps for L = 256, At = 0.5, sqrt(g L) = 0.04
+    "rt256_T": (lambda: workloads.rayleigh_taylor_case(256, 1024, steps=9051), 9051, 1),
     "rtpaper25_40000": (lambda: workloads.rayleigh_taylor_case(256, 1024, steps=40000,
                                                                reynolds=400.0, atwood=0.25),
                         40000, 1),
 }
+
+
+def sample_index(phi, seed=20240601, n_band=2560, n_uniform=1536):
+    """Stratified sample nodes of a final (ny, nx) field: n_band nodes where |phi| < 0.95,
+    n_uniform nodes over the whole lattice, and the whole row with most band nodes."""
+    ny, nx = phi.shape
+    rng = np.random.default_rng(seed)
+    flat = phi.ravel()
+    band = np.flatnonzero(np.abs(flat) < 0.95)
+    pick = [rng.choice(band, size=min(n_band, len(band)), replace=False)] if len(band) else []
+    pick.append(rng.choice(nx * ny, size=n_uniform, replace=False))
+    row = int(np.argmax((np.abs(phi) < 0.95).sum(axis=1)))
+    pick.append(row * nx + np.arange(nx))
+    return np.unique(np.concatenate(pick)), row
+
+
+def _state(w, p):
+    if w.velocity is not None:
+        U, V = workloads.separable_field(w.velocity)
+        return oracle.State(p, w.phi0, U, V, w.velocity["tf"])
+    return oracle.State(p, w.phi0)
 
 
 def make(name):
@@ -45,25 +79,29 @@ def make(name):
     w = build()
     p = oracle.Params(nx=w.nx, ny=w.ny, walls=walls, ns=1 if "tau_f" in w.phys else 0,
                       **w.phys)
-    if w.velocity is not None:
-        U, V = workloads.separable_field(w.velocity)
-        s = oracle.State(p, w.phi0, U, V, w.velocity["tf"])
-    else:
-        s = oracle.State(p, w.phi0)
+    s = _state(w, p)
     d0 = oracle.diag(p, s.phi)
     t0 = time.time()
     s.run(steps)
     phi = s.phi
     d = oracle.diag(p, phi, w.phi0)
-    rng = np.random.default_rng(20240601)
-    idx = np.sort(rng.choice(w.nx * w.ny, size=4096, replace=False))
+    idx, row = sample_index(phi)
+    extra = {}
+    if p.ns:
+        pr = dataclasses.replace(p, round_f32=1)
+        sr = _state(w, pr).run(steps)
+        ref = phi.ravel()[idx]
+        extra = dict(sens_rel_l2=float(np.sqrt(((sr.phi.ravel()[idx] - ref) ** 2).sum()
+                                                / (ref ** 2).sum())),
+                     sens_max_abs=float(np.abs(sr.phi.ravel()[idx] - ref).max()))
+        print("float32-rounded rerun: sampled rel L2 %.3e" % extra["sens_rel_l2"])
     out = os.path.join(HERE, "%s_oracle_%d.npz" % (name.split("_")[0], steps))
-    np.savez_compressed(out, steps=steps, index=idx, phi=phi.ravel()[idx],
+    np.savez_compressed(out, steps=steps, index=idx, phi=phi.ravel()[idx], row=row,
                         mass0=d0["mass"], abs_mass0=d0["abs_mass"], mass=d["mass"],
                         e_phi=np.sqrt(d["err2"] / d["ref2"]), max=d["max"], min=d["min"],
-                        threads=oracle.num_threads(), seconds=time.time() - t0)
-    print(out, "E_phi=%.4e max=%.4f min=%.4f %.0fs" % (
-        np.sqrt(d["err2"] / d["ref2"]), d["max"], d["min"], time.time() - t0))
+                        threads=oracle.num_threads(), seconds=time.time() - t0, **extra)
+    print(out, "samples=%d E_phi=%.4e max=%.4f min=%.4f %.0fs" % (
+        len(idx), np.sqrt(d["err2"] / d["ref2"]), d["max"], d["min"], time.time() - t0))
 
 
 def adjoint_run(case, p, phi0, theta, scale):

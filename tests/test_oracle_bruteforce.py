@@ -77,9 +77,17 @@ def _step_mp(g, ux, uy, par, n, first):
         return {(c, *p): geq(p, c, wi) for p in nodes for c, wi in zip(cs, w)}
     gm = grad(mu)
     force = {}
-    for p in nodes:
-        rho = a * phi[p] + b
-        force[p] = [phi[p] / rho * (-phi[p] * gm[p][0]), phi[p] / rho * (-phi[p] * gm[p][1])]
+    if par.get("f1_form", 0) == 1:
+        # the material acceleration of a steady prescribed u: F1 = phi (u.grad) u
+        gu, gv = grad(ux), grad(uy)
+        for p in nodes:
+            force[p] = [phi[p] * (ux[p] * gu[p][0] + uy[p] * gu[p][1]),
+                        phi[p] * (ux[p] * gv[p][0] + uy[p] * gv[p][1])]
+    else:
+        for p in nodes:
+            rho = a * phi[p] + b
+            force[p] = [phi[p] / rho * (-phi[p] * gm[p][0]),
+                        phi[p] / rho * (-phi[p] * gm[p][1])]
     if par["model"] == 2:
         qx = {p: phi[p] * ux[p] for p in nodes}
         qy = {p: phi[p] * uy[p] for p in nodes}
@@ -98,8 +106,11 @@ def _step_mp(g, ux, uy, par, n, first):
     return out
 
 
-@pytest.mark.parametrize("tau,model", [(1.0, 2), (0.8, 2), (0.8, 1), (1.3, 2)])
-def test_two_steps_match_50_digit_brute_force(tau, model):
+@pytest.mark.parametrize("tau,model,f1_form", [(1.0, 2, 0), (0.8, 2, 0), (0.8, 1, 0),
+                                               (1.3, 2, 0), (0.8, 1, 1), (1.3, 2, 1)])
+def test_two_steps_match_50_digit_brute_force(tau, model, f1_form):
+    """f1_form 1 is the alternative reading of F1 with a prescribed velocity (the
+    material acceleration of u, here steady) that the oracle keeps for comparison."""
     mp.dps = 50
     n = 8
     rng = np.random.default_rng(21)
@@ -108,14 +119,14 @@ def test_two_steps_match_50_digit_brute_force(tau, model):
     uy = rng.uniform(-0.05, 0.05, (n, n))
     phys = dict(tau_g=tau, mobility=0.02, sigma=0.01, width=3.0, phi_a=1.0, phi_b=-1.0,
                 rho_a=1.0, rho_b=0.4)
-    p = oracle.Params(nx=n, ny=n, model=model, **phys)
+    p = oracle.Params(nx=n, ny=n, model=model, f1_form=f1_form, **phys)
     st = oracle.State(p, phi0, ux, uy)
     orc = [st.g.copy()]
     for _ in range(2):
         st.run(1)
         orc.append(st.g.copy())
 
-    par = {"tau": mp.mpf(tau), "model": model, "phi0": {}}
+    par = {"tau": mp.mpf(tau), "model": model, "f1_form": f1_form, "phi0": {}}
     for k in ("mobility", "sigma", "width", "phi_a", "phi_b", "rho_a", "rho_b"):
         par[k] = mp.mpf(phys[k])
     U, V = {}, {}
@@ -141,3 +152,22 @@ def test_two_steps_match_50_digit_brute_force(tau, model):
                     err = max(err, abs(float(gm[((cx[i], cy[i]), x, y)]) - go[i, y, x]))
         print("tau %.2f model %d after %d steps: max |g_oracle - g_brute| = %.2e" % (tau, model, k, err))
         assert err <= 1e-14, (k, err)
+
+
+def test_round_f32_rounds_the_stored_populations_only():
+    """round_f32 (the sensitivity runs that derive long-run tolerances) changes nothing
+    but the storage: one step with it is one step without it, rounded to float32."""
+    n = 16
+    rng = np.random.default_rng(5)
+    phi0 = np.clip(rng.normal(0.0, 0.6, (n, n)), -1.2, 1.2)
+    ux = rng.uniform(-0.05, 0.05, (n, n))
+    uy = rng.uniform(-0.05, 0.05, (n, n))
+    phys = dict(nx=n, ny=n, model=2, tau_g=0.8, mobility=0.02, sigma=0.01, width=3.0)
+    a = oracle.State(oracle.Params(**phys), phi0, ux, uy)
+    b = oracle.State(oracle.Params(round_f32=1, **phys), phi0, ux, uy)
+    b.g[:] = a.g.astype(np.float32).astype(np.float64)
+    a.g[:] = b.g
+    a.run(1)
+    b.run(1)
+    assert np.array_equal(b.g, a.g.astype(np.float32).astype(np.float64))
+    assert not np.array_equal(b.g, a.g)
