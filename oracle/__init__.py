@@ -74,7 +74,7 @@ class Params:
     gravity: float = 0.0
     accel_x: float = 0.0
     f1_form: int = 0  # 0: F1 = (phi/rho) F_s (grad p = 0); 1: F1 = phi Du/Dt of the prescribed u
-    round_f32: int = 0  # 1: round the populations to float32 after every step (sensitivity runs)
+    round_f32: int = 0  # 1: round what the GPU path holds in float32 (sensitivity runs)
 
     def c(self) -> _Params:
         return _Params(*[getattr(self, f.name) for f in dataclasses.fields(self)])

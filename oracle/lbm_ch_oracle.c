@@ -282,10 +282,18 @@ static void ns_velocity_pressure(const orc_params* p, const orc_coeffs* c, const
 }
 
 /* Order parameter, chemical potential and their gradients for the current g. */
+/* Sensitivity runs (round_f32): round a field to float32, as the GPU path holds it. */
+static void to_f32(const orc_params* p, double* a, size_t n) {
+  if (!p->round_f32) return;
+  for (size_t k = 0; k < n; ++k) a[k] = (double)(float)a[k];
+}
+
 static void phase_fields(const orc_params* p, const orc_coeffs* c, const double* g, orc_work* w) {
   (void)c;
   order_parameter(p, g, w->phi);
+  to_f32(p, w->phi, nn(p));
   orc_chemical_potential(p, w->phi, w->mu);
+  to_f32(p, w->mu, nn(p));
   orc_grad(p, w->mu, +1, w->mux, w->muy);
   if (p->ns) {
     orc_lap(p, w->mu, +1, w->lapmu);
@@ -299,6 +307,9 @@ static void velocity_fields(const orc_params* p, const orc_coeffs* c, const doub
   size_t n = nn(p);
   if (p->ns) {
     ns_velocity_pressure(p, c, f, w);
+    to_f32(p, w->u, n);
+    to_f32(p, w->v, n);
+    to_f32(p, w->pr, n);
     orc_grad(p, w->pr, +1, w->px, w->py);
     return;
   }
@@ -384,6 +395,8 @@ static void ch_force(const orc_params* p, const orc_coeffs* c, orc_work* w, doub
     w->qx[k] = w->phi[k] * w->u[k];
     w->qy[k] = w->phi[k] * w->v[k];
   }
+  to_f32(p, w->qx, n);
+  to_f32(p, w->qy, n);
   int ylo = p->walls ? -1 : 0, yhi = p->walls ? ny : ny - 1;
 #pragma omp parallel for schedule(static)
   for (int y = ylo; y <= yhi; ++y)
@@ -393,6 +406,7 @@ static void ch_force(const orc_params* p, const orc_coeffs* c, orc_work* w, doub
       grad_at(p, w->qy, -1, x, y, &bx, &by);
       w->dext[(size_t)(y + 1) * nx + x] = ax + by;
     }
+  to_f32(p, w->dext, (size_t)nx * (ny + 2));
 #pragma omp parallel for schedule(static)
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
@@ -482,12 +496,8 @@ void orc_run(const orc_params* p, double* g, double* f, const double* ux, const 
     else if (tf && nsteps > 1) w.dtf = tf[1] - tf[0];
     ch_force(p, &c, &w, hist, hist_valid);
     collide_stream(p, &c, g, f, &w);
-    if (p->round_f32) {
-      size_t n9 = 9 * nn(p);
-      for (size_t k = 0; k < n9; ++k) g[k] = (double)(float)g[k];
-      if (p->ns && f)
-        for (size_t k = 0; k < n9; ++k) f[k] = (double)(float)f[k];
-    }
+    to_f32(p, g, 9 * nn(p));
+    if (p->ns && f) to_f32(p, f, 9 * nn(p));
   }
   work_free(&w);
 }

@@ -56,10 +56,12 @@ typedef struct {
                          div(phi u u) = phi (d_t u + u.grad u), using the t1-scale balance
                          d_t phi + div(phi u) = 0 (Eq. moments0order a); d_t u from a
                          one-step difference of the time factor                          */
-  int round_f32;   /* 0 normally.  1: after every step the populations are rounded to
-                      float32 (the storage precision of the GPU path), to measure how much
-                      the dynamics amplify perturbations of that size when deriving a
-                      long-run tolerance; the method itself is unchanged                */
+  int round_f32;   /* 0 normally.  1: every value the GPU path holds in float32 between
+                      its stages is rounded to float32 where it is formed: phi, mu, the
+                      NS velocity and pressure, q = phi u and div q within a step, and the
+                      populations after it.  Used to measure how much the dynamics
+                      amplify perturbations of that size when deriving a long-run
+                      tolerance; the method itself is unchanged                          */
 } orc_params;
 
 typedef struct {

@@ -57,13 +57,15 @@ def _step_mp(g, ux, uy, par, n, first):
         return {p: 2 * sum(wi * (psi[shift(*p, c)] - psi[p]) for c, wi in zip(cs, w)) / cs2
                 for p in nodes}
 
+    r32 = (lambda d: {k: mp.mpf(float(np.float32(float(v)))) for k, v in d.items()}) \
+        if par.get("round32") and not first else (lambda d: d)
     if first:
         phi = par["phi0"]
     else:
-        phi = {p: sum(g[(c, *p)] for c in cs) for p in nodes}
+        phi = r32({p: sum(g[(c, *p)] for c in cs) for p in nodes})
     lp = lap(phi)
-    mu = {p: 2 * beta * (phi[p] - pa) * (phi[p] - pb) * (2 * phi[p] - pa - pb) - kappa * lp[p]
-          for p in nodes}
+    mu = r32({p: 2 * beta * (phi[p] - pa) * (phi[p] - pb) * (2 * phi[p] - pa - pb) - kappa * lp[p]
+              for p in nodes})
 
     def geq(p, c, wi):
         u, v = ux[p], uy[p]
@@ -89,10 +91,10 @@ def _step_mp(g, ux, uy, par, n, first):
             force[p] = [phi[p] / rho * (-phi[p] * gm[p][0]),
                         phi[p] / rho * (-phi[p] * gm[p][1])]
     if par["model"] == 2:
-        qx = {p: phi[p] * ux[p] for p in nodes}
-        qy = {p: phi[p] * uy[p] for p in nodes}
+        qx = r32({p: phi[p] * ux[p] for p in nodes})
+        qy = r32({p: phi[p] * uy[p] for p in nodes})
         gqx, gqy = grad(qx), grad(qy)
-        div = {p: gqx[p][0] + gqy[p][1] for p in nodes}
+        div = r32({p: gqx[p][0] + gqy[p][1] for p in nodes})
         gd = grad(div)
         for p in nodes:
             force[p][0] += 3 * cs2 * K * gd[p][0]
@@ -103,7 +105,7 @@ def _step_mp(g, ux, uy, par, n, first):
             src = wi * (c[0] * force[p][0] + c[1] * force[p][1]) / cs2
             post = g[(c, *p)] - (g[(c, *p)] - geq(p, c, wi)) / tau + (1 - 1 / (2 * tau)) * src
             out[(c, *shift(*p, c))] = post  # push
-    return out
+    return r32(out)
 
 
 @pytest.mark.parametrize("tau,model,f1_form", [(1.0, 2, 0), (0.8, 2, 0), (0.8, 1, 0),
@@ -154,20 +156,39 @@ def test_two_steps_match_50_digit_brute_force(tau, model, f1_form):
         assert err <= 1e-14, (k, err)
 
 
-def test_round_f32_rounds_the_stored_populations_only():
-    """round_f32 (the sensitivity runs that derive long-run tolerances) changes nothing
-    but the storage: one step with it is one step without it, rounded to float32."""
-    n = 16
-    rng = np.random.default_rng(5)
+def test_round_f32_rounds_where_the_gpu_holds_float32():
+    """round_f32 (the sensitivity runs that derive long-run tolerances) rounds phi, mu,
+    q = phi u and div q to float32 where they are formed, and the populations after each
+    step; the 50-digit step with the same rounding points agrees to FP64 accuracy, and
+    the rounding does change the result."""
+    mp.dps = 50
+    n = 8
+    rng = np.random.default_rng(9)
     phi0 = np.clip(rng.normal(0.0, 0.6, (n, n)), -1.2, 1.2)
     ux = rng.uniform(-0.05, 0.05, (n, n))
     uy = rng.uniform(-0.05, 0.05, (n, n))
-    phys = dict(nx=n, ny=n, model=2, tau_g=0.8, mobility=0.02, sigma=0.01, width=3.0)
-    a = oracle.State(oracle.Params(**phys), phi0, ux, uy)
-    b = oracle.State(oracle.Params(round_f32=1, **phys), phi0, ux, uy)
-    b.g[:] = a.g.astype(np.float32).astype(np.float64)
-    a.g[:] = b.g
-    a.run(1)
-    b.run(1)
-    assert np.array_equal(b.g, a.g.astype(np.float32).astype(np.float64))
-    assert not np.array_equal(b.g, a.g)
+    phys = dict(tau_g=0.8, mobility=0.02, sigma=0.01, width=3.0, phi_a=1.0, phi_b=-1.0,
+                rho_a=1.0, rho_b=0.4)
+    st = oracle.State(oracle.Params(nx=n, ny=n, model=2, round_f32=1, **phys), phi0, ux, uy)
+    plain = oracle.State(oracle.Params(nx=n, ny=n, model=2, **phys), phi0, ux, uy)
+    st.run(2)
+    plain.run(2)
+    par = {"tau": mp.mpf(0.8), "model": 2, "round32": True, "phi0": {}}
+    for k in ("mobility", "sigma", "width", "phi_a", "phi_b", "rho_a", "rho_b"):
+        par[k] = mp.mpf(phys[k])
+    U, V = {}, {}
+    for y in range(n):
+        for x in range(n):
+            par["phi0"][(x, y)] = mp.mpf(phi0[y, x])
+            U[(x, y)] = mp.mpf(ux[y, x])
+            V[(x, y)] = mp.mpf(uy[y, x])
+    g = _step_mp(None, U, V, par, n, first=True)
+    for _ in range(2):
+        g = _step_mp(g, U, V, par, n, first=False)
+    cx = [0, 1, 0, -1, 0, 1, -1, -1, 1]
+    cy = [0, 0, 1, 0, -1, 1, 1, -1, -1]
+    ref = np.array([[[float(g[((cx[i], cy[i]), x, y)]) for x in range(n)] for y in range(n)]
+                    for i in range(9)])
+    assert np.array_equal(st.g, st.g.astype(np.float32).astype(np.float64))
+    assert np.abs(st.g - ref).max() <= 1e-14
+    assert np.abs(st.g - plain.g).max() > 1e-10
