@@ -368,8 +368,36 @@ static int run_steps(lbm_ch_ctx* c, int64_t nsteps, float* phi_out, hipStream_t 
     a.ux = c->u; a.uy = c->v; a.pf = c->pr;
   }
   const int vmode = ns ? VEL_NSFIELD : c->vmode;
+  // Coupled steps of models 1 and 2 run as one launch (f and g together) on output tiles
+  // of 64 columns x rows; model 3 keeps the two launches (NS step, then phase field).
+  const bool fused = ns && (c->p.model == 1 || c->p.model == 2);
+  StepArgs r = a;
+  int rt_rows = 0, rt_blocks = 0;
+  if (fused) {
+    rt_rows = rt_step_rows(c->ty);
+    r.nstrips = (c->p.nx + 63) / 64;
+    rt_blocks = r.nstrips * ((c->p.ny + rt_rows - 1) / rt_rows);
+    r.xcd_remap = rt_blocks % 8 == 0 ? 1 : 0;
+  }
   for (int64_t s = 0; s < nsteps; ++s) {
     const int src = c->cur, dst = 1 - c->cur;
+    if (fused) {
+      float* rec = phi_out ? phi_out + (size_t)s * c->p.nx * c->p.ny : nullptr;
+      hipError_t e = hipSuccess;
+      if (rec)
+        e = launch_phi_field(walls, c->p.storage, c->g[src], c->L.pitch, c->p.nx, c->p.ny,
+                             rec, stream);
+      if (e == hipSuccess) {
+        r.src = c->g[src];
+        r.dst = c->g[dst];
+        e = launch_rt_step(rt_rows, walls, c->p.model, c->p.storage, r, c->f[src], c->f[dst],
+                           rt_blocks, stream);
+      }
+      if (e != hipSuccess) return hip_fail(e);
+      c->cur = dst;
+      c->step += 1;
+      continue;
+    }
     hipError_t e;
     if (ns) {
       n.gsrc = c->g[src];

@@ -96,6 +96,13 @@ hipError_t launch_phi_batch(int tx, int vmode, bool model2, bool t1, bool persis
                             const BatchArgs& b, int grid, hipStream_t s);
 hipError_t launch_ns_step(int tx, bool walls, int storage, const NsArgs& a, int nblocks,
                           hipStream_t s);
+// Single-launch coupled step (models 1 and 2): f and g of one time step, output tiles
+// of 64 columns x rows (2, 4 or 8; rt_step_rows maps a tile height onto them) in
+// ceil(nx / 64) * ceil(ny / rows) workgroups; a.src/a.dst are the g buffers, a.nstrips =
+// ceil(nx / 64).  hipErrorInvalidValue for other models.
+int rt_step_rows(int ty);
+hipError_t launch_rt_step(int rows, bool walls, int model, int storage, const StepArgs& a,
+                          const float* fsrc, float* fdst, int nblocks, hipStream_t s);
 
 hipError_t launch_init(bool walls, int vmode, int storage, const Coef& c, int nx, int ny,
                        uint32_t pitch, const float* phi0, const float* ax, const float* ay,
