@@ -104,3 +104,52 @@ def test_translating_density_interface_converges():
     (u4, d4), (u8, d8), (u16, d16) = errs
     assert d4 / d8 > 3.5 and d8 / d16 > 3.5
     assert u4 / u16 > 3.0 and u16 < 0.025 * 0.02
+
+
+def _rt_run(w, steps, chunk):
+    """Run a Rayleigh-Taylor workload in the oracle; returns (steps reached while finite,
+    extrema of phi seen, largest |u| seen)."""
+    p = oracle.Params(nx=w.nx, ny=w.ny, walls=1, ns=1, **w.phys)
+    s = oracle.State(p, w.phi0)
+    done, ext, umax = 0, 1.0, 0.0
+    while done < steps:
+        s.run(chunk)
+        phi, mu, u, v, pr = s.fields()
+        if not (np.isfinite(phi).all() and np.isfinite(u).all()):
+            return done, ext, umax
+        done += chunk
+        ext = max(ext, float(np.abs(phi).max()))
+        umax = max(umax, float(np.hypot(u, v).max()))
+    return done, ext, umax
+
+
+@pytest.fixture
+def two_threads():
+    """Small lattices: a step is too short to share among many threads."""
+    n = oracle.num_threads()
+    oracle.set_num_threads(min(n, 2))
+    yield
+    oracle.set_num_threads(n)
+
+
+def test_rayleigh_taylor_at05_re3000_diverges_paper_case_does_not(two_threads):
+    """The At = 0.5, Re = 3000 Rayleigh-Taylor case is not reachable with the BGK
+    Navier-Stokes model (reading R11) for 40000 steps: at full size (256x1024) the FP64
+    oracle goes non-finite near 1.4 T.  The same dimensionless case at 64x256 (sqrt(gL) =
+    0.04, W = 4, Pe = 1000, 0.1 L perturbation; T = 2263 steps) goes non-finite before
+    2 T, after its largest velocity has passed 0.08 (lattice Mach number 0.14).  The
+    paper's own case (Sec. III.E: At = 0.25, Re = 400, 0.05 d perturbation) at the same
+    size stays finite through 3.125 T, the length of its 40000-step full-size run."""
+    cfg = workloads.rayleigh_taylor_case(64, 256, steps=4600)
+    T = 2263
+    reached, ext, umax = _rt_run(cfg, 2 * T, 250)
+    print("At 0.5 Re 3000 at 64x256: finite through %d steps (%.2f T), max |phi| %.3f, "
+          "max |u| %.3f" % (reached, reached / T, ext, umax))
+    assert reached < 2 * T
+    assert umax > 0.08
+    paper = workloads.rayleigh_taylor_paper(0.25, nx=64, ny=256, steps=10000)
+    reached, ext, umax = _rt_run(paper, 10000, 1000)
+    print("At 0.25 Re 400 at 64x256: finite through %d steps, max |phi| %.3f, max |u| %.3f"
+          % (reached, ext, umax))
+    assert reached == 10000
+    assert ext < 1.5 and umax < 0.06

@@ -218,10 +218,16 @@ def rt_params(nx=256, atwood=0.5, reynolds=3000.0, sqrt_gl=0.04, sigma=5e-5, wid
                 rho_a=rho_h, rho_b=rho_l, model=2, tau_f=0.5 + 3.0 * nu, gravity=g)
 
 
-def rayleigh_taylor_case(nx=256, ny=1024, steps=40000, **kw):
+def rayleigh_taylor_case(nx=256, ny=1024, steps=40000, amp_frac=0.1, **kw):
     phys = rt_params(nx=nx, **kw)
     return Workload("rayleigh_taylor%dx%d" % (nx, ny), nx, ny, steps, phys,
-                    rayleigh_taylor(nx, ny, phys["width"]))
+                    rayleigh_taylor(nx, ny, phys["width"], amp_frac))
+
+
+def rayleigh_taylor_paper(atwood, nx=256, ny=1024, steps=40000):
+    """Sec. III.E's own case: Re = 400, rho_h = 1, D = W = 4, Pe = 1000, sqrt(g lambda) =
+    0.04, d = lambda = nx, interface perturbed by 0.05 d cos(2 pi x / lambda)."""
+    return rayleigh_taylor_case(nx, ny, steps, amp_frac=0.05, reynolds=400.0, atwood=atwood)
 
 
 def stream_basis(n, modes):
