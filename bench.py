@@ -318,14 +318,13 @@ def adjoint_leg(lbm, torch, reps=3):
 
 def rt_leg(lbm, torch, steps=500, warm=50):
     """The coupled Rayleigh-Taylor step at its full 256x1024 size (walls in y, Atwood
-    0.5, Re 3000): one Navier-Stokes launch plus one phase-field launch per step.
-    Algorithmic bytes per node update: NS 36 (g) + 36 + 36 (f) + 12 (u, v, p written),
-    phase field 36 + 36 (g) + 12 (u, v, p read) = 204 B in float32; 16-bit g storage
-    saves 3 x 16 B = 48 B."""
+    0.5, Re 3000): one launch of k_rt_step per step (f and g together).  Algorithmic
+    bytes per node update: g 36 + 36 and f 36 + 36 = 144 B in float32; 16-bit g storage
+    makes g 20 + 20, 112 B."""
     import workloads
     w = workloads.rayleigh_taylor_case(256, 1024, steps=steps + warm)
     out = {"workload": "rayleigh_taylor 256x1024 (coupled NS + phase field, walls)"}
-    for name, st, bytes_lu in (("f32", 0, 204), ("f16", 1, 156)):
+    for name, st, bytes_lu in (("f32", 0, 144), ("f16", 1, 112)):
         s = lbm.solver_for(w, walls=1, storage=st)
         s.step(warm)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -336,15 +335,16 @@ def rt_leg(lbm, torch, steps=500, warm=50):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
         d = s.diagnostics()
+        tiles = s.tiles
         s.close()
         lu = w.nx * w.ny / (ms * 1e-3)
         out[name] = {"MLUPS": round(lu / 1e6, 1), "us_per_step": round(ms * 1e3, 2),
-                     "bytes_per_lu": bytes_lu,
+                     "bytes_per_lu": bytes_lu, "tile_rows": tiles[1],
                      "effective_GBps": round(lu * bytes_lu / 1e9, 1),
                      "nonfinite": int(d["nonfinite"]),
                      "roofline": roofline(bytes_lu, w.nx * w.ny, ms * 1e3,
-                                          "coupled step (per step, all its launches)",
-                                          "profiles/ns_step_rt256x1024_kernel_trace.md")}
+                                          "k_rt_step (one launch per step)",
+                                          "profiles/rt_step_rt256x1024_kernel_trace.md")}
     return out
 
 

@@ -151,7 +151,10 @@ int lbm_ch_init(lbm_ch_ctx** out, const lbm_ch_params* p, const lbm_ch_velocity*
                 hipStream_t stream);
 
 /* Enqueue nsteps >= 0 time steps (Eq. LB plus streaming; with NS also the coupled
- * NS step) on `stream`.  The step counter n advances by nsteps.  Non-finite values:
+ * NS step) on `stream`.  The step counter n advances by nsteps.  With NS and model 1 or
+ * 2 a step is one launch that advances f and g together (velocity and pressure are
+ * formed inside it and not stored; lbm_ch_moments recomputes them); model 3 runs the NS
+ * step and then the phase-field step.  Non-finite values:
  * every step kernel raises a flag of the context when a phi it sums from the
  * populations is NaN or Inf; the flag lives in 4 bytes of pinned host memory mapped
  * into the device (allocated by lbm_ch_init, freed by lbm_ch_destroy), so it lands on
@@ -198,7 +201,9 @@ int lbm_ch_load_state(lbm_ch_ctx* ctx, const void* src, size_t bytes, int64_t st
  * the lattice size and storage (the widest, then tallest, shape with ty from 32 down to 1
  * that gives at least 512 blocks with float32 storage, 1024 with 16-bit; tx = 512 only
  * with float32 storage and at least 1024 blocks; 64 x 1 if none does); it changes speed
- * only, never results.  Errors:
+ * only, never results.  The single-launch coupled step (NS, models 1 and 2) has output
+ * tiles of 64 columns whatever tx, and 16, 8, 4 or 2 rows: the largest of these not above
+ * ty (2 below); its default is 64 x 16.  Errors:
  * LBM_CH_EINVAL for other shapes. */
 int lbm_ch_set_tiles(lbm_ch_ctx* ctx, int32_t tx, int32_t ty);
 int lbm_ch_get_tiles(const lbm_ch_ctx* ctx, int32_t* tx, int32_t* ty);

@@ -97,7 +97,7 @@ hipError_t launch_phi_batch(int tx, int vmode, bool model2, bool t1, bool persis
 hipError_t launch_ns_step(int tx, bool walls, int storage, const NsArgs& a, int nblocks,
                           hipStream_t s);
 // Single-launch coupled step (models 1 and 2): f and g of one time step, output tiles
-// of 64 columns x rows (2, 4 or 8; rt_step_rows maps a tile height onto them) in
+// of 64 columns x rows (2, 4, 8 or 16; rt_step_rows maps a tile height onto them) in
 // ceil(nx / 64) * ceil(ny / rows) workgroups; a.src/a.dst are the g buffers, a.nstrips =
 // ceil(nx / 64).  hipErrorInvalidValue for other models.
 int rt_step_rows(int ty);

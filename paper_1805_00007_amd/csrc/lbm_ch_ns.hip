@@ -429,7 +429,7 @@ __global__ void __launch_bounds__(64 * R) k_rt_step(const StepArgs a, const floa
     fxg = fmaf(c.k2, t1_dx(dd - RT_W, dd, dd + RT_W, 0), fxg);
     fyg = fmaf(c.k2, t1_dy(dd - RT_W, dd, dd + RT_W, 0), fyg);
   }
-  collide_g(c, phio, lo, s_mu[ko], uo, vo, fxg, fyg, go);
+  collide_strict(c, phio, s_mu[ko], uo, vo, fxg, fyg, go);
   finish_store<ST>(rgd, pitch, (uint32_t)xo, (uint32_t)yo, (double)phio + (double)lo, go);
 }
 #pragma clang fp contract(fast)
@@ -473,6 +473,7 @@ hipError_t rt_step_t(int rows, bool walls, bool model2, const StepArgs& a, const
     case 2: return rt_step_r<2, ST>(walls, model2, a, fs, fd, nb, s);
     case 4: return rt_step_r<4, ST>(walls, model2, a, fs, fd, nb, s);
     case 8: return rt_step_r<8, ST>(walls, model2, a, fs, fd, nb, s);
+    case 16: return rt_step_r<16, ST>(walls, model2, a, fs, fd, nb, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -489,7 +490,7 @@ hipError_t launch_ns_step(int tx, bool walls, int storage, const NsArgs& a, int 
   }
 }
 
-int rt_step_rows(int ty) { return ty >= 8 ? 8 : ty >= 4 ? 4 : 2; }
+int rt_step_rows(int ty) { return ty >= 16 ? 16 : ty >= 8 ? 8 : ty >= 4 ? 4 : 2; }
 
 hipError_t launch_rt_step(int rows, bool walls, int model, int storage, const StepArgs& a,
                           const float* fsrc, float* fdst, int nblocks, hipStream_t s) {

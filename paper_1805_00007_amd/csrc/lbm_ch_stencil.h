@@ -60,6 +60,21 @@ __device__ __forceinline__ void collide_t1(const Coef& c, float phi, float mu, f
   pair(v - u, hy - hx, WT[6], g[6], g[8]);
 }
 
+// Collision of Eq. LB at any tau_g (g^eq of Eq. geq, S_i = 3 w_i c_i.F of Eq. liangFi):
+//   g_i* = (1 - omega) g_i + w_i (omega (eta mu + phi s_i(u)) + srcg c_i.F),  i = 1..8,
+// with every multiply-add written out; g_0* is left to the mass-conserving store.
+__device__ __forceinline__ void collide_strict(const Coef& c, float phi, float mu, float u,
+                                               float v, float fx, float fy, float g[9]) {
+  const float A = fmaf(-1.5f * phi, fmaf(u, u, v * v), c.eta * mu);
+  const float om1 = 1.0f - c.omega;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const float cu = CX[i] * u + CY[i] * v;
+    const float cf = CX[i] * fx + CY[i] * fy;
+    const float eq = fmaf(phi * cu, fmaf(4.5f, cu, 3.0f), A);
+    g[i] = fmaf(om1, g[i], WT[i] * fmaf(c.omega, eq, c.srcg * cf));
+  }
+}
 #pragma clang fp contract(fast)
 
 }  // namespace

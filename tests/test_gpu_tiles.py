@@ -40,13 +40,13 @@ def test_results_do_not_depend_on_tiles(lbm, walls):
 
 @pytest.mark.parametrize("walls", [0, 1])
 def test_ns_results_do_not_depend_on_tiles(lbm, walls):
-    """The coupled step (one launch, output tiles of 64 columns x 2, 4 or 8 rows picked by
-    the tile height) gives bitwise the same state for every tile height; 130 rows leave a
-    partial last row of tiles for each, and with walls its rows beyond the wall are
-    mirrored."""
+    """The coupled step (one launch, output tiles of 64 columns x 2, 4, 8 or 16 rows picked
+    by the tile height) gives bitwise the same state for every tile height; 130 rows
+    leave a partial last row of tiles for each, and with walls its rows beyond the wall
+    are mirrored."""
     w = workloads.rayleigh_taylor_case(64, 130, steps=80)
     ref = _run(lbm, w, 80, (64, 16), walls=walls)
-    for tiles in ((128, 3), (64, 1), (256, 4)):
+    for tiles in ((128, 3), (64, 1), (256, 4), (64, 8)):
         assert np.array_equal(_run(lbm, w, 80, tiles, walls=walls), ref), tiles
 
 
