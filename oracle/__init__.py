@@ -21,6 +21,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_ch_oracle.c")
 _LIB = os.path.join(_HERE, "liblbm_ch_oracle.so")
+# the same source in float32 arithmetic (sensitivity runs only, see State32)
+_LIB32 = os.path.join(_HERE, "liblbm_ch_oracle_f32.so")
 
 # Lattice of Sec. II.B, for the tests that reason about the method in k-space.
 CX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
@@ -29,12 +31,14 @@ W = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (OpenMP over rows).  Returns the library path."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
-               "-o", _LIB + ".tmp", _SRC, "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(_LIB + ".tmp", _LIB)
+    """Compile the oracle with gcc (OpenMP over rows), and its float32 build.  Returns the
+    path of the FP64 library."""
+    for lib, extra in ((_LIB, []), (_LIB32, ["-DORC_REAL=float", "-fsingle-precision-constant"])):
+        if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+            cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
+                   *extra, "-o", lib + ".tmp", _SRC, "-lm"]
+            subprocess.run(cmd, check=True)
+            os.replace(lib + ".tmp", lib)
     return _LIB
 
 
@@ -245,3 +249,75 @@ def rel_l2(phi, phi_ref):
     """Relative L2 error of Eq. err."""
     phi, phi_ref = np.asarray(phi, np.float64), np.asarray(phi_ref, np.float64)
     return float(np.sqrt(((phi - phi_ref) ** 2).sum() / (phi_ref ** 2).sum()))
+
+
+# --- the float32 build (sensitivity runs) ----------------------------------------------
+
+class _Params32(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_float if t is ctypes.c_double else t) for n, t in _Params._fields_]
+
+
+_lib32 = None
+_F = ctypes.POINTER(ctypes.c_float)
+
+
+def _load32():
+    global _lib32
+    if _lib32 is None:
+        if not os.path.exists(_LIB32):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB32)
+        P = ctypes.POINTER(_Params32)
+        lib.orc_init.argtypes = [P, _F, _F, _F, _F, _F]
+        lib.orc_run.argtypes = [P, _F, _F, _F, _F, _F, ctypes.c_long, _F, ctypes.POINTER(ctypes.c_int)]
+        lib.orc_set_num_threads.argtypes = [ctypes.c_int]
+        _lib32 = lib
+    return _lib32
+
+
+def _p32(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float32 and a.flags.c_contiguous
+    return a.ctypes.data_as(_F)
+
+
+def _f32(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float32)
+
+
+class State32:
+    """The oracle's code compiled with float32 arithmetic (``orc_real = float``): the same
+    method, steps and order as ``State``, every operation rounded to float32.  Not a
+    reference: its distance from the FP64 ``State`` measures how far float32 evaluation
+    of the method drifts over a run, which sets the tolerance of long unstable runs.
+    Populations ``g`` (and ``f``) are float32 arrays; ``phi`` sums them in FP64."""
+
+    def __init__(self, p: Params, phi0, ux=None, uy=None, tf=None):
+        assert p.model != 3, "model 3 history is not wrapped for the float32 build"
+        self.p = p
+        self.c32 = _Params32(*[getattr(p, f.name) for f in dataclasses.fields(p)])
+        self.ux, self.uy, self.tf = _f32(ux), _f32(uy), _f32(tf)
+        self.n = 0
+        phi0 = _f32(phi0)
+        self.g = np.zeros((9, p.ny, p.nx), dtype=np.float32)
+        self.f = np.zeros((9, p.ny, p.nx), dtype=np.float32) if p.ns else None
+        f0 = 1.0 if self.tf is None else float(self.tf[0])
+        u0 = None if self.ux is None else _f32(f0 * self.ux)
+        v0 = None if self.uy is None else _f32(f0 * self.uy)
+        _load32().orc_init(ctypes.byref(self.c32), _p32(phi0), _p32(u0), _p32(v0),
+                           _p32(self.g), _p32(self.f))
+
+    def run(self, nsteps: int) -> "State32":
+        tf = None
+        if self.tf is not None:
+            assert self.n + nsteps <= len(self.tf), "time-factor table too short"
+            tf = np.ascontiguousarray(self.tf[self.n:self.n + nsteps])
+        _load32().orc_run(ctypes.byref(self.c32), _p32(self.g), _p32(self.f), _p32(self.ux),
+                          _p32(self.uy), _p32(tf), int(nsteps), None, None)
+        self.n += nsteps
+        return self
+
+    @property
+    def phi(self):
+        return self.g.astype(np.float64).sum(axis=0)

@@ -20,9 +20,9 @@
 static const int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 static const int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
-static const double W[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+static const orc_real W[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                             1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-static const double CS2 = 1.0 / 3.0; /* c_s^2 = c^2/3 with c = 1 */
+static const orc_real CS2 = 1.0 / 3.0; /* c_s^2 = c^2/3 with c = 1 */
 
 int orc_num_threads(void) {
 #ifdef _OPENMP
@@ -43,9 +43,9 @@ void orc_set_num_threads(int n) {
 /* ---------------------------------------------------------------- parameters */
 
 int orc_coeffs_from(const orc_params* p, orc_coeffs* c) {
-  double dphi = p->phi_a - p->phi_b;
+  orc_real dphi = p->phi_a - p->phi_b;
   if (!(p->tau_g > 0.5) || dphi == 0.0) return -1;
-  double ad = fabs(dphi);
+  orc_real ad = fabs(dphi);
   /* Eq. betakappa */
   c->beta = 12.0 * p->sigma / (p->width * ad * ad * ad * ad);
   c->kappa = 3.0 * p->sigma * p->width / (2.0 * ad * ad);
@@ -62,28 +62,28 @@ int orc_coeffs_from(const orc_params* p, orc_coeffs* c) {
 /* ---------------------------------------------------------- node primitives */
 
 /* s_i(u) = c_i.u/cs^2 + (c_i.u)^2/(2 cs^4) - u^2/(2 cs^2), the bracket of Eq. geq. */
-static double s_poly(int i, double ux, double uy) {
-  double cu = CX[i] * ux + CY[i] * uy;
-  double u2 = ux * ux + uy * uy;
+static orc_real s_poly(int i, orc_real ux, orc_real uy) {
+  orc_real cu = CX[i] * ux + CY[i] * uy;
+  orc_real u2 = ux * ux + uy * uy;
   return cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - u2 / (2.0 * CS2);
 }
 
 /* Eq. geq. */
-void orc_equilibrium_g(double phi, double mu, double ux, double uy, double eta, double geq[9]) {
-  double u2 = ux * ux + uy * uy;
+void orc_equilibrium_g(orc_real phi, orc_real mu, orc_real ux, orc_real uy, orc_real eta, orc_real geq[9]) {
+  orc_real u2 = ux * ux + uy * uy;
   geq[0] = phi + (W[0] - 1.0) * eta * mu - W[0] * phi * u2 / (2.0 * CS2);
   for (int i = 1; i < 9; ++i) geq[i] = W[i] * eta * mu + W[i] * phi * s_poly(i, ux, uy);
 }
 
 /* Eq. liangFi: S_i = w_i c_i . F / cs^2. */
-void orc_source_g(double fx, double fy, double s[9]) {
+void orc_source_g(orc_real fx, orc_real fy, orc_real s[9]) {
   for (int i = 0; i < 9; ++i) s[i] = W[i] * (CX[i] * fx + CY[i] * fy) / CS2;
 }
 
 /* Navier-Stokes equilibrium (pressure-based incompressible form):
  * f_0 = (w_0 - 1) p/cs^2 + rho w_0 s_0(u),  f_i = w_i p/cs^2 + rho w_i s_i(u),
  * so that sum f = 0, sum c f = rho u, sum c c f = p I + rho u u. */
-void orc_equilibrium_f(double p, double rho, double ux, double uy, double feq[9]) {
+void orc_equilibrium_f(orc_real p, orc_real rho, orc_real ux, orc_real uy, orc_real feq[9]) {
   feq[0] = (W[0] - 1.0) * p / CS2 + rho * W[0] * s_poly(0, ux, uy);
   for (int i = 1; i < 9; ++i) feq[i] = W[i] * p / CS2 + rho * W[i] * s_poly(i, ux, uy);
 }
@@ -91,13 +91,13 @@ void orc_equilibrium_f(double p, double rho, double ux, double uy, double feq[9]
 /* Navier-Stokes forcing with moments sum G = u.grad rho, sum c G = F,
  * sum c c G = u F + F u + cs^2 (u.grad rho I + u grad rho + grad rho u):
  * G_i = w_i [ (c_i - u).F/cs^2 + (c_i.u)(c_i.F)/cs^4 + (c_i.u)(c_i.grad rho)/cs^2 ]. */
-void orc_source_f(double fx, double fy, double ux, double uy, double drx, double dry,
-                  double s[9]) {
+void orc_source_f(orc_real fx, orc_real fy, orc_real ux, orc_real uy, orc_real drx, orc_real dry,
+                  orc_real s[9]) {
   for (int i = 0; i < 9; ++i) {
-    double cu = CX[i] * ux + CY[i] * uy;
-    double cf = CX[i] * fx + CY[i] * fy;
-    double cr = CX[i] * drx + CY[i] * dry;
-    double cmuf = (CX[i] - ux) * fx + (CY[i] - uy) * fy;
+    orc_real cu = CX[i] * ux + CY[i] * uy;
+    orc_real cf = CX[i] * fx + CY[i] * fy;
+    orc_real cr = CX[i] * drx + CY[i] * dry;
+    orc_real cmuf = (CX[i] - ux) * fx + (CY[i] - uy) * fy;
     s[i] = W[i] * (cmuf / CS2 + cu * cf / (CS2 * CS2) + cu * cr / CS2);
   }
 }
@@ -109,7 +109,7 @@ static size_t nn(const orc_params* p) { return (size_t)p->nx * (size_t)p->ny; }
 /* Value of a grid field at any (x, y): x periodic; y periodic, or mirrored across
  * the walls at y = -1/2 and y = ny - 1/2 with the given parity (+1 for phi, mu, p;
  * -1 for the velocity, whose no-slip value on the wall is zero). */
-static double at(const orc_params* p, const double* a, int parity, int x, int y) {
+static orc_real at(const orc_params* p, const orc_real* a, int parity, int x, int y) {
   int nx = p->nx, ny = p->ny;
   x = ((x % nx) + nx) % nx;
   if (!p->walls) {
@@ -125,11 +125,11 @@ static double at(const orc_params* p, const double* a, int parity, int x, int y)
  *   d_a psi(x) = (1/cs^2) sum_i w_i c_ia psi(x + c_i)
  *   lap psi(x) = (2/cs^2) sum_i w_i [psi(x + c_i) - psi(x)]
  * The gradient is exact for quadratics and the Laplacian for cubics. */
-static void grad_at(const orc_params* p, const double* a, int parity, int x, int y,
-                    double* gx, double* gy) {
-  double sx = 0.0, sy = 0.0;
+static void grad_at(const orc_params* p, const orc_real* a, int parity, int x, int y,
+                    orc_real* gx, orc_real* gy) {
+  orc_real sx = 0.0, sy = 0.0;
   for (int i = 1; i < 9; ++i) {
-    double v = at(p, a, parity, x + CX[i], y + CY[i]);
+    orc_real v = at(p, a, parity, x + CX[i], y + CY[i]);
     sx += W[i] * CX[i] * v;
     sy += W[i] * CY[i] * v;
   }
@@ -137,14 +137,14 @@ static void grad_at(const orc_params* p, const double* a, int parity, int x, int
   *gy = sy / CS2;
 }
 
-static double lap_at(const orc_params* p, const double* a, int parity, int x, int y) {
-  double c = at(p, a, parity, x, y);
-  double s = 0.0;
+static orc_real lap_at(const orc_params* p, const orc_real* a, int parity, int x, int y) {
+  orc_real c = at(p, a, parity, x, y);
+  orc_real s = 0.0;
   for (int i = 1; i < 9; ++i) s += W[i] * (at(p, a, parity, x + CX[i], y + CY[i]) - c);
   return 2.0 * s / CS2;
 }
 
-void orc_grad(const orc_params* p, const double* psi, int parity, double* gx, double* gy) {
+void orc_grad(const orc_params* p, const orc_real* psi, int parity, orc_real* gx, orc_real* gy) {
 #pragma omp parallel for schedule(static)
   for (int y = 0; y < p->ny; ++y)
     for (int x = 0; x < p->nx; ++x) {
@@ -153,19 +153,19 @@ void orc_grad(const orc_params* p, const double* psi, int parity, double* gx, do
     }
 }
 
-void orc_lap(const orc_params* p, const double* psi, int parity, double* out) {
+void orc_lap(const orc_params* p, const orc_real* psi, int parity, orc_real* out) {
 #pragma omp parallel for schedule(static)
   for (int y = 0; y < p->ny; ++y)
     for (int x = 0; x < p->nx; ++x) out[(size_t)y * p->nx + x] = lap_at(p, psi, parity, x, y);
 }
 
 /* df/dphi of Eq. bulk: 2 beta (phi - phi_A)(phi - phi_B)(2 phi - phi_A - phi_B). */
-static double dbulk(const orc_params* p, const orc_coeffs* c, double phi) {
+static orc_real dbulk(const orc_params* p, const orc_coeffs* c, orc_real phi) {
   return 2.0 * c->beta * (phi - p->phi_a) * (phi - p->phi_b) * (2.0 * phi - p->phi_a - p->phi_b);
 }
 
 /* Eq. mu. */
-void orc_chemical_potential(const orc_params* p, const double* phi, double* mu) {
+void orc_chemical_potential(const orc_params* p, const orc_real* phi, orc_real* mu) {
   orc_coeffs c;
   orc_coeffs_from(p, &c);
 #pragma omp parallel for schedule(static)
@@ -177,13 +177,13 @@ void orc_chemical_potential(const orc_params* p, const double* phi, double* mu) 
 }
 
 /* Eq. macroscopicg. */
-static void order_parameter(const orc_params* p, const double* g, double* phi) {
+static void order_parameter(const orc_params* p, const orc_real* g, orc_real* phi) {
   size_t n = nn(p);
 #pragma omp parallel for schedule(static)
   for (int y = 0; y < p->ny; ++y)
     for (int x = 0; x < p->nx; ++x) {
       size_t k = (size_t)y * p->nx + x;
-      double s = 0.0;
+      orc_real s = 0.0;
       for (int i = 0; i < 9; ++i) s += g[i * n + k];
       phi[k] = s;
     }
@@ -192,7 +192,7 @@ static void order_parameter(const orc_params* p, const double* g, double* phi) {
 /* Streaming g_i(x + c_i, t + 1) = g_i*(x, t) in pull form; with walls a
  * population whose source lies beyond a wall is the one that left the same node in
  * the opposite direction (half-way bounce-back). */
-static void stream(const orc_params* p, const double* post, double* out) {
+static void stream(const orc_params* p, const orc_real* post, orc_real* out) {
   size_t n = nn(p);
   int nx = p->nx, ny = p->ny;
 #pragma omp parallel for schedule(static)
@@ -212,17 +212,17 @@ static void stream(const orc_params* p, const double* post, double* out) {
 /* ------------------------------------------------------------------- method */
 
 typedef struct {
-  double *phi, *mu, *mux, *muy, *lapmu, *phx, *phy; /* order parameter and derived   */
-  double *gux, *guy, *gvx, *gvy;                    /* gradient of a prescribed u   */
-  const double *ux0, *uy0;                          /* base field of a prescribed u */
-  double dtf;                                       /* d/dt of its time factor      */
-  double *u, *v, *pr, *px, *py;                     /* velocity and pressure         */
-  double *qx, *qy, *dext;                           /* phi u and its divergence      */
-  double *fx, *fy, *ftx, *fty;                      /* CH force F; NS total force    */
-  double* post;                                     /* post-collision populations    */
+  orc_real *phi, *mu, *mux, *muy, *lapmu, *phx, *phy; /* order parameter and derived   */
+  orc_real *gux, *guy, *gvx, *gvy;                    /* gradient of a prescribed u   */
+  const orc_real *ux0, *uy0;                          /* base field of a prescribed u */
+  orc_real dtf;                                       /* d/dt of its time factor      */
+  orc_real *u, *v, *pr, *px, *py;                     /* velocity and pressure         */
+  orc_real *qx, *qy, *dext;                           /* phi u and its divergence      */
+  orc_real *fx, *fy, *ftx, *fty;                      /* CH force F; NS total force    */
+  orc_real* post;                                     /* post-collision populations    */
 } orc_work;
 
-static double* zalloc(size_t n) { return (double*)calloc(n, sizeof(double)); }
+static orc_real* zalloc(size_t n) { return (orc_real*)calloc(n, sizeof(orc_real)); }
 
 static void work_alloc(const orc_params* p, orc_work* w) {
   size_t n = nn(p);
@@ -237,7 +237,7 @@ static void work_alloc(const orc_params* p, orc_work* w) {
 }
 
 static void work_free(orc_work* w) {
-  double* all[] = {w->phi, w->mu, w->mux, w->muy, w->lapmu, w->phx, w->phy, w->u, w->v,
+  orc_real* all[] = {w->phi, w->mu, w->mux, w->muy, w->lapmu, w->phx, w->phy, w->u, w->v,
                    w->pr, w->px, w->py, w->qx, w->qy, w->dext, w->fx, w->fy, w->ftx,
                    w->fty, w->gux, w->guy, w->gvx, w->gvy, w->post};
   for (size_t i = 0; i < sizeof(all) / sizeof(all[0]); ++i) free(all[i]);
@@ -249,32 +249,32 @@ static void work_free(orc_work* w) {
  * momentum balance that the LBE recovers into the non-conservative Eq. NS(b);
  * rho u = sum_i c_i f_i + F/2 (solved for u); and
  * p = cs^2/(1 - w_0) [sum_{i>0} f_i + u.grad rho / 2 + rho w_0 s_0(u)]. */
-static void ns_velocity_pressure(const orc_params* p, const orc_coeffs* c, const double* f,
+static void ns_velocity_pressure(const orc_params* p, const orc_coeffs* c, const orc_real* f,
                                  orc_work* w) {
   size_t n = nn(p);
-  double rho_mean = 0.5 * (p->rho_a + p->rho_b);
+  orc_real rho_mean = 0.5 * (p->rho_a + p->rho_b);
 #pragma omp parallel for schedule(static)
   for (int y = 0; y < p->ny; ++y)
     for (int x = 0; x < p->nx; ++x) {
       size_t k = (size_t)y * p->nx + x;
-      double phi = w->phi[k];
-      double rho = c->a * phi + c->b;
-      double fsx = -phi * w->mux[k], fsy = -phi * w->muy[k];
-      double fbx = rho * p->accel_x, fby = -(rho - rho_mean) * p->gravity;
-      double mx = 0.0, my = 0.0;
+      orc_real phi = w->phi[k];
+      orc_real rho = c->a * phi + c->b;
+      orc_real fsx = -phi * w->mux[k], fsy = -phi * w->muy[k];
+      orc_real fbx = rho * p->accel_x, fby = -(rho - rho_mean) * p->gravity;
+      orc_real mx = 0.0, my = 0.0;
       for (int i = 0; i < 9; ++i) {
         mx += CX[i] * f[i * n + k];
         my += CY[i] * f[i * n + k];
       }
-      double corr = c->a * p->mobility * w->lapmu[k];
-      double ux = (mx + 0.5 * (fsx + fbx)) / (rho - 0.5 * corr);
-      double uy = (my + 0.5 * (fsy + fby)) / (rho - 0.5 * corr);
+      orc_real corr = c->a * p->mobility * w->lapmu[k];
+      orc_real ux = (mx + 0.5 * (fsx + fbx)) / (rho - 0.5 * corr);
+      orc_real uy = (my + 0.5 * (fsy + fby)) / (rho - 0.5 * corr);
       w->u[k] = ux;
       w->v[k] = uy;
       w->ftx[k] = fsx + fbx + ux * corr;
       w->fty[k] = fsy + fby + uy * corr;
-      double drx = c->a * w->phx[k], dry = c->a * w->phy[k];
-      double s = 0.0;
+      orc_real drx = c->a * w->phx[k], dry = c->a * w->phy[k];
+      orc_real s = 0.0;
       for (int i = 1; i < 9; ++i) s += f[i * n + k];
       w->pr[k] = CS2 / (1.0 - W[0]) *
                  (s + 0.5 * (ux * drx + uy * dry) + rho * W[0] * s_poly(0, ux, uy));
@@ -283,12 +283,12 @@ static void ns_velocity_pressure(const orc_params* p, const orc_coeffs* c, const
 
 /* Order parameter, chemical potential and their gradients for the current g. */
 /* Sensitivity runs (round_f32): round a field to float32, as the GPU path holds it. */
-static void to_f32(const orc_params* p, double* a, size_t n) {
+static void to_f32(const orc_params* p, orc_real* a, size_t n) {
   if (!p->round_f32) return;
-  for (size_t k = 0; k < n; ++k) a[k] = (double)(float)a[k];
+  for (size_t k = 0; k < n; ++k) a[k] = (orc_real)(float)a[k];
 }
 
-static void phase_fields(const orc_params* p, const orc_coeffs* c, const double* g, orc_work* w) {
+static void phase_fields(const orc_params* p, const orc_coeffs* c, const orc_real* g, orc_work* w) {
   (void)c;
   order_parameter(p, g, w->phi);
   to_f32(p, w->phi, nn(p));
@@ -302,8 +302,8 @@ static void phase_fields(const orc_params* p, const orc_coeffs* c, const double*
 }
 
 /* Velocity at step n: prescribed (factor times base field) or from the NS populations. */
-static void velocity_fields(const orc_params* p, const orc_coeffs* c, const double* f,
-                            const double* ux, const double* uy, double tfac, orc_work* w) {
+static void velocity_fields(const orc_params* p, const orc_coeffs* c, const orc_real* f,
+                            const orc_real* ux, const orc_real* uy, orc_real tfac, orc_work* w) {
   size_t n = nn(p);
   if (p->ns) {
     ns_velocity_pressure(p, c, f, w);
@@ -325,11 +325,11 @@ static void velocity_fields(const orc_params* p, const orc_coeffs* c, const doub
 /* F = F1 (+ F2): Eq. t0-phiu and Eq. mark3 (model 2) or Eq. F2-1 (model 3).  For
  * model 3, hist holds F1 and grad mu of the previous step (planes F1x, F1y, mux, muy)
  * and *hist_valid says whether there was one. */
-static void ch_force(const orc_params* p, const orc_coeffs* c, orc_work* w, double* hist,
+static void ch_force(const orc_params* p, const orc_coeffs* c, orc_work* w, orc_real* hist,
                      int* hist_valid) {
   size_t n = nn(p);
   int nx = p->nx, ny = p->ny;
-  double rho_mean = 0.5 * (p->rho_a + p->rho_b);
+  orc_real rho_mean = 0.5 * (p->rho_a + p->rho_b);
   /* F1 = (phi/rho) (F_s + F_b - grad p), F_s = -phi grad mu.  With a prescribed
    * velocity there is no pressure field or body force: grad p = 0, F_b = 0. */
   if (p->f1_form == 1 && !p->ns) {
@@ -340,9 +340,9 @@ static void ch_force(const orc_params* p, const orc_coeffs* c, orc_work* w, doub
     orc_grad(p, w->v, -1, w->gvx, w->gvy);
 #pragma omp parallel for schedule(static)
     for (size_t k = 0; k < n; ++k) {
-      double dtu = w->ux0 ? w->dtf * w->ux0[k] : 0.0, dtv = w->uy0 ? w->dtf * w->uy0[k] : 0.0;
-      double ax = dtu + w->u[k] * w->gux[k] + w->v[k] * w->guy[k];
-      double ay = dtv + w->u[k] * w->gvx[k] + w->v[k] * w->gvy[k];
+      orc_real dtu = w->ux0 ? w->dtf * w->ux0[k] : 0.0, dtv = w->uy0 ? w->dtf * w->uy0[k] : 0.0;
+      orc_real ax = dtu + w->u[k] * w->gux[k] + w->v[k] * w->guy[k];
+      orc_real ay = dtv + w->u[k] * w->gvx[k] + w->v[k] * w->gvy[k];
       w->fx[k] = w->phi[k] * ax;
       w->fy[k] = w->phi[k] * ay;
     }
@@ -351,10 +351,10 @@ static void ch_force(const orc_params* p, const orc_coeffs* c, orc_work* w, doub
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
       size_t k = (size_t)y * nx + x;
-      double phi = w->phi[k];
-      double rho = c->a * phi + c->b;
-      double tx = -phi * w->mux[k] - w->px[k];
-      double ty = -phi * w->muy[k] - w->py[k];
+      orc_real phi = w->phi[k];
+      orc_real rho = c->a * phi + c->b;
+      orc_real tx = -phi * w->mux[k] - w->px[k];
+      orc_real ty = -phi * w->muy[k] - w->py[k];
       if (p->ns) {
         tx += rho * p->accel_x;
         ty += -(rho - rho_mean) * p->gravity;
@@ -368,16 +368,16 @@ static void ch_force(const orc_params* p, const orc_coeffs* c, orc_work* w, doub
    * scale, as Remarks I and II allow) as differences over the last step; zero on the
    * first step, which has no earlier state. */
   if (p->model == 3) {
-    double cA = 2.0 * p->tau_g - 1.0 + 3.0 * c->K;
-    double cB = 3.0 * CS2 * c->eta * c->K;
+    orc_real cA = 2.0 * p->tau_g - 1.0 + 3.0 * c->K;
+    orc_real cB = 3.0 * CS2 * c->eta * c->K;
     int valid = hist_valid ? *hist_valid : 0;
 #pragma omp parallel for schedule(static)
     for (size_t k = 0; k < n; ++k) {
-      double f1x = w->fx[k], f1y = w->fy[k];
-      double dF1x = valid ? f1x - hist[k] : 0.0;
-      double dF1y = valid ? f1y - hist[n + k] : 0.0;
-      double dmux = valid ? w->mux[k] - hist[2 * n + k] : 0.0;
-      double dmuy = valid ? w->muy[k] - hist[3 * n + k] : 0.0;
+      orc_real f1x = w->fx[k], f1y = w->fy[k];
+      orc_real dF1x = valid ? f1x - hist[k] : 0.0;
+      orc_real dF1y = valid ? f1y - hist[n + k] : 0.0;
+      orc_real dmux = valid ? w->mux[k] - hist[2 * n + k] : 0.0;
+      orc_real dmuy = valid ? w->muy[k] - hist[3 * n + k] : 0.0;
       hist[k] = f1x;
       hist[n + k] = f1y;
       hist[2 * n + k] = w->mux[k];
@@ -401,7 +401,7 @@ static void ch_force(const orc_params* p, const orc_coeffs* c, orc_work* w, doub
 #pragma omp parallel for schedule(static)
   for (int y = ylo; y <= yhi; ++y)
     for (int x = 0; x < nx; ++x) {
-      double ax, ay, bx, by;
+      orc_real ax, ay, bx, by;
       grad_at(p, w->qx, -1, x, y, &ax, &ay);
       grad_at(p, w->qy, -1, x, y, &bx, &by);
       w->dext[(size_t)(y + 1) * nx + x] = ax + by;
@@ -410,12 +410,12 @@ static void ch_force(const orc_params* p, const orc_coeffs* c, orc_work* w, doub
 #pragma omp parallel for schedule(static)
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
-      double sx = 0.0, sy = 0.0;
+      orc_real sx = 0.0, sy = 0.0;
       for (int i = 1; i < 9; ++i) {
         int xx = ((x + CX[i]) % nx + nx) % nx;
         int yy = y + CY[i];
         if (!p->walls) yy = (yy % ny + ny) % ny;
-        double d = w->dext[(size_t)(yy + 1) * nx + xx];
+        orc_real d = w->dext[(size_t)(yy + 1) * nx + xx];
         sx += W[i] * CX[i] * d;
         sy += W[i] * CY[i] * d;
       }
@@ -426,15 +426,15 @@ static void ch_force(const orc_params* p, const orc_coeffs* c, orc_work* w, doub
 }
 
 /* Eq. LB collision for g (and the NS collision for f), then streaming. */
-static void collide_stream(const orc_params* p, const orc_coeffs* c, double* g, double* f,
+static void collide_stream(const orc_params* p, const orc_coeffs* c, orc_real* g, orc_real* f,
                            orc_work* w) {
   size_t n = nn(p);
-  double tg = p->tau_g;
+  orc_real tg = p->tau_g;
 #pragma omp parallel for schedule(static)
   for (int y = 0; y < p->ny; ++y)
     for (int x = 0; x < p->nx; ++x) {
       size_t k = (size_t)y * p->nx + x;
-      double geq[9], s[9];
+      orc_real geq[9], s[9];
       orc_equilibrium_g(w->phi[k], w->mu[k], w->u[k], w->v[k], c->eta, geq);
       orc_source_g(w->fx[k], w->fy[k], s);
       for (int i = 0; i < 9; ++i)
@@ -442,13 +442,13 @@ static void collide_stream(const orc_params* p, const orc_coeffs* c, double* g, 
     }
   stream(p, w->post, g);
   if (!p->ns) return;
-  double tf = p->tau_f;
+  orc_real tf = p->tau_f;
 #pragma omp parallel for schedule(static)
   for (int y = 0; y < p->ny; ++y)
     for (int x = 0; x < p->nx; ++x) {
       size_t k = (size_t)y * p->nx + x;
-      double feq[9], s[9];
-      double rho = c->a * w->phi[k] + c->b;
+      orc_real feq[9], s[9];
+      orc_real rho = c->a * w->phi[k] + c->b;
       orc_equilibrium_f(w->pr[k], rho, w->u[k], w->v[k], feq);
       orc_source_f(w->ftx[k], w->fty[k], w->u[k], w->v[k], c->a * w->phx[k], c->a * w->phy[k], s);
       for (int i = 0; i < 9; ++i)
@@ -457,19 +457,19 @@ static void collide_stream(const orc_params* p, const orc_coeffs* c, double* g, 
   stream(p, w->post, f);
 }
 
-void orc_init(const orc_params* p, const double* phi0, const double* ux0, const double* uy0,
-              double* g, double* f) {
+void orc_init(const orc_params* p, const orc_real* phi0, const orc_real* ux0, const orc_real* uy0,
+              orc_real* g, orc_real* f) {
   orc_coeffs c;
   orc_coeffs_from(p, &c);
   size_t n = nn(p);
-  double* mu = zalloc(n);
+  orc_real* mu = zalloc(n);
   orc_chemical_potential(p, phi0, mu);
   for (size_t k = 0; k < n; ++k) {
-    double geq[9];
+    orc_real geq[9];
     orc_equilibrium_g(phi0[k], mu[k], ux0 ? ux0[k] : 0.0, uy0 ? uy0[k] : 0.0, c.eta, geq);
     for (int i = 0; i < 9; ++i) g[i * n + k] = geq[i];
     if (p->ns && f) {
-      double feq[9];
+      orc_real feq[9];
       orc_equilibrium_f(0.0, c.a * phi0[k] + c.b, ux0 ? ux0[k] : 0.0, uy0 ? uy0[k] : 0.0, feq);
       for (int i = 0; i < 9; ++i) f[i * n + k] = feq[i];
     }
@@ -477,8 +477,8 @@ void orc_init(const orc_params* p, const double* phi0, const double* ux0, const 
   free(mu);
 }
 
-void orc_run(const orc_params* p, double* g, double* f, const double* ux, const double* uy,
-             const double* tf, long nsteps, double* hist, int* hist_valid) {
+void orc_run(const orc_params* p, orc_real* g, orc_real* f, const orc_real* ux, const orc_real* uy,
+             const orc_real* tf, long nsteps, orc_real* hist, int* hist_valid) {
   orc_coeffs c;
   if (orc_coeffs_from(p, &c) != 0) return;
   if (p->model == 3 && (!hist || !hist_valid)) return;
@@ -502,9 +502,9 @@ void orc_run(const orc_params* p, double* g, double* f, const double* ux, const 
   work_free(&w);
 }
 
-void orc_fields(const orc_params* p, const double* g, const double* f, const double* ux,
-                const double* uy, double tfac, double* phi, double* mu, double* u, double* v,
-                double* pr) {
+void orc_fields(const orc_params* p, const orc_real* g, const orc_real* f, const orc_real* ux,
+                const orc_real* uy, orc_real tfac, orc_real* phi, orc_real* mu, orc_real* u, orc_real* v,
+                orc_real* pr) {
   orc_coeffs c;
   orc_coeffs_from(p, &c);
   orc_work w;
@@ -512,29 +512,29 @@ void orc_fields(const orc_params* p, const double* g, const double* f, const dou
   size_t n = nn(p);
   phase_fields(p, &c, g, &w);
   velocity_fields(p, &c, f, ux, uy, tfac, &w);
-  if (phi) memcpy(phi, w.phi, n * sizeof(double));
-  if (mu) memcpy(mu, w.mu, n * sizeof(double));
-  if (u) memcpy(u, w.u, n * sizeof(double));
-  if (v) memcpy(v, w.v, n * sizeof(double));
-  if (pr) memcpy(pr, w.pr, n * sizeof(double));
+  if (phi) memcpy(phi, w.phi, n * sizeof(orc_real));
+  if (mu) memcpy(mu, w.mu, n * sizeof(orc_real));
+  if (u) memcpy(u, w.u, n * sizeof(orc_real));
+  if (v) memcpy(v, w.v, n * sizeof(orc_real));
+  if (pr) memcpy(pr, w.pr, n * sizeof(orc_real));
   work_free(&w);
 }
 
-void orc_diag(const orc_params* p, const double* phi, const double* phi_ref, double out[8]) {
+void orc_diag(const orc_params* p, const orc_real* phi, const orc_real* phi_ref, orc_real out[8]) {
   orc_coeffs c;
   orc_coeffs_from(p, &c);
-  double s = 0, sa = 0, e = 0, d2 = 0, r2 = 0, mx = -INFINITY, mn = INFINITY, bad = 0;
+  orc_real s = 0, sa = 0, e = 0, d2 = 0, r2 = 0, mx = -INFINITY, mn = INFINITY, bad = 0;
   for (int y = 0; y < p->ny; ++y)
     for (int x = 0; x < p->nx; ++x) {
       size_t k = (size_t)y * p->nx + x;
-      double v = phi[k];
+      orc_real v = phi[k];
       if (!isfinite(v)) { bad += 1; continue; }
       s += v;
       sa += fabs(v);
       /* Eq. freeEnergy with the bulk density of Eq. bulk */
-      double gx, gy;
+      orc_real gx, gy;
       grad_at(p, phi, +1, x, y, &gx, &gy);
-      double fa = v - p->phi_a, fb = v - p->phi_b;
+      orc_real fa = v - p->phi_a, fb = v - p->phi_b;
       e += c.beta * fa * fa * fb * fb + 0.5 * c.kappa * (gx * gx + gy * gy);
       if (phi_ref) {
         d2 += (v - phi_ref[k]) * (v - phi_ref[k]);

@@ -39,6 +39,15 @@
 extern "C" {
 #endif
 
+/* The arithmetic type: double.  Built with -DORC_REAL=float (and single-precision
+ * constants) the same code runs in float32 arithmetic; that build is used only to
+ * measure how far evaluating the method in float32 drifts from FP64 over a long
+ * unstable run (the sensitivity that sets long-run tolerances), never as a reference. */
+#ifndef ORC_REAL
+#define ORC_REAL double
+#endif
+typedef ORC_REAL orc_real;
+
 typedef struct {
   int nx, ny;
   int walls;     /* 0: periodic in y; 1: no-slip walls below row 0 and above row ny-1 */
@@ -46,10 +55,10 @@ typedef struct {
                     3: F = F1 + F2 of Eq. F2-1 with the time derivatives as one-step
                     backward differences (Model-II at any tau_g)                       */
   int ns;        /* 0: prescribed velocity, grad p = 0; 1: coupled Navier-Stokes        */
-  double tau_g, mobility, sigma, width, phi_a, phi_b, rho_a, rho_b;
-  double tau_f;    /* NS relaxation time, nu = cs^2 (tau_f - 1/2)                      */
-  double gravity;  /* NS: acceleration g along -y, applied as -(rho - rho_mean) g        */
-  double accel_x;  /* NS: uniform acceleration along +x, applied as rho * accel_x        */
+  orc_real tau_g, mobility, sigma, width, phi_a, phi_b, rho_a, rho_b;
+  orc_real tau_f;    /* NS relaxation time, nu = cs^2 (tau_f - 1/2)                      */
+  orc_real gravity;  /* NS: acceleration g along -y, applied as -(rho - rho_mean) g        */
+  orc_real accel_x;  /* NS: uniform acceleration along +x, applied as rho * accel_x        */
   int f1_form;     /* reading of F1 with a prescribed velocity (ns = 0):
                       0: Eq. t0-phiu with grad p = 0, F1 = (phi/rho) F_s = -(phi^2/rho) grad mu;
                       1: Eq. cFi1 evaluated from the prescribed field, F1 = d_t(phi u) +
@@ -65,54 +74,54 @@ typedef struct {
 } orc_params;
 
 typedef struct {
-  double beta, kappa;  /* Eq. betakappa                    */
-  double eta;          /* M = cs^2 eta (tau_g - 1/2)        */
-  double K;            /* (tau - 1/6 - tau^2)/(tau - 1/2)   */
-  double a, b;         /* rho = a phi + b, Eq. rho          */
+  orc_real beta, kappa;  /* Eq. betakappa                    */
+  orc_real eta;          /* M = cs^2 eta (tau_g - 1/2)        */
+  orc_real K;            /* (tau - 1/6 - tau^2)/(tau - 1/2)   */
+  orc_real a, b;         /* rho = a phi + b, Eq. rho          */
 } orc_coeffs;
 
 /* Derived coefficients.  Returns 0, or -1 if tau_g <= 1/2 or phi_a == phi_b. */
 int orc_coeffs_from(const orc_params* p, orc_coeffs* c);
 
 /* Single-node building blocks (exposed so that the tests can pin them). */
-void orc_equilibrium_g(double phi, double mu, double ux, double uy, double eta, double geq[9]);
-void orc_source_g(double fx, double fy, double s[9]);
-void orc_equilibrium_f(double p, double rho, double ux, double uy, double feq[9]);
-void orc_source_f(double fx, double fy, double ux, double uy, double drx, double dry,
-                  double s[9]);
+void orc_equilibrium_g(orc_real phi, orc_real mu, orc_real ux, orc_real uy, orc_real eta, orc_real geq[9]);
+void orc_source_g(orc_real fx, orc_real fy, orc_real s[9]);
+void orc_equilibrium_f(orc_real p, orc_real rho, orc_real ux, orc_real uy, orc_real feq[9]);
+void orc_source_f(orc_real fx, orc_real fy, orc_real ux, orc_real uy, orc_real drx, orc_real dry,
+                  orc_real s[9]);
 
 /* Grid operators with the ghost rule of the boundary (periodic, or mirror with the
  * given parity +1/-1 across the walls).  Outputs are full nx*ny grids. */
-void orc_grad(const orc_params* p, const double* psi, int parity, double* gx, double* gy);
-void orc_lap(const orc_params* p, const double* psi, int parity, double* out);
+void orc_grad(const orc_params* p, const orc_real* psi, int parity, orc_real* gx, orc_real* gy);
+void orc_lap(const orc_params* p, const orc_real* psi, int parity, orc_real* out);
 
 /* Chemical potential of a phi field, Eq. mu with the bulk energy of Eq. bulk. */
-void orc_chemical_potential(const orc_params* p, const double* phi, double* mu);
+void orc_chemical_potential(const orc_params* p, const orc_real* phi, orc_real* mu);
 
 /* Initial populations: g_i = g_i^eq(phi0, mu[phi0], u0), no source; f_i = f_i^eq
  * (p = 0, rho(phi0), u0) when ns = 1.  u0 may be NULL (zero). */
-void orc_init(const orc_params* p, const double* phi0, const double* ux0, const double* uy0,
-              double* g, double* f);
+void orc_init(const orc_params* p, const orc_real* phi0, const orc_real* ux0, const orc_real* uy0,
+              orc_real* g, orc_real* f);
 
 /* Advance nsteps.  g (and f when ns = 1) hold the state on entry and exit.
  * Prescribed velocity at step n (from t_n to t_{n+1}) is tf[n]*ux, tf[n]*uy;
  * tf may be NULL (factor 1); ux/uy may be NULL (zero velocity).  Model 3 also needs
  * hist (4*nx*ny doubles: F1 and grad mu of the previous step, updated) and
  * *hist_valid (0 before the first step, set to 1); both may be NULL otherwise. */
-void orc_run(const orc_params* p, double* g, double* f, const double* ux, const double* uy,
-             const double* tf, long nsteps, double* hist, int* hist_valid);
+void orc_run(const orc_params* p, orc_real* g, orc_real* f, const orc_real* ux, const orc_real* uy,
+             const orc_real* tf, long nsteps, orc_real* hist, int* hist_valid);
 
 /* Macroscopic fields of a state.  For ns = 0 the velocity written is tfac*ux, tfac*uy
  * and p = 0.  Any output pointer may be NULL. */
-void orc_fields(const orc_params* p, const double* g, const double* f, const double* ux,
-                const double* uy, double tfac, double* phi, double* mu, double* u,
-                double* v, double* pr);
+void orc_fields(const orc_params* p, const orc_real* g, const orc_real* f, const orc_real* ux,
+                const orc_real* uy, orc_real tfac, orc_real* phi, orc_real* mu, orc_real* u,
+                orc_real* v, orc_real* pr);
 
 /* FP64 diagnostics of a phi field (phi_ref may be NULL):
  * out[0] sum phi, out[1] sum |phi|, out[2] free energy (Eq. freeEnergy),
  * out[3] sum (phi-phi_ref)^2, out[4] sum phi_ref^2, out[5] max phi, out[6] min phi,
  * out[7] number of non-finite values. */
-void orc_diag(const orc_params* p, const double* phi, const double* phi_ref, double out[8]);
+void orc_diag(const orc_params* p, const orc_real* phi, const orc_real* phi_ref, orc_real out[8]);
 
 /* Threads the OpenMP loops use (1 when built without OpenMP). */
 int orc_num_threads(void);

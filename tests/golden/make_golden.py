@@ -8,11 +8,13 @@ work, is well represented: about half of them where |phi| < 0.95 at the end of t
 run, a uniform draw over the lattice, and one whole lattice row crossing the
 interface (the row holding most interface nodes).
 
-For the Rayleigh-Taylor cases the oracle also runs a second time with its populations
-rounded to float32 after every step (the GPU path's storage precision); the sampled
-relative L2 distance between the two runs (sens_rel_l2) measures how much the growing
-instability amplifies perturbations of that size, and the long-run GPU tolerance is
-derived from it.
+For the Rayleigh-Taylor cases the run is repeated twice in float32: with the values the
+float32 path holds rounded to float32 where they are formed (round_f32; sens_rel_l2),
+and with the oracle's own code compiled in float32 arithmetic (State32; sens32_rel_l2).
+The sampled relative L2 distance of each from the FP64 run measures how far the
+growing instability carries float32 rounding; the long-run GPU tolerance is derived
+from the float32 build's (``--sens-only`` recomputes just these runs of an existing
+file).
 
     python tests/golden/make_golden.py vortex2048     # 2048^2, 1000 steps
     python tests/golden/make_golden.py vortex512      # 512^2, one period T = 20000
@@ -47,9 +49,7 @@ CASES = {
     "rt256_4000": (lambda: workloads.rayleigh_taylor_case(256, 1024, steps=4000), 4000, 1),
     # T = sqrt(L / (At g)) = 9051 steps for L = 256, At = 0.5, sqrt(g L) = 0.04
     "rt256_T": (lambda: workloads.rayleigh_taylor_case(256, 1024, steps=9051), 9051, 1),
-    "rtpaper25_40000": (lambda: workloads.rayleigh_taylor_case(256, 1024, steps=40000,
-                                                               reynolds=400.0, atwood=0.25),
-                        40000, 1),
+    "rtpaper25_40000": (lambda: workloads.rayleigh_taylor_paper(0.25, steps=40000), 40000, 1),
 }
 
 
@@ -74,28 +74,52 @@ def _state(w, p):
     return oracle.State(p, w.phi0)
 
 
-def make(name):
+def sensitivity(w, p, steps, idx, ref, have=None):
+    """Sampled distances of two float32 runs from the FP64 run at `idx` (values `ref`):
+    the oracle with its float32 values rounded where the float32 path holds them
+    (round_f32), and the oracle's own code compiled with float32 arithmetic (State32).
+    The round_f32 run is skipped when `have` already holds its results."""
+    rel = lambda x: float(np.sqrt(((x - ref) ** 2).sum() / (ref ** 2).sum()))
+    out = {}
+    if have and "sens_rel_l2" in have:
+        out = dict(sens_rel_l2=float(have["sens_rel_l2"]), sens_max_abs=float(have["sens_max_abs"]))
+    else:
+        r = _state(w, dataclasses.replace(p, round_f32=1)).run(steps).phi.ravel()[idx]
+        out = dict(sens_rel_l2=rel(r), sens_max_abs=float(np.abs(r - ref).max()))
+    if w.velocity is not None:
+        U, V = workloads.separable_field(w.velocity)
+        s32 = oracle.State32(p, w.phi0, U, V, w.velocity["tf"])
+    else:
+        s32 = oracle.State32(p, w.phi0)
+    q = s32.run(steps).phi.ravel()[idx]
+    out.update(sens32_rel_l2=rel(q), sens32_max_abs=float(np.abs(q - ref).max()))
+    print("float32-rounded rerun: sampled rel L2 %.3e; float32 build: %.3e" % (
+        out["sens_rel_l2"], out["sens32_rel_l2"]), flush=True)
+    return out
+
+
+def make(name, sens_only=False):
+    """Run case `name` and write its file; with sens_only, keep the FP64 results of the
+    existing file and recompute only its sensitivity runs."""
     build, steps, walls = CASES[name]
     w = build()
     p = oracle.Params(nx=w.nx, ny=w.ny, walls=walls, ns=1 if "tau_f" in w.phys else 0,
                       **w.phys)
+    out = os.path.join(HERE, "%s_oracle_%d.npz" % (name.split("_")[0], steps))
+    t0 = time.time()
+    if sens_only:
+        old = dict(np.load(out))
+        old.update(sensitivity(w, p, steps, old["index"], old["phi"], have=old))
+        np.savez_compressed(out, **old)
+        print(out, "sensitivity %.0fs" % (time.time() - t0))
+        return
     s = _state(w, p)
     d0 = oracle.diag(p, s.phi)
-    t0 = time.time()
     s.run(steps)
     phi = s.phi
     d = oracle.diag(p, phi, w.phi0)
     idx, row = sample_index(phi)
-    extra = {}
-    if p.ns:
-        pr = dataclasses.replace(p, round_f32=1)
-        sr = _state(w, pr).run(steps)
-        ref = phi.ravel()[idx]
-        extra = dict(sens_rel_l2=float(np.sqrt(((sr.phi.ravel()[idx] - ref) ** 2).sum()
-                                                / (ref ** 2).sum())),
-                     sens_max_abs=float(np.abs(sr.phi.ravel()[idx] - ref).max()))
-        print("float32-rounded rerun: sampled rel L2 %.3e" % extra["sens_rel_l2"])
-    out = os.path.join(HERE, "%s_oracle_%d.npz" % (name.split("_")[0], steps))
+    extra = sensitivity(w, p, steps, idx, phi.ravel()[idx]) if p.ns else {}
     np.savez_compressed(out, steps=steps, index=idx, phi=phi.ravel()[idx], row=row,
                         mass0=d0["mass"], abs_mass0=d0["abs_mass"], mass=d["mass"],
                         e_phi=np.sqrt(d["err2"] / d["ref2"]), max=d["max"], min=d["min"],
@@ -154,8 +178,10 @@ def make_adjoint(n=256, steps=2000):
 
 
 if __name__ == "__main__":
-    for n in sys.argv[1:] or ["vortex2048"]:
+    args = sys.argv[1:]
+    sens_only = "--sens-only" in args
+    for n in [a for a in args if a != "--sens-only"] or ["vortex2048"]:
         if n == "adjoint256":
             make_adjoint()
         else:
-            make(n)
+            make(n, sens_only)

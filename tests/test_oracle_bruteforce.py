@@ -192,3 +192,27 @@ def test_round_f32_rounds_where_the_gpu_holds_float32():
     assert np.array_equal(st.g, st.g.astype(np.float32).astype(np.float64))
     assert np.abs(st.g - ref).max() <= 1e-14
     assert np.abs(st.g - plain.g).max() > 1e-10
+
+
+def test_float32_build_is_the_same_method():
+    """The float32 build of the oracle (sensitivity runs only) is the same code in another
+    precision: a few steps agree with the FP64 oracle to float32 rounding, prescribed
+    flow (Model-II, tau = 0.8) and coupled Navier-Stokes with walls, and they do differ."""
+    n = 16
+    rng = np.random.default_rng(11)
+    phi0 = np.clip(rng.normal(0.0, 0.6, (n, n)), -1.2, 1.2)
+    ux = rng.uniform(-0.05, 0.05, (n, n))
+    uy = rng.uniform(-0.05, 0.05, (n, n))
+    p = oracle.Params(nx=n, ny=n, model=2, tau_g=0.8, mobility=0.02, sigma=0.01, width=3.0,
+                      rho_b=0.4)
+    a = oracle.State(p, phi0, ux, uy).run(3)
+    b = oracle.State32(p, phi0, ux, uy).run(3)
+    d = np.abs(a.g - b.g).max()
+    assert 0 < d <= 2e-6 and b.g.dtype == np.float32
+    import workloads
+    w = workloads.rayleigh_taylor_case(16, 48, steps=20, reynolds=100.0)
+    q = oracle.Params(nx=16, ny=48, walls=1, ns=1, **w.phys)
+    a = oracle.State(q, w.phi0).run(20)
+    b = oracle.State32(q, w.phi0).run(20)
+    assert 0 < np.abs(a.phi - b.phi).max() <= 1e-5
+    assert 0 < np.abs(a.f - b.f).max() <= 1e-7
