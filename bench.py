@@ -34,7 +34,8 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_LU = 72.0
 # sources of the fused step kernel: a counter summary is used only while they are unchanged
 KERNEL_SRC = (os.path.join(ROOT, "paper_1805_00007_amd", "csrc", "lbm_ch_step.hip"),
-              os.path.join(ROOT, "paper_1805_00007_amd", "csrc", "lbm_ch_device.h"))
+              os.path.join(ROOT, "paper_1805_00007_amd", "csrc", "lbm_ch_device.h"),
+              os.path.join(ROOT, "paper_1805_00007_amd", "csrc", "lbm_ch_stencil.h"))
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "phi_step_vortex2048_traffic.txt")
 GOLDEN = os.path.join(ROOT, "tests", "golden", "vortex2048_oracle_1000.npz")
 ADJ_GOLDEN = os.path.join(ROOT, "tests", "golden", "adjoint256_oracle_2000.npz")

@@ -54,6 +54,15 @@
  * the HIP runtime holds these until the batch or context is destroyed (or, for a
  * context, its graphs are dropped).
  *
+ * The calls
+ * ---------
+ * The core is lbm_ch_init, lbm_ch_step and lbm_ch_moments.  The FP64 reductions have
+ * a call of their own, lbm_ch_diagnostics, so that reading the fields never forces a
+ * reduction and a reduction needs no field buffers; the velocity inputs of lbm_ch_init
+ * travel in one struct (lbm_ch_velocity) because which of them are needed depends on
+ * the velocity mode.  The rest (state copies, tiles, graphs, autotuning, the adjoint
+ * and the batch) is optional.
+ *
  * Streams and errors
  * ------------------
  * Calls that take a stream enqueue their device work on it and return without
