@@ -164,9 +164,10 @@ static void apply_tiles(lbm_ch_ctx* c, int tx, int ty) {
 // Default: the widest tile (fewest halo columns), then the tallest (fewest halo rows
 // per row; heights 32 down to 1), that still gives at least 2 workgroups per CU on 256
 // CUs (float32), or 4 with 16-bit storage, whose extra decode work per byte needs more
-// waves in flight to cover memory latency.  With float32 storage the 512-column tile (8
-// waves per workgroup) is taken when it gives at least 1024 workgroups, i.e. on lattices
-// of 2048^2 and up, where it halves the halo columns of the 256-column tile.  Small lattices thus get
+// waves in flight to cover memory latency.  The 512-column tile (8 waves per workgroup)
+// is taken with float32 storage when it gives at least 1024 workgroups, and with 16-bit
+// storage when it gives at least 512 workgroups of 8 rows or more: on lattices of 2048^2
+// and up, where it halves the halo columns of the 256-column tile.  Small lattices thus get
 // short row chunks (each block's march is a chain of dependent loads), and the smallest
 // get 64 x 1.  lbm_ch_set_tiles overrides; lbm_ch_autotune measures.
 static void choose_tiles(lbm_ch_ctx* c) {
@@ -177,14 +178,18 @@ static void choose_tiles(lbm_ch_ctx* c) {
     apply_tiles(c, 64, 16);
     return;
   }
-  const long min_blocks = c->p.storage == LBM_CH_STORE_F32 ? 512 : 1024;
+  const bool f32 = c->p.storage == LBM_CH_STORE_F32;
+  const long min_blocks = f32 ? 512 : 1024;
   int tx = 64, ty = 1;
   bool found = false;
   for (int xx : {512, 256, 128, 64}) {
     if (xx > nx && xx > 64) continue;
-    if (xx == 512 && c->p.storage != LBM_CH_STORE_F32) continue;
-    const long need = xx == 512 ? 2 * min_blocks : min_blocks;
+    // 512 columns: at least 1024 blocks with float32 storage (2048^2: 512 x 8), at least
+    // 512 blocks of 8 rows or more with 16-bit storage (2048^2: 512 x 16, 58.2 us
+    // against 63.5 us at 256 x 16)
+    const long need = xx == 512 ? (f32 ? 2 * min_blocks : min_blocks / 2) : min_blocks;
     for (int yy : {32, 16, 8, 4, 2, 1}) {
+      if (xx == 512 && !f32 && yy < 8) break;
       const long nb = (long)((nx + xx - 1) / xx) * ((ny + yy - 1) / yy);
       if (nb >= need) {
         tx = xx;

@@ -76,11 +76,11 @@ def test_autotune_restores_state(lbm):
     assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("storage,expect", [(0, (512, 8)), (1, (256, 16)), (2, (256, 16))])
+@pytest.mark.parametrize("storage,expect", [(0, (512, 8)), (1, (512, 16)), (2, (512, 16))])
 def test_default_tiles(lbm, storage, expect):
     """Default tile of a 2048^2 lattice: the widest, then tallest, shape with at least 512
     blocks for float32 populations (1024 for the 512-column tile) and 1024 for 16-bit
-    ones."""
+    ones (512 blocks of 8 rows or more for the 512-column tile)."""
     w = workloads.metric2048(steps=1)
     s = lbm.solver_for(w, storage=storage)
     assert s.tiles == expect
