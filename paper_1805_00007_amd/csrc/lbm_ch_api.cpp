@@ -184,11 +184,13 @@ static void choose_tiles(lbm_ch_ctx* c) {
   bool found = false;
   for (int xx : {512, 256, 128, 64}) {
     if (xx > nx && xx > 64) continue;
-    // 512 columns: at least 1024 blocks with float32 storage (2048^2: 512 x 8), at least
-    // 512 blocks of 8 rows or more with 16-bit storage (2048^2: 512 x 16, 58.2 us
-    // against 63.5 us at 256 x 16)
+    // 512 columns: at least 1024 blocks of at most 16 rows with float32 storage (2048^2:
+    // 512 x 8; 4096^2: 512 x 16, 216 us against 219 us at 512 x 32; 7680^2: 512 x 16,
+    // 797 us against 825 us), at least 512 blocks of 8 rows or more with 16-bit storage
+    // (2048^2: 512 x 16, 58.2 us against 63.5 us at 256 x 16)
     const long need = xx == 512 ? (f32 ? 2 * min_blocks : min_blocks / 2) : min_blocks;
     for (int yy : {32, 16, 8, 4, 2, 1}) {
+      if (xx == 512 && f32 && yy > 16) continue;
       if (xx == 512 && !f32 && yy < 8) break;
       const long nb = (long)((nx + xx - 1) / xx) * ((ny + yy - 1) / yy);
       if (nb >= need) {

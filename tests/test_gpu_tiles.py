@@ -76,12 +76,15 @@ def test_autotune_restores_state(lbm):
     assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("storage,expect", [(0, (512, 8)), (1, (512, 16)), (2, (512, 16))])
-def test_default_tiles(lbm, storage, expect):
-    """Default tile of a 2048^2 lattice: the widest, then tallest, shape with at least 512
-    blocks for float32 populations (1024 for the 512-column tile) and 1024 for 16-bit
-    ones (512 blocks of 8 rows or more for the 512-column tile)."""
-    w = workloads.metric2048(steps=1)
+@pytest.mark.parametrize("n,storage,expect", [(2048, 0, (512, 8)), (2048, 1, (512, 16)),
+                                              (2048, 2, (512, 16)), (4096, 0, (512, 16))])
+def test_default_tiles(lbm, n, storage, expect):
+    """Default tile of an n^2 lattice: the widest, then tallest, shape with at least 512
+    blocks for float32 populations (1024 blocks of at most 16 rows for the 512-column
+    tile) and 1024 for 16-bit ones (512 blocks of 8 rows or more for the 512-column
+    tile)."""
+    w = workloads.metric2048(steps=1) if n == 2048 else workloads.vortex(n, period=80000,
+                                                                          steps=1)
     s = lbm.solver_for(w, storage=storage)
     assert s.tiles == expect
     s.close()
