@@ -37,31 +37,36 @@ KERNEL_SRC = (os.path.join(ROOT, "paper_1805_00007_amd", "csrc", "lbm_ch_step.hi
               os.path.join(ROOT, "paper_1805_00007_amd", "csrc", "lbm_ch_device.h"),
               os.path.join(ROOT, "paper_1805_00007_amd", "csrc", "lbm_ch_stencil.h"))
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "phi_step_vortex2048_traffic.txt")
+# the same for the coupled Rayleigh-Taylor step kernel
+RT_KERNEL_SRC = (os.path.join(ROOT, "paper_1805_00007_amd", "csrc", "lbm_ch_ns.hip"),
+                 os.path.join(ROOT, "paper_1805_00007_amd", "csrc", "lbm_ch_device.h"),
+                 os.path.join(ROOT, "paper_1805_00007_amd", "csrc", "lbm_ch_stencil.h"))
+RT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rt_step_rt256x1024_traffic.txt")
 GOLDEN = os.path.join(ROOT, "tests", "golden", "vortex2048_oracle_1000.npz")
 ADJ_GOLDEN = os.path.join(ROOT, "tests", "golden", "adjoint256_oracle_2000.npz")
 
 
-def kernel_sha():
+def kernel_sha(sources=KERNEL_SRC):
     h = hashlib.sha256()
-    for path in KERNEL_SRC:
+    for path in sources:
         with open(path, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """Bytes per launch from the committed counter summary, if the kernel is unchanged."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(path=TRAFFIC_FILE, sources=KERNEL_SRC, key="hbm_bytes_per_launch"):
+    """Bytes per launch from a committed counter summary, if the kernel is unchanged."""
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
-        if ":" in line:
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha") != kernel_sha():
+    if vals.get("kernel_source_sha") != kernel_sha(sources):
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
 
@@ -145,13 +150,15 @@ def accuracy(lbm, w, torch):
             "max_abs_err": float(np.abs(phi[idx] - ref).max()), "mass_drift": drift}
 
 
-def roofline(bytes_per_lu, nodes, us, kernel, profile):
+def roofline(bytes_per_lu, nodes, us, kernel, profile, traffic=None):
     """Roofline sub-object of a leg: algorithmic bytes of one launch over its duration,
-    against the 8 TB/s HBM peak."""
+    against the 8 TB/s HBM peak; traffic = measured HBM bytes per launch, where a
+    committed counter summary of the unchanged kernel holds them."""
     achieved = bytes_per_lu * nodes / (us * 1e-6) / 1e9
     return {"bound": "hbm", "bytes_per_lu": bytes_per_lu, "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "kernel": kernel, "kernel_avg_us": round(us, 2), "profile": profile}
+            "traffic": traffic, "kernel": kernel, "kernel_avg_us": round(us, 2),
+            "profile": profile}
 
 
 def storage_variant(lbm, torch, storage, steps):
@@ -345,7 +352,9 @@ def rt_leg(lbm, torch, steps=500, warm=50):
                      "nonfinite": int(d["nonfinite"]),
                      "roofline": roofline(bytes_lu, w.nx * w.ny, ms * 1e3,
                                           "k_rt_step (one launch per step)",
-                                          "profiles/rt_step_rt256x1024_kernel_trace.md")}
+                                          "profiles/rt_step_rt256x1024_kernel_trace.md",
+                                          measured_traffic(RT_TRAFFIC_FILE, RT_KERNEL_SRC,
+                                                           "hbm_bytes_per_launch_" + name))}
     return out
 
 
@@ -420,6 +429,8 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 1 GiB x 10 (counter calibration)")
+    ap.add_argument("--rt-only", action="store_true",
+                    help="only run the Rayleigh-Taylor leg (--steps timed, --warmup untimed)")
     args = ap.parse_args()
     if args.copy_probe:
         import torch
@@ -449,6 +460,10 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.rt_only:
+        print(json.dumps({"rayleigh_taylor": rt_leg(lbm, torch, steps=args.steps,
+                                                    warm=args.warmup)}), flush=True)
+        return
     w = workloads.metric2048(steps=args.steps + args.warmup)
     s = lbm.solver_for(w)
     stream = s.stream
