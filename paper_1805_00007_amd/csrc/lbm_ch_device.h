@@ -35,6 +35,22 @@ __device__ __forceinline__ int row_of(int r, int ny, float& vsign) {
   return r < 0 ? r + ny : r;
 }
 
+// A value that every lane of the wave holds identically (loaded from one address),
+// moved into scalar registers word by word.  The compiler cannot prove such a value
+// uniform when it is loaded after a store, and would then run every buffer access that
+// takes it as a scalar operand once per lane value.
+template <class T>
+__device__ __forceinline__ T wave_uniform(const T& x) {
+  static_assert(sizeof(T) % 4 == 0, "whole words");
+  uint32_t w[sizeof(T) / 4];
+  __builtin_memcpy(w, &x, sizeof(T));
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  T y;
+  __builtin_memcpy(&y, w, sizeof(T));
+  return y;
+}
+
 // Range-checked buffer access (gfx9 raw buffer, stride 0): an offset at or beyond
 // the descriptor's byte count reads 0 and drops the store, so no index can reach
 // memory outside the array it belongs to.
@@ -143,6 +159,44 @@ __device__ __forceinline__ void pull9(rsrc_t s, uint32_t pitch, int ny, int y, u
     g[7] = ldpop<ST>(s, 7, pitch, cp, yp);
     g[8] = ldpop<ST>(s, 8, pitch, cm, yp);
   }
+}
+
+// Population I at byte offset `off` (plane and row) and column col, everything in the
+// lane's own offset: for loads whose row differs between the lanes of a wave.  (A scalar
+// offset that differs between lanes makes the compiler issue the load once per distinct
+// value.)  I fixes the element size and the weight of a 16-bit code.
+template <int ST, int I>
+__device__ __forceinline__ float ldpop_lane(rsrc_t s, uint32_t col, uint32_t off) {
+  if (ST == ST_F32 || I == 0) return ldb(s, col * 4u + off, 0);
+  const uint32_t h = __builtin_amdgcn_raw_buffer_load_b16(s, col * 2u + off, 0, 0);
+  return WT[I] * dec16<ST>(h);
+}
+
+// pull9 for a row that differs between the lanes of a wave (the margins of a
+// two-dimensional tile): same values, but all offsets travel in the lanes' own offsets
+// and the wall cases are chosen per lane, so a wave issues nine loads whatever rows its
+// lanes hold.  A bounced-back population has the weight of the one it replaces.
+template <bool WALLS, int ST>
+__device__ __forceinline__ void pull9_lanes(rsrc_t s, uint32_t pitch, int ny, int y,
+                                            uint32_t cc, uint32_t cm, uint32_t cp,
+                                            float g[9]) {
+  const uint32_t ym = y == 0 ? ny - 1 : y - 1;
+  const uint32_t yp = y == ny - 1 ? 0 : y + 1;
+  const uint32_t yc = y;
+  const bool w0 = WALLS && y == 0, w1 = WALLS && y == ny - 1;
+  g[0] = ldpop_lane<ST, 0>(s, cc, pop_off<ST>(0, pitch, yc));
+  g[1] = ldpop_lane<ST, 1>(s, cm, pop_off<ST>(1, pitch, yc));
+  g[3] = ldpop_lane<ST, 3>(s, cp, pop_off<ST>(3, pitch, yc));
+  g[2] = ldpop_lane<ST, 2>(s, cc, w0 ? pop_off<ST>(4, pitch, yc) : pop_off<ST>(2, pitch, ym));
+  g[5] = ldpop_lane<ST, 5>(s, w0 ? cc : cm,
+                           w0 ? pop_off<ST>(7, pitch, yc) : pop_off<ST>(5, pitch, ym));
+  g[6] = ldpop_lane<ST, 6>(s, w0 ? cc : cp,
+                           w0 ? pop_off<ST>(8, pitch, yc) : pop_off<ST>(6, pitch, ym));
+  g[4] = ldpop_lane<ST, 4>(s, cc, w1 ? pop_off<ST>(2, pitch, yc) : pop_off<ST>(4, pitch, yp));
+  g[7] = ldpop_lane<ST, 7>(s, w1 ? cc : cp,
+                           w1 ? pop_off<ST>(5, pitch, yc) : pop_off<ST>(7, pitch, yp));
+  g[8] = ldpop_lane<ST, 8>(s, w1 ? cc : cm,
+                           w1 ? pop_off<ST>(6, pitch, yc) : pop_off<ST>(8, pitch, yp));
 }
 
 // Order parameter of Eq. macroscopicg and mass bookkeeping.  The nine float32

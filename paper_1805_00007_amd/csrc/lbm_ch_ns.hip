@@ -291,40 +291,58 @@ __global__ void __launch_bounds__(64 * R) k_rt_step(const StepArgs a, const floa
   const int y0 = (L / a.nstrips) * R;
   const int t = threadIdx.x;
 
-  // region node (rr, cc) <-> lattice row y0 - 4 + rr, column x0 - 4 + cc (wrapped)
-  auto pull = [&](rsrc_t r, auto st, int rr, int cc, float g[9]) {
+  // region node (rr, cc) <-> lattice row y0 - 4 + rr, column x0 - 4 + cc (wrapped).
+  // x0 - 4 + cc lies in [-4, nx + 66] and y0 - 4 + rr in [-4, ny + R + 2], so one
+  // conditional wrap suffices on lattices at least that wide (or tall); smaller ones
+  // take the remainder.  Own rows are wave-uniform (one wave = one tile row) and keep
+  // their row offsets in the scalar operand; margin rows differ between lanes.
+  auto pull = [&](rsrc_t r, auto st, auto lanes, int rr, int cc, float g[9]) {
     constexpr int S = decltype(st)::value;
-    float sg;
-    const int sr = row_of<WALLS>(y0 - 4 + rr, ny, sg);
-    const int x = ((x0 - 4 + cc) % nx + nx) % nx;
+    int sr = y0 - 4 + rr;
+    if (WALLS || ny < R + 8) {
+      float sg;
+      sr = row_of<WALLS>(sr, ny, sg);
+    } else {
+      sr = sr < 0 ? sr + ny : (sr >= ny ? sr - ny : sr);
+    }
+    int x = x0 - 4 + cc;
+    if (nx >= RT_W) x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
+    else x = (x % nx + nx) % nx;
     const uint32_t xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-    pull9<WALLS, S>(r, pitch, ny, sr, (uint32_t)x, xm, xp, g);
+    if constexpr (decltype(lanes)::value)
+      pull9_lanes<WALLS, S>(r, pitch, ny, sr, (uint32_t)x, xm, xp, g);
+    else
+      pull9<WALLS, S>(r, pitch, ny, sr, (uint32_t)x, xm, xp, g);
   };
   using GS = std::integral_constant<int, ST>;
   using FS = std::integral_constant<int, ST_F32>;
+  using OWN = std::false_type;
+  using MARGIN = std::true_type;
   // a row beyond a wall (its NS values are mirrored, not computed)
   auto beyond = [&](int rr) {
     const int y = y0 - 4 + rr;
     return WALLS && (y < 0 || y >= ny);
   };
 
-  // own node: column x0 + (t % 64), row y0 + t / 64
-  const int ro = 4 + t / RT_C, co = 4 + t % RT_C, ko = ro * RT_W + co;
-  const int xo = x0 + t % RT_C, yo = y0 + t / RT_C;
+  // own node: column x0 + (t % 64), row y0 + t / 64 (the same for a whole wave)
+  static_assert(RT_C == 64, "one wave per tile row");
+  const int tw = __builtin_amdgcn_readfirstlane(t / RT_C);
+  const int ro = 4 + tw, co = 4 + t % RT_C, ko = ro * RT_W + co;
+  const int xo = x0 + t % RT_C, yo = y0 + tw;
   const bool own = xo < nx && yo < ny;
 
   // --- all pulls at once: g of the own node and the phi margin, f of the own node and
   // the NS margin
   float go[9], fo[9], gx[EG][9], fx[EF][9];
-  pull(rg, GS{}, ro, co, go);
-  pull(rf, FS{}, ro, co, fo);
+  pull(rg, GS{}, OWN{}, ro, co, go);
+  pull(rf, FS{}, OWN{}, ro, co, fo);
 #pragma unroll
   for (int i = 0; i < EG; ++i) {
     const int e = t + i * NT;
     if (e < NXG) {
       int rr, cc;
       band_node<R>(e, 4, rr, cc);
-      pull(rg, GS{}, rr, cc, gx[i]);
+      pull(rg, GS{}, MARGIN{}, rr, cc, gx[i]);
     }
   }
 #pragma unroll
@@ -333,7 +351,7 @@ __global__ void __launch_bounds__(64 * R) k_rt_step(const StepArgs a, const floa
     if (e < NXF) {
       int rr, cc;
       band_node<R>(e, 2, rr, cc);
-      pull(rf, FS{}, rr, cc, fx[i]);
+      pull(rf, FS{}, MARGIN{}, rr, cc, fx[i]);
     }
   }
   // --- phi (Eq. macroscopicg)

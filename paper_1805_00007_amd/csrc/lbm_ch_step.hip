@@ -665,17 +665,20 @@ k_phi_batch_persistent(const BatchArgs b) {
     const int mid = (lo_i + hi_i) >> 1;
     if (b.start[mid] <= v) lo_i = mid; else hi_i = mid;
   }
-  int inst = lo_i;
+  int inst = __builtin_amdgcn_readfirstlane(lo_i);
 #pragma unroll 1
   for (; v < hi; v += slots) {
-    while (b.start[inst + 1] <= v) ++inst;
-    StepArgs a = b.args[inst];
+    // the table is read after the previous tile's stores: its values (the same in every
+    // lane) are moved to scalar registers explicitly
+    while (__builtin_amdgcn_readfirstlane(b.start[inst + 1]) <= v) ++inst;
+    StepArgs a = wave_uniform(b.args[inst]);
     if (b.parity) {
       const void* t = a.src;
       a.src = a.dst;
       a.dst = const_cast<void*>(t);
     }
-    step_tile<TX, false, VMODE, MODEL2 ? 2 : 1, ST_F32, false, T1>(a, v - b.start[inst]);
+    step_tile<TX, false, VMODE, MODEL2 ? 2 : 1, ST_F32, false, T1>(
+        a, v - __builtin_amdgcn_readfirstlane(b.start[inst]));
     __syncthreads();  // the LDS rings are reused by the next tile
   }
 }
