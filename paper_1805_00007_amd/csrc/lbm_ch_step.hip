@@ -489,11 +489,15 @@ __device__ __forceinline__ void phi_tile_t1(const StepArgs& a, const int L) {
     issue(y0 - d, vc, vm, vp, T1);
     issue(y0, vc, vm, vp, P0);
     issue(y0 + d, vc, vm, vp, P1);
+    // row m = 2 is pulled with the others (its stage 1 waits for the ring slot of row
+    // m = -2, below), so a chunk start waits for memory once (twice in wave 0)
+    issue(y0 + 2 * d, vc, vm, vp, pb);
     if (hwave) {
       stage1(y0 - 2 * d, U0, X, hj, axh, bxh, 0, hl);
       stage1(y0 - d, U1, X, hj, axh, bxh, 1, hl);
       issue(y0, hvc, hvm, hvp, U0);
       issue(y0 + d, hvc, hvm, hvp, U1);
+      issue(y0 + 2 * d, hvc, hvm, hvp, hb);
     }
     stage1(y0 - 2 * d, T0, X, j, axc, bxc, 0);
     stage1(y0 - d, T1, X, j, axc, bxc, 1);
@@ -504,8 +508,6 @@ __device__ __forceinline__ void phi_tile_t1(const StepArgs& a, const int L) {
       stage1(y0 + d, U1, X, hj, axh, bxh, 3, hl);
     }
   }
-  if (hwave) issue(y0 + 2 * d, hvc, hvm, hvp, hb);
-  issue(y0 + 2 * d, vc, vm, vp, pb);
   __syncthreads();
   {
     // rows m = -1 (slots 0, 1, 2 in march order) and m = 0 (slots 1, 2, 3)
