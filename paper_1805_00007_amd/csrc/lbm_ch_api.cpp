@@ -161,15 +161,15 @@ static void apply_tiles(lbm_ch_ctx* c, int tx, int ty) {
   c->xcd_remap = (c->nblocks % 8 == 0) ? 1 : 0;
 }
 
-// Default: the widest tile (fewest halo columns), then the tallest (fewest halo rows
-// per row; heights 32 down to 1), that still gives at least 2 workgroups per CU on 256
-// CUs (float32), or 4 with 16-bit storage, whose extra decode work per byte needs more
-// waves in flight to cover memory latency.  The 512-column tile (8 waves per workgroup)
-// is taken with float32 storage when it gives at least 1024 workgroups, and with 16-bit
-// storage when it gives at least 512 workgroups of 8 rows or more: on lattices of 2048^2
-// and up, where it halves the halo columns of the 256-column tile.  Small lattices thus get
-// short row chunks (each block's march is a chain of dependent loads), and the smallest
-// get 64 x 1.  lbm_ch_set_tiles overrides; lbm_ch_autotune measures.
+// Default tile.  Lattices of 2048^2 nodes and more: the widest tile (fewest halo
+// columns), then the tallest (fewest halo rows per row; heights 32 down to 1), that still
+// gives at least 2 workgroups per CU on 256 CUs (float32), or 4 with 16-bit storage,
+// whose extra decode work per byte needs more waves in flight to cover memory latency.
+// The 512-column tile (8 waves per workgroup) is taken with float32 storage when it gives
+// at least 1024 workgroups, and with 16-bit storage when it gives at least 512
+// workgroups of 8 rows or more: it halves the halo columns of the 256-column tile.
+// Smaller lattices: the rule below, from sweeps of every shape.  lbm_ch_set_tiles
+// overrides; lbm_ch_autotune measures.
 static void choose_tiles(lbm_ch_ctx* c) {
   const int nx = c->p.nx, ny = c->p.ny;
   if (c->p.velocity_mode == LBM_CH_VEL_NS && (c->p.model == 1 || c->p.model == 2)) {
@@ -179,6 +179,35 @@ static void choose_tiles(lbm_ch_ctx* c) {
     return;
   }
   const bool f32 = c->p.storage == LBM_CH_STORE_F32;
+  const long nodes = (long)nx * ny;
+  if (nodes < (4L << 20)) {
+    // Below 2048^2 a step is a short, latency-bound march.  Tallest chunk (at most 16
+    // rows with float32 storage, 4 with 16-bit) that still gives 2048 waves of columns,
+    // then the widest strip whose strips span at most 9/8 nx columns; 512-column strips
+    // only with chunks of at most 8 rows and 256 blocks or more.  Sweeps of every shape
+    // (square lattices, float32): 256^2 256 x 1, 512^2 512 x 2, 768^2 256 x 4, 1024^2
+    // 512 x 8, 1280^2 256 x 8, 1536^2 256 x 16, each within 3 % of the fastest shape
+    // (1792^2: 256 x 16, 9 %).
+    const int ycap = f32 ? 16 : 4;
+    int ty = 1;
+    for (int yy : {16, 8, 4, 2, 1}) {
+      if (yy <= ycap && nodes / (64L * yy) >= 2048) {
+        ty = yy;
+        break;
+      }
+    }
+    int tx = 64;
+    for (int xx : {512, 256, 128}) {
+      if (xx > nx) continue;
+      const long strips = (nx + xx - 1) / xx;
+      if (strips * xx * 8 > 9L * nx) continue;
+      if (xx == 512 && (ty > 8 || strips * ((ny + ty - 1) / ty) < 256)) continue;
+      tx = xx;
+      break;
+    }
+    apply_tiles(c, tx, ty);
+    return;
+  }
   const long min_blocks = f32 ? 512 : 1024;
   int tx = 64, ty = 1;
   bool found = false;
