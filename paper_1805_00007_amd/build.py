@@ -9,6 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblbm_ch.so")
 SOURCES = [os.path.join(HERE, "csrc", "lbm_ch_step.hip"),
+           os.path.join(HERE, "csrc", "lbm_ch_step16.hip"),
            os.path.join(HERE, "csrc", "lbm_ch_ns.hip"),
            os.path.join(HERE, "csrc", "lbm_ch_aux.hip"),
            os.path.join(HERE, "csrc", "lbm_ch_api.cpp")]
@@ -16,6 +17,9 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          # no packed-FP32 instructions in the device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+# per-source code-generation options: the 16-bit step kernels fit their register budget
+# only without machine-level loop-invariant code motion (see lbm_ch_step16.hip)
+EXTRA = {"lbm_ch_step16.hip": ["-mllvm", "-disable-machine-licm"]}
 
 
 def build(verbose: bool = False) -> str:
@@ -25,7 +29,8 @@ def build(verbose: bool = False) -> str:
         for src in SOURCES:
             obj = os.path.join(tmpdir, os.path.basename(src) + ".o")
             objs.append(obj)
-            procs.append(subprocess.Popen(["hipcc", *FLAGS, "-c", src, "-o", obj],
+            extra = EXTRA.get(os.path.basename(src), [])
+            procs.append(subprocess.Popen(["hipcc", *FLAGS, *extra, "-c", src, "-o", obj],
                                           stdout=subprocess.PIPE, stderr=subprocess.PIPE,
                                           text=True))
         errs = []

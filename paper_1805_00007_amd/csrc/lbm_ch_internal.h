@@ -83,6 +83,10 @@ uint32_t population_bytes(int storage, uint32_t pitch, uint32_t ny);
 // prescribed velocity (other cases ignore it).
 hipError_t launch_phi_step(int tx, bool walls, int vmode, int model, int storage, bool t1,
                            const StepArgs& a, int nblocks, hipStream_t s);
+// The 16-bit storage cases of launch_phi_step (storage ST_F16 / ST_BF16), defined in
+// lbm_ch_step16.hip.
+hipError_t launch_phi_step16(int tx, bool walls, int vmode, int model, int storage, bool t1,
+                             const StepArgs& a, int nblocks, hipStream_t s);
 // The same step that also writes phi of the source state to a.phi_rec (the sums stage 1
 // forms anyway).  Periodic float32 lattices with a prescribed velocity (VEL_SEP or
 // VEL_FIELD) and model 1 or 2 only; hipErrorInvalidValue otherwise.

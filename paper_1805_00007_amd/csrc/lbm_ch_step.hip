@@ -754,6 +754,18 @@ hipError_t phi_step_t(int tx, bool walls, int vmode, int model, bool t1, const S
 
 }  // namespace
 
+#ifdef LBM_STEP_16BIT_TU
+// The 16-bit storage instances of the step, in their own translation unit
+// (lbm_ch_step16.hip, built with other code-generation options).
+hipError_t launch_phi_step16(int tx, bool walls, int vmode, int model, int storage, bool t1,
+                             const StepArgs& a, int nblocks, hipStream_t s) {
+  switch (storage) {
+    case ST_F16: return phi_step_t<ST_F16>(tx, walls, vmode, model, t1, a, nblocks, s);
+    case ST_BF16: return phi_step_t<ST_BF16>(tx, walls, vmode, model, t1, a, nblocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+#else
 bool phi_record_fused(bool walls, int vmode, int model, int storage) {
   return !walls && storage == ST_F32 && (vmode == VEL_SEP || vmode == VEL_FIELD) &&
          (model == 1 || model == 2);
@@ -792,8 +804,8 @@ hipError_t launch_phi_step(int tx, bool walls, int vmode, int model, int storage
                            const StepArgs& a, int nblocks, hipStream_t s) {
   switch (storage) {
     case ST_F32: return phi_step_t<ST_F32>(tx, walls, vmode, model, t1, a, nblocks, s);
-    case ST_F16: return phi_step_t<ST_F16>(tx, walls, vmode, model, t1, a, nblocks, s);
-    case ST_BF16: return phi_step_t<ST_BF16>(tx, walls, vmode, model, t1, a, nblocks, s);
+    case ST_F16:
+    case ST_BF16: return launch_phi_step16(tx, walls, vmode, model, storage, t1, a, nblocks, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -839,5 +851,6 @@ hipError_t launch_phi_batch(int tx, int vmode, bool model2, bool t1, bool persis
   return t1 ? phi_batch_tx<false, true>(tx, vmode, model2, b, grid, s)
             : phi_batch_tx<false, false>(tx, vmode, model2, b, grid, s);
 }
+#endif  // LBM_STEP_16BIT_TU
 
 }  // namespace lbmch
