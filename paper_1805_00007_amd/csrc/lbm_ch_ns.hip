@@ -295,7 +295,10 @@ __global__ void __launch_bounds__(64 * R) k_rt_step(const StepArgs a, const floa
   // x0 - 4 + cc lies in [-4, nx + 66] and y0 - 4 + rr in [-4, ny + R + 2], so one
   // conditional wrap suffices on lattices at least that wide (or tall); smaller ones
   // take the remainder.  Own rows are wave-uniform (one wave = one tile row) and keep
-  // their row offsets in the scalar operand; margin rows differ between lanes.
+  // their row offsets in the scalar operand; margin rows differ between lanes.  In the
+  // last, partly filled row chunk of a short walled lattice, margin rows far past the
+  // wall mirror to negative rows: they feed only outputs outside the lattice (never
+  // stored), and their offsets, in the range-checked lane operand, read as zero.
   auto pull = [&](rsrc_t r, auto st, auto lanes, int rr, int cc, float g[9]) {
     constexpr int S = decltype(st)::value;
     int sr = y0 - 4 + rr;

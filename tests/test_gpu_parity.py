@@ -123,6 +123,16 @@ def test_rayleigh_taylor_coupled_ns(lbm):
     _compare(lbm, w, 600, walls=1, ns=True, check_fields=True)
 
 
+@pytest.mark.parametrize("ny", [17, 20])
+def test_coupled_ns_short_walled_lattices(lbm, ny):
+    """Walled lattices barely taller than one 16-row tile of the coupled step: the last,
+    partly filled row chunk and its margins reach past the far wall (with 17 rows by more
+    than the lattice height, so some margin rows mirror outside it and only feed outputs
+    that are never stored).  phi, mu, u, v and p against the oracle."""
+    w = workloads.rayleigh_taylor_case(nx=64, ny=ny, steps=60, reynolds=300.0)
+    _compare(lbm, w, 60, walls=1, ns=True, check_fields=True)
+
+
 def test_small_and_degenerate_grids(lbm):
     for n in (4, 5, 8, 70):
         w = workloads.Workload("noise%d" % n, n, n + 3, 40, dict(workloads.PRESCRIBED),
