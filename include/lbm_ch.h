@@ -209,9 +209,9 @@ int lbm_ch_load_state(lbm_ch_ctx* ctx, const void* src, size_t bytes, int64_t st
  * ty >= 1 rows per thread block (ty is clipped to ny).  The default is chosen at init from
  * the lattice size and storage.  From 2048^2 nodes up: the widest, then tallest, shape
  * with ty from 32 down to 1 that gives at least 512 blocks with float32 storage, 1024 with
- * 16-bit; tx = 512 needs 1024 blocks of ty <= 16 with float32 storage, and 512 blocks of
- * ty = 16 with 16-bit storage (which then takes ty = 16 below 1024 such blocks, else
- * ty = 8); 64 x 1 if none does.  Below: the tallest ty (at most 16
+ * 16-bit; tx = 512 needs 1024 blocks of ty = 8 with float32 storage (and takes ty = 16
+ * once that gives 2048 blocks), and 512 blocks of ty = 16 with 16-bit storage (which
+ * then takes ty = 16 below 1024 such blocks, else ty = 8); 64 x 1 if none does.  Below: the tallest ty (at most 16
  * with float32 storage, 4 with 16-bit) with nx ny / (64 ty) >= 2048, then the widest tx
  * whose strips span at most 9/8 nx columns (tx = 512 only with ty <= 8 and 256 blocks or
  * more; else 64).  The default changes speed

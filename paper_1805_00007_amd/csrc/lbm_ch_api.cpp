@@ -213,11 +213,24 @@ static void choose_tiles(lbm_ch_ctx* c) {
   bool found = false;
   for (int xx : {512, 256, 128, 64}) {
     if (xx > nx && xx > 64) continue;
-    // 512 columns: at least 1024 blocks of at most 16 rows with float32 storage (2048^2:
-    // 512 x 8; 4096^2: 512 x 16, 216 us against 219 us at 512 x 32; 7680^2: 512 x 16,
-    // 797 us against 825 us), at least 512 blocks of 16 rows with 16-bit storage
-    // (2048^2: 512 x 16, 58.2 us against 63.5 us at 256 x 16)
+    // 512 columns: at least 1024 blocks with float32 storage, at least 512 blocks of 16
+    // rows with 16-bit storage (2048^2: 512 x 16, 58.2 us against 63.5 us at 256 x 16)
     const long need = xx == 512 ? (f32 ? 2 * min_blocks : min_blocks / 2) : min_blocks;
+    if (xx == 512 && f32) {
+      // float32, 512 columns: 16-row chunks once they give 2048 blocks, else 8 rows
+      // (2048^2: 61.5 us against 62.2 us at 512 x 16; 3072^2: 137 us against 143 us;
+      // 4096^2: 215 us against 225 us at 512 x 8 and 219 us at 512 x 32; 7680^2: 796 us
+      // against 825 us at 512 x 32)
+      const long strips = (nx + xx - 1) / xx;
+      const long n16 = strips * ((ny + 15) / 16), n8 = strips * ((ny + 7) / 8);
+      if (n8 >= need) {
+        tx = xx;
+        ty = n16 >= 2048 ? 16 : 8;
+        found = true;
+        break;
+      }
+      continue;
+    }
     if (xx == 512 && !f32) {
       // 16-bit, 512 columns: 16-row chunks while they give fewer than 1024 blocks
       // (2048^2), 8-row chunks from there up (3072^2: 147 us against 158 us at 512 x 16
@@ -232,7 +245,6 @@ static void choose_tiles(lbm_ch_ctx* c) {
       continue;
     }
     for (int yy : {32, 16, 8, 4, 2, 1}) {
-      if (xx == 512 && f32 && yy > 16) continue;
       const long nb = (long)((nx + xx - 1) / xx) * ((ny + yy - 1) / yy);
       if (nb >= need) {
         tx = xx;

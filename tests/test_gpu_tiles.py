@@ -80,12 +80,13 @@ def test_autotune_restores_state(lbm):
     (2048, 0, (512, 8)), (2048, 1, (512, 16)), (2048, 2, (512, 16)), (4096, 0, (512, 16)),
     (256, 0, (256, 1)), (512, 0, (512, 2)), (768, 0, (256, 4)), (1024, 0, (512, 8)),
     (1280, 0, (256, 8)), (1536, 0, (256, 16)), (512, 1, (512, 2)), (1024, 1, (512, 4)),
-    (4096, 1, (512, 8))])
+    (4096, 1, (512, 8)), (3072, 0, (512, 8))])
 def test_default_tiles(lbm, n, storage, expect):
     """Default tile of an n^2 lattice.  From 2048^2 up: the widest, then tallest, shape
-    with at least 512 blocks for float32 populations (1024 blocks of at most 16 rows for
-    the 512-column tile) and 1024 for 16-bit ones (for the 512-column tile 512 blocks of
-    16 rows, and 8-row chunks once 16-row ones give 1024 blocks).  Below: the tallest chunk (16 rows at most, 4 with 16-bit storage)
+    with at least 512 blocks for float32 populations (for the 512-column tile 1024 blocks
+    of 8 rows, and 16-row chunks once they give 2048 blocks) and 1024 for 16-bit ones (for
+    the 512-column tile 512 blocks of 16 rows, and 8-row chunks once 16-row ones give
+    1024 blocks).  Below: the tallest chunk (16 rows at most, 4 with 16-bit storage)
     that gives 2048 waves, then the widest strip whose strips span at most 9/8 nx."""
     w = workloads.metric2048(steps=1) if n == 2048 else workloads.vortex(n, period=80000,
                                                                           steps=1)
