@@ -206,21 +206,25 @@ int lbm_ch_load_state(lbm_ch_ctx* ctx, const void* src, size_t bytes, int64_t st
                       hipStream_t stream);
 
 /* Tile shape of the step kernels: tx columns (one lane each; 64, 128, 256 or 512) by
- * ty >= 1 rows per thread block (ty is clipped to ny).  The default is chosen at init from
- * the lattice size and storage.  From 2048^2 nodes up: the widest, then tallest, shape
- * with ty from 32 down to 1 that gives at least 512 blocks with float32 storage, 1024 with
- * 16-bit; tx = 512 needs 1024 blocks of ty = 8 with float32 storage (and takes ty = 16
- * once that gives 2048 blocks), and 512 blocks of ty = 16 with 16-bit storage (which
- * then takes ty = 16 below 1024 such blocks, else ty = 8); 64 x 1 if none does.  Below: the tallest ty (at most 16
- * with float32 storage, 4 with 16-bit) with nx ny / (64 ty) >= 2048, then the widest tx
- * whose strips span at most 9/8 nx columns (tx = 512 only with ty <= 8 and 256 blocks or
- * more; else 64).  The default changes speed
- * only, never results.  The single-launch coupled step (NS, models 1 and 2) has output
- * tiles of 64 columns whatever tx, and 16, 8, 4 or 2 rows: the largest of these not above
- * ty (2 below); its default is 64 x 16.  Errors:
- * LBM_CH_EINVAL for other shapes. */
+ * ty >= 1 rows per thread block (ty is clipped to ny).  The default is chosen at init
+ * from the lattice size and storage; it changes speed only, never results.
+ *   From 2048^2 nodes up: the widest, then tallest, shape with ty from 32 down to 1 that
+ *   gives at least 512 blocks with float32 storage, 1024 with 16-bit; tx = 512 needs
+ *   1024 blocks of ty = 8 with float32 storage (and takes ty = 16 once that gives 2048
+ *   blocks), and 512 blocks of ty = 16 with 16-bit storage (ty = 16 below 1024 such
+ *   blocks, else ty = 8); 64 x 1 if none does.
+ *   Below: the tallest ty (at most 16 with float32 storage, 4 with 16-bit) with
+ *   nx ny / (64 ty) >= 2048, then the widest tx whose strips span at most 9/8 nx
+ *   columns (tx = 512 only with ty <= 8 and 256 blocks or more; else 64).
+ * The single-launch coupled step (NS, models 1 and 2) has output tiles of 64 columns
+ * whatever tx, and 16, 8, 4 or 2 rows: the largest of these not above ty (2 below); its
+ * default is 64 x 16.  lbm_ch_set_tiles: LBM_CH_EINVAL for other shapes. */
 int lbm_ch_set_tiles(lbm_ch_ctx* ctx, int32_t tx, int32_t ty);
 int lbm_ch_get_tiles(const lbm_ch_ctx* ctx, int32_t* tx, int32_t* ty);
+/* The default tile shape lbm_ch_init would choose for these parameters (above), without
+ * a device or a context.  Errors: LBM_CH_EINVAL for invalid parameters (as
+ * lbm_ch_workspace_bytes rejects them) or null outputs. */
+int lbm_ch_default_tiles(const lbm_ch_params* params, int32_t* tx, int32_t* ty);
 
 /* Graph replay (enable = 1; 0, the default, turns it off and frees the cached graphs).
  * With it on, lbm_ch_step, lbm_ch_record and lbm_ch_adjoint capture the launches of a

@@ -27,7 +27,8 @@ STORE_F32, STORE_F16, STORE_BF16 = 0, 1, 2
 EXPORTS = ("lbm_ch_workspace_bytes", "lbm_ch_init", "lbm_ch_step", "lbm_ch_moments",
            "lbm_ch_diagnostics", "lbm_ch_check_finite", "lbm_ch_step_count",
            "lbm_ch_state_bytes", "lbm_ch_save_state", "lbm_ch_load_state",
-           "lbm_ch_set_tiles", "lbm_ch_get_tiles", "lbm_ch_set_graphs", "lbm_ch_autotune",
+           "lbm_ch_set_tiles", "lbm_ch_get_tiles", "lbm_ch_default_tiles", "lbm_ch_set_graphs",
+           "lbm_ch_autotune",
            "lbm_ch_adjoint_scratch_bytes", "lbm_ch_record", "lbm_ch_adjoint",
            "lbm_ch_adjoint_static",
            "lbm_ch_batch_workspace_bytes", "lbm_ch_batch_create", "lbm_ch_batch_set_tiles",
@@ -79,6 +80,8 @@ def lib():
         PP = ctypes.POINTER(Params)
         L.lbm_ch_workspace_bytes.argtypes = [PP]
         L.lbm_ch_workspace_bytes.restype = ctypes.c_size_t
+        L.lbm_ch_default_tiles.argtypes = [PP, ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int32)]
         L.lbm_ch_init.argtypes = [ctypes.POINTER(vp), PP, ctypes.POINTER(Velocity), vp,
                                   ctypes.c_size_t, vp, vp]
         L.lbm_ch_step.argtypes = [vp, i64, vp]
@@ -143,6 +146,14 @@ def make_params(nx, ny, *, walls=0, model=2, velocity_mode=VEL_SEPARABLE, storag
 
 def workspace_bytes(params: Params) -> int:
     return lib().lbm_ch_workspace_bytes(ctypes.byref(params))
+
+
+def default_tiles(params: Params):
+    """The tile shape (tx, ty) lbm_ch_init would choose for these parameters."""
+    tx, ty = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().lbm_ch_default_tiles(ctypes.byref(params), ctypes.byref(tx), ctypes.byref(ty)),
+           "lbm_ch_default_tiles")
+    return tx.value, ty.value
 
 
 def _ptr(t):

@@ -170,15 +170,16 @@ static void apply_tiles(lbm_ch_ctx* c, int tx, int ty) {
 // workgroups of 8 rows or more: it halves the halo columns of the 256-column tile.
 // Smaller lattices: the rule below, from sweeps of every shape.  lbm_ch_set_tiles
 // overrides; lbm_ch_autotune measures.
-static void choose_tiles(lbm_ch_ctx* c) {
-  const int nx = c->p.nx, ny = c->p.ny;
-  if (c->p.velocity_mode == LBM_CH_VEL_NS && (c->p.model == 1 || c->p.model == 2)) {
+static void default_tiles(const lbm_ch_params& p, int& tx_out, int& ty_out) {
+  const int nx = p.nx, ny = p.ny;
+  if (p.velocity_mode == LBM_CH_VEL_NS && (p.model == 1 || p.model == 2)) {
     // the single-launch coupled step: output tiles of 64 columns x 16 rows (256 x 1024
     // Rayleigh-Taylor: 11.0 us per step, against 11.6 us with 8 rows and 13.8 with 4)
-    apply_tiles(c, 64, 16);
+    tx_out = 64;
+    ty_out = 16;
     return;
   }
-  const bool f32 = c->p.storage == LBM_CH_STORE_F32;
+  const bool f32 = p.storage == LBM_CH_STORE_F32;
   const long nodes = (long)nx * ny;
   if (nodes < (4L << 20)) {
     // Below 2048^2 a step is a short, latency-bound march.  Tallest chunk (at most 16
@@ -205,7 +206,8 @@ static void choose_tiles(lbm_ch_ctx* c) {
       tx = xx;
       break;
     }
-    apply_tiles(c, tx, ty);
+    tx_out = tx;
+    ty_out = ty;
     return;
   }
   const long min_blocks = f32 ? 512 : 1024;
@@ -255,6 +257,13 @@ static void choose_tiles(lbm_ch_ctx* c) {
     }
     if (found) break;
   }
+  tx_out = tx;
+  ty_out = ty;
+}
+
+static void choose_tiles(lbm_ch_ctx* c) {
+  int tx, ty;
+  default_tiles(c->p, tx, ty);
   apply_tiles(c, tx, ty);
 }
 
@@ -709,6 +718,15 @@ int lbm_ch_set_tiles(lbm_ch_ctx* c, int32_t tx, int32_t ty) {
   if (!live(c)) return LBM_CH_ESTATE;
   if (!valid_tile(tx, ty)) return LBM_CH_EINVAL;
   apply_tiles(c, tx, ty);
+  return LBM_CH_OK;
+}
+
+int lbm_ch_default_tiles(const lbm_ch_params* p, int32_t* tx, int32_t* ty) {
+  if (!tx || !ty || !valid_params(p)) return LBM_CH_EINVAL;
+  int x, y;
+  default_tiles(*p, x, y);
+  *tx = x;
+  *ty = y > p->ny ? p->ny : y;
   return LBM_CH_OK;
 }
 

@@ -155,3 +155,43 @@ def test_missing_library_fails_loudly(tmp_path):
                        text=True, timeout=120)
     assert r.returncode == 0, r.stderr
     assert "raised: liblbm_ch.so is not built" in r.stdout
+
+
+@pytest.mark.parametrize("n,storage,expect", [
+    (2048, 0, (512, 8)), (2048, 1, (512, 16)), (2048, 2, (512, 16)), (3072, 0, (512, 8)),
+    (4096, 0, (512, 16)), (4096, 1, (512, 8)), (7680, 0, (512, 16)),
+    (128, 0, (128, 1)), (200, 0, (64, 1)), (256, 0, (256, 1)), (512, 0, (512, 2)),
+    (768, 0, (256, 4)), (1024, 0, (512, 8)), (1280, 0, (256, 8)), (1536, 0, (256, 16)),
+    (512, 1, (512, 2)), (1024, 1, (512, 4)), (8, 0, (64, 1))])
+def test_default_tiles_rule(n, storage, expect):
+    """The default tile rule (include/lbm_ch.h) on the host, without a device: the
+    shapes the size sweeps picked for square lattices."""
+    assert lbm.default_tiles(lbm.make_params(n, n, storage=storage)) == expect
+
+
+def test_default_tiles_invariants():
+    """Over many lattice shapes: a valid shape, ty within the lattice, no strip wider
+    than needed, and the coupled step's 64 x 16 (clipped to ny)."""
+    sizes = [4, 7, 33, 64, 65, 100, 130, 200, 257, 384, 600, 1000, 1500, 2047, 2048, 2500,
+             4100, 7680]
+    for nx in sizes:
+        for ny in sizes:
+            if lbm.workspace_bytes(lbm.make_params(nx, ny)) == 0:
+                continue
+            for storage in (0, 1, 2):
+                tx, ty = lbm.default_tiles(lbm.make_params(nx, ny, storage=storage))
+                assert tx in (64, 128, 256, 512) and 1 <= ty <= min(ny, 32), (nx, ny, tx, ty)
+                assert tx == 64 or tx <= nx, (nx, ny, tx)
+            tx, ty = lbm.default_tiles(lbm.make_params(nx, ny, walls=1, ns=True,
+                                                       gravity=1e-6))
+            assert (tx, ty) == (64, min(16, ny)), (nx, ny, tx, ty)
+
+
+def test_default_tiles_rejects_invalid():
+    L = lbm.lib()
+    tx, ty = ctypes.c_int32(), ctypes.c_int32()
+    bad = lbm.make_params(64, 48, tau_g=0.5)
+    assert L.lbm_ch_default_tiles(ctypes.byref(bad), ctypes.byref(tx), ctypes.byref(ty)) \
+        == lbm.EINVAL
+    good = lbm.make_params(64, 48)
+    assert L.lbm_ch_default_tiles(ctypes.byref(good), None, ctypes.byref(ty)) == lbm.EINVAL
