@@ -206,16 +206,21 @@ int lbm_ch_load_state(lbm_ch_ctx* ctx, const void* src, size_t bytes, int64_t st
                       hipStream_t stream);
 
 /* Tile shape of the step kernels: tx columns (one lane each; 64, 128, 256 or 512) by
- * ty >= 1 rows per thread block (ty is clipped to ny).  The default is chosen at init
+ * ty >= 1 rows per thread block (ty is clipped to ny), marching down the rows; or tx = 0:
+ * single-pass tiles of 64 columns x ty rows (ty 4, 8 or 16) that pull their rows and a
+ * margin of 2 at once, for periodic float32 lattices with a prescribed velocity at
+ * tau_g = 1, models 1 and 2 (LBM_CH_EINVAL elsewhere).  The default is chosen at init
  * from the lattice size and storage; it changes speed only, never results.
+ *   Below 2048^2 nodes, where single-pass tiles serve: tx = 0 with ty = 4 up to 65536
+ *   nodes, else 16.
  *   From 2048^2 nodes up: the widest, then tallest, shape with ty from 32 down to 1 that
  *   gives at least 512 blocks with float32 storage, 1024 with 16-bit; tx = 512 needs
  *   1024 blocks of ty = 8 with float32 storage (and takes ty = 16 once that gives 2048
  *   blocks), and 512 blocks of ty = 16 with 16-bit storage (ty = 16 below 1024 such
  *   blocks, else ty = 8); 64 x 1 if none does.
- *   Below: the tallest ty (at most 16 with float32 storage, 4 with 16-bit) with
- *   nx ny / (64 ty) >= 2048, then the widest tx whose strips span at most 9/8 nx
- *   columns (tx = 512 only with ty <= 8 and 256 blocks or more; else 64).
+ *   Other lattices below: the tallest ty (at most 16 with float32 storage, 4 with
+ *   16-bit) with nx ny / (64 ty) >= 2048, then the widest tx whose strips span at most
+ *   9/8 nx columns (tx = 512 only with ty <= 8 and 256 blocks or more; else 64).
  * The single-launch coupled step (NS, models 1 and 2) has output tiles of 64 columns
  * whatever tx, and 16, 8, 4 or 2 rows: the largest of these not above ty (2 below); its
  * default is 64 x 16.  lbm_ch_set_tiles: LBM_CH_EINVAL for other shapes. */

@@ -138,6 +138,14 @@ static bool live(const lbm_ch_ctx* c) { return c && c->magic == CTX_MAGIC; }
 // tau_g = 1 exactly: the collision keeps none of the pulled populations (omega = 1).
 static bool tau_one(const lbm_ch_ctx* c) { return c->p.tau_g == 1.0; }
 
+// The single-pass tile (tx = 0 in lbm_ch_set_tiles) serves periodic float32 lattices with a
+// prescribed velocity at tau_g = 1, models 1 and 2.
+static bool pass_eligible(const lbm_ch_params& p) {
+  const int vmode = p.velocity_mode == LBM_CH_VEL_FIELD ? VEL_FIELD
+                    : p.velocity_mode == LBM_CH_VEL_SEPARABLE ? VEL_SEP : -1;
+  return vmode >= 0 && phi_pass_ok(p.walls != 0, vmode, p.model, p.storage, p.tau_g == 1.0);
+}
+
 static float time_factor(const lbm_ch_ctx* c, int64_t n) {
   if (c->tf.empty()) return 1.0f;
   if (n < (int64_t)c->tf.size()) return (float)c->tf[(size_t)n];
@@ -152,6 +160,14 @@ static bool valid_tile(int tx, int ty) {
 static void apply_tiles(lbm_ch_ctx* c, int tx, int ty) {
   drop_graphs(c);  // the launch shape is part of every captured sequence
   const int nx = c->p.nx, ny = c->p.ny;
+  if (tx == 0) {  // single-pass tiles of 64 columns x ty rows (ty is a kernel constant)
+    c->tx = 0;
+    c->ty = ty;
+    c->nstrips = (nx + 63) / 64;
+    c->nblocks = c->nstrips * ((ny + ty - 1) / ty);
+    c->xcd_remap = (c->nblocks % 8 == 0) ? 1 : 0;
+    return;
+  }
   if (ty > ny) ty = ny;
   c->tx = tx;
   c->ty = ty;
@@ -181,6 +197,14 @@ static void default_tiles(const lbm_ch_params& p, int& tx_out, int& ty_out) {
   }
   const bool f32 = p.storage == LBM_CH_STORE_F32;
   const long nodes = (long)nx * ny;
+  if (nodes < (4L << 20) && pass_eligible(p)) {
+    // single-pass tiles below 2048^2 where they serve (us per step, marching default /
+    // single pass: 256^2 6.78 / 4.77 (4 rows); 512^2 9.27 / 5.93, 768^2 16.1 / 12.8,
+    // 1536^2 44.0 / 39.7 (16 rows); 1024^2 20.6 / 21.0)
+    tx_out = 0;
+    ty_out = nodes <= 65536 ? 4 : 16;
+    return;
+  }
   if (nodes < (4L << 20)) {
     // Below 2048^2 a step is a short, latency-bound march.  Tallest chunk (at most 16
     // rows with float32 storage, 4 with 16-bit) that still gives 2048 waves of columns,
@@ -489,7 +513,11 @@ static int run_steps(lbm_ch_ctx* c, int64_t nsteps, float* phi_out, hipStream_t 
     a.xh = c->xh;
     a.xfirst = c->step == 0 ? 1 : 0;
     float* rec = phi_out ? phi_out + (size_t)s * c->p.nx * c->p.ny : nullptr;
-    if (rec && phi_record_fused(walls, vmode, c->p.model, c->p.storage)) {
+    if (c->tx == 0) {  // single-pass tiles (records phi itself when asked)
+      a.phi_rec = rec;
+      e = launch_phi_pass(c->ty, vmode, c->p.model, a, c->nblocks, stream);
+      a.phi_rec = nullptr;
+    } else if (rec && phi_record_fused(walls, vmode, c->p.model, c->p.storage)) {
       // the step writes phi of its source state itself
       a.phi_rec = rec;
       e = launch_phi_record(c->tx, vmode, c->p.model, tau_one(c), a, c->nblocks, stream);
@@ -716,7 +744,11 @@ int lbm_ch_load_state(lbm_ch_ctx* c, const void* src, size_t bytes, int64_t step
 
 int lbm_ch_set_tiles(lbm_ch_ctx* c, int32_t tx, int32_t ty) {
   if (!live(c)) return LBM_CH_ESTATE;
-  if (!valid_tile(tx, ty)) return LBM_CH_EINVAL;
+  if (tx == 0) {
+    if (!pass_eligible(c->p) || (ty != 4 && ty != 8 && ty != 16)) return LBM_CH_EINVAL;
+  } else if (!valid_tile(tx, ty)) {
+    return LBM_CH_EINVAL;
+  }
   apply_tiles(c, tx, ty);
   return LBM_CH_OK;
 }
@@ -726,7 +758,7 @@ int lbm_ch_default_tiles(const lbm_ch_params* p, int32_t* tx, int32_t* ty) {
   int x, y;
   default_tiles(*p, x, y);
   *tx = x;
-  *ty = y > p->ny ? p->ny : y;
+  *ty = (x != 0 && y > p->ny) ? p->ny : y;  // single-pass rows are a kernel constant
   return LBM_CH_OK;
 }
 
@@ -753,10 +785,13 @@ int lbm_ch_autotune(lbm_ch_ctx* c, void* backup, size_t backup_bytes, int32_t tr
   float best = -1.0f;
   int btx = tx0, bty = ty0;
   const int nx = c->p.nx, ny = c->p.ny;
-  for (int xx : {64, 128, 256, 512}) {
+  const bool pass = pass_eligible(c->p);
+  for (int xx : {0, 64, 128, 256, 512}) {
     if (e != hipSuccess) break;
+    if (xx == 0 && !pass) continue;
     if (xx > 64 && xx / 2 >= nx) continue;  // more than half the lanes idle
     for (int yy : {1, 2, 4, 8, 16, 32}) {
+      if (xx == 0 && yy != 4 && yy != 8 && yy != 16) continue;
       if (yy > ny && yy > 2) continue;
       apply_tiles(c, xx, yy);
       r = run_steps(c, 1, nullptr, stream);  // untimed: first launch of this kernel shape

@@ -605,6 +605,159 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int L) {
     phi_tile<TX, WALLS, VMODE, MODEL, ST, REC>(a, L);
 }
 
+// ---------------------------------------------------------------------------------
+// Single-pass tile of the tau_g = 1 step (periodic lattice, float32 populations,
+// prescribed velocity, models 1 and 2): for small lattices, where a march is a chain of
+// dependent row loads.  A workgroup owns 64 columns x R rows (one wave per row) and
+// issues every pull it needs at once: its own nodes and a margin of 2 (phi, and q =
+// phi u for model 2); then mu and D on the tile plus 1, then stage 3 on the tile.  The
+// margins are recomputed by each workgroup that needs them (L2 hits), so the workgroup
+// waits for memory once.  Every value is formed by the same expressions as in
+// phi_tile_t1, so results are bitwise those of the marching tiles.
+#pragma clang fp contract(off)
+constexpr int PS_C = 64;          // output columns per workgroup
+constexpr int PS_W = PS_C + 4;    // region row length (margin 2 on each side)
+
+template <int R, int VMODE, bool MODEL2, bool REC>
+__global__ void __launch_bounds__(64 * R) k_phi_pass(const StepArgs a) {
+  constexpr int NT = 64 * R;
+  constexpr int N = (R + 4) * PS_W;
+  constexpr int NX = N - R * PS_C;                 // margin nodes
+  constexpr int EX = (NX + NT - 1) / NT;
+  __shared__ float s_ph[N], s_mu[N], s_qx[MODEL2 ? N : 1], s_qy[MODEL2 ? N : 1],
+      s_d[MODEL2 ? N : 1];
+  const Coef& c = a.c;
+  const int nx = a.nx, ny = a.ny;
+  const uint32_t pitch = a.pitch;
+  const rsrc_t rsrc = make_rsrc(a.src, pop_bytes(ST_F32, pitch, ny));
+  const rsrc_t rdst = make_rsrc(a.dst, pop_bytes(ST_F32, pitch, ny));
+  int L = blockIdx.x;
+  if (a.xcd_remap) {
+    const int per = gridDim.x >> 3;
+    L = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  }
+  const int x0 = (L % a.nstrips) * PS_C;
+  const int y0 = (L / a.nstrips) * R;
+  const int t = threadIdx.x;
+  const uint32_t nodes = (uint32_t)nx * ny;
+  const uint32_t rb = (uint32_t)nx * 4u;
+
+  // region node (rr, cc) <-> lattice row y0 - 2 + rr, column x0 - 2 + cc (periodic);
+  // x0 - 2 + cc lies in [-2, nx + 64] and y0 - 2 + rr in [-2, ny + R]
+  auto col = [&](int cc) {
+    int x = x0 - 2 + cc;
+    if (nx >= PS_W) return x < 0 ? x + nx : (x >= nx ? x - nx : x);
+    return (x % nx + nx) % nx;
+  };
+  auto row = [&](int rr) {
+    int y = y0 - 2 + rr;
+    if (ny >= R + 4) return y < 0 ? y + ny : (y >= ny ? y - ny : y);
+    return (y % ny + ny) % ny;
+  };
+  // stage 1 at one region node: pull, phi (with its FP64 remainder), the velocity factors
+  // as phi_tile_t1 keeps them (separable: ay[y] tf and bx[x] ... as a, b) and q = phi u
+  struct Node {
+    float phi, lo, a, b, u, v;
+  };
+  auto node = [&](auto lanes, int rr, int cc) {
+    const int x = col(cc), y = row(rr);
+    const uint32_t xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    float g[9];
+    if constexpr (decltype(lanes)::value)
+      pull9_lanes<false, ST_F32>(rsrc, pitch, ny, y, (uint32_t)x, xm, xp, g);
+    else
+      pull9<false, ST_F32>(rsrc, pitch, ny, y, (uint32_t)x, xm, xp, g);
+    Node n;
+    n.phi = sum9(g, n.lo);
+    const float f = a.tf;  // periodic: the row parity factor is 1
+    if (VMODE == VEL_SEP) {
+      n.a = a.ay[y] * f;
+      n.b = a.by[y] * f;
+      n.u = a.ax[x] * n.a;
+      n.v = a.bx[x] * n.b;
+    } else {
+      const uint32_t k = (uint32_t)y * nx + x;
+      n.a = n.u = f * a.ux[k];
+      n.b = n.v = f * a.uy[k];
+    }
+    return n;
+  };
+  using OWN = std::false_type;
+  using MARGIN = std::true_type;
+
+  // own node: column x0 + (t % 64), row y0 + t / 64 (the same for a whole wave)
+  static_assert(PS_C == 64, "one wave per tile row");
+  const int tw = __builtin_amdgcn_readfirstlane(t / PS_C);
+  const int ro = 2 + tw, co = 2 + t % PS_C, ko = ro * PS_W + co;
+  const int xo = x0 + t % PS_C, yo = y0 + tw;
+  const bool own = xo < nx && yo < ny;
+
+  const Node no = node(OWN{}, ro, co);
+  if (__builtin_expect(!__builtin_isfinite(no.phi), 0) && own && a.nonfinite) *a.nonfinite = 1;
+  s_ph[ko] = no.phi;
+  if (MODEL2) {
+    s_qx[ko] = no.phi * no.u;
+    s_qy[ko] = no.phi * no.v;
+  }
+#pragma unroll
+  for (int i = 0; i < EX; ++i) {
+    const int e = t + i * NT;
+    if (e < NX) {
+      int rr, cc;  // the band of width 2 around the tile, row by row
+      if (e < 2 * PS_W) {
+        rr = e / PS_W;
+        cc = e % PS_W;
+      } else if (e < 2 * PS_W + 4 * R) {
+        const int q = e - 2 * PS_W;
+        rr = 2 + q / 4;
+        const int k = q % 4;
+        cc = k < 2 ? k : PS_C + k;
+      } else {
+        const int q = e - 2 * PS_W - 4 * R;
+        rr = 2 + R + q / PS_W;
+        cc = q % PS_W;
+      }
+      const Node m = node(MARGIN{}, rr, cc);
+      const int k = rr * PS_W + cc;
+      s_ph[k] = m.phi;
+      if (MODEL2) {
+        s_qx[k] = m.phi * m.u;
+        s_qy[k] = m.phi * m.v;
+      }
+    }
+  }
+  __syncthreads();
+  // stage 2: mu and D on the tile plus 1 (Eqs. mu, mark3)
+  for (int e = t; e < (R + 2) * (PS_C + 2); e += NT) {
+    const int k = (1 + e / (PS_C + 2)) * PS_W + 1 + e % (PS_C + 2);
+    s_mu[k] = t1_mu(c, s_ph[k], t1_lap(s_ph + k - PS_W, s_ph + k, s_ph + k + PS_W, 0));
+    if (MODEL2)
+      s_d[k] = t1_dx(s_qx + k - PS_W, s_qx + k, s_qx + k + PS_W, 0) +
+               t1_dy(s_qy + k - PS_W, s_qy + k, s_qy + k + PS_W, 0);
+  }
+  __syncthreads();
+  if (!own) return;
+  // stage 3 (as in phi_tile_t1)
+  const float* m = s_mu + ko;
+  const float mux = t1_dx(m - PS_W, m, m + PS_W, 0), muy = t1_dy(m - PS_W, m, m + PS_W, 0);
+  const float rho = fmaf(c.a, no.phi, c.b);
+  const float s1 = -(no.phi * no.phi) * rcp(rho);
+  float fx = s1 * mux, fy = s1 * muy;
+  if (MODEL2) {
+    const float* dd = s_d + ko;
+    fx = fmaf(c.k2, t1_dx(dd - PS_W, dd, dd + PS_W, 0), fx);
+    fy = fmaf(c.k2, t1_dy(dd - PS_W, dd, dd + PS_W, 0), fy);
+  }
+  if (REC) {
+    const rsrc_t rrec = make_rsrc(a.phi_rec, nodes * 4u);
+    stb_nt(rrec, no.phi, (uint32_t)xo * 4u, (uint32_t)yo * rb);
+  }
+  float g[9];
+  collide_t1(c, no.phi, s_mu[ko], no.u, no.v, fx, fy, g);
+  finish_store<ST_F32>(rdst, pitch, (uint32_t)xo, (uint32_t)yo, (double)no.phi + (double)no.lo, g);
+}
+#pragma clang fp contract(fast)
+
 template <int TX, bool WALLS, int VMODE, int MODEL, int ST, bool REC = false, bool T1 = false>
 __global__ void __launch_bounds__(TX)
 __attribute__((amdgpu_waves_per_eu(MODEL == 3 ? 3 : WPE_PHI, 8)))
@@ -752,6 +905,20 @@ hipError_t phi_step_t(int tx, bool walls, int vmode, int model, bool t1, const S
   }
 }
 
+template <int R>
+hipError_t phi_pass_r(int vmode, bool model2, bool rec, const StepArgs& a, int nb, hipStream_t s) {
+#define LBM_PASS(V, M, RC) hipLaunchKernelGGL((k_phi_pass<R, V, M, RC>), dim3(nb), dim3(64 * R), 0, s, a)
+  if (vmode == VEL_SEP) {
+    if (model2) { if (rec) LBM_PASS(VEL_SEP, true, true); else LBM_PASS(VEL_SEP, true, false); }
+    else { if (rec) LBM_PASS(VEL_SEP, false, true); else LBM_PASS(VEL_SEP, false, false); }
+  } else {
+    if (model2) { if (rec) LBM_PASS(VEL_FIELD, true, true); else LBM_PASS(VEL_FIELD, true, false); }
+    else { if (rec) LBM_PASS(VEL_FIELD, false, true); else LBM_PASS(VEL_FIELD, false, false); }
+  }
+#undef LBM_PASS
+  return hipGetLastError();
+}
+
 }  // namespace
 
 #ifdef LBM_STEP_16BIT_TU
@@ -796,6 +963,23 @@ hipError_t launch_phi_record(int tx, int vmode, int model, bool t1, const StepAr
                         : phi_record_t<256, false>(vmode, model, a, nblocks, s);
     case 512: return t1 ? phi_record_t<512, true>(vmode, model, a, nblocks, s)
                         : phi_record_t<512, false>(vmode, model, a, nblocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+bool phi_pass_ok(bool walls, int vmode, int model, int storage, bool t1) {
+  return !walls && storage == ST_F32 && t1 && (vmode == VEL_SEP || vmode == VEL_FIELD) &&
+         (model == 1 || model == 2);
+}
+
+hipError_t launch_phi_pass(int rows, int vmode, int model, const StepArgs& a, int nblocks,
+                           hipStream_t s) {
+  if (!phi_pass_ok(false, vmode, model, ST_F32, true)) return hipErrorInvalidValue;
+  const bool rec = a.phi_rec != nullptr, m2 = model == 2;
+  switch (rows) {
+    case 4: return phi_pass_r<4>(vmode, m2, rec, a, nblocks, s);
+    case 8: return phi_pass_r<8>(vmode, m2, rec, a, nblocks, s);
+    case 16: return phi_pass_r<16>(vmode, m2, rec, a, nblocks, s);
     default: return hipErrorInvalidValue;
   }
 }

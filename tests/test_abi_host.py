@@ -160,13 +160,21 @@ def test_missing_library_fails_loudly(tmp_path):
 @pytest.mark.parametrize("n,storage,expect", [
     (2048, 0, (512, 8)), (2048, 1, (512, 16)), (2048, 2, (512, 16)), (3072, 0, (512, 8)),
     (4096, 0, (512, 16)), (4096, 1, (512, 8)), (7680, 0, (512, 16)),
-    (128, 0, (128, 1)), (200, 0, (64, 1)), (256, 0, (256, 1)), (512, 0, (512, 2)),
-    (768, 0, (256, 4)), (1024, 0, (512, 8)), (1280, 0, (256, 8)), (1536, 0, (256, 16)),
-    (512, 1, (512, 2)), (1024, 1, (512, 4)), (8, 0, (64, 1))])
+    (128, 0, (0, 4)), (256, 0, (0, 4)), (512, 0, (0, 16)), (1536, 0, (0, 16)), (8, 0, (0, 4)),
+    (512, 1, (512, 2)), (1024, 1, (512, 4))])
 def test_default_tiles_rule(n, storage, expect):
     """The default tile rule (include/lbm_ch.h) on the host, without a device: the
-    shapes the size sweeps picked for square lattices."""
+    shapes the size sweeps picked for square lattices (periodic, tau_g = 1, separable
+    velocity, Model-II: single-pass tiles below 2048^2 with float32 storage)."""
     assert lbm.default_tiles(lbm.make_params(n, n, storage=storage)) == expect
+
+
+@pytest.mark.parametrize("n,expect", [
+    (128, (128, 1)), (200, (64, 1)), (256, (256, 1)), (512, (512, 2)), (768, (256, 4)),
+    (1024, (512, 8)), (1280, (256, 8)), (1536, (256, 16))])
+def test_default_marching_tiles_rule(n, expect):
+    """Where single-pass tiles do not serve (here tau_g != 1) the marching tiles' rule."""
+    assert lbm.default_tiles(lbm.make_params(n, n, tau_g=0.8)) == expect
 
 
 def test_default_tiles_invariants():
@@ -179,9 +187,15 @@ def test_default_tiles_invariants():
             if lbm.workspace_bytes(lbm.make_params(nx, ny)) == 0:
                 continue
             for storage in (0, 1, 2):
-                tx, ty = lbm.default_tiles(lbm.make_params(nx, ny, storage=storage))
-                assert tx in (64, 128, 256, 512) and 1 <= ty <= min(ny, 32), (nx, ny, tx, ty)
-                assert tx == 64 or tx <= nx, (nx, ny, tx)
+                for walls in (0, 1):
+                    tx, ty = lbm.default_tiles(lbm.make_params(nx, ny, storage=storage,
+                                                               walls=walls))
+                    if tx == 0:  # single pass: periodic float32, below 2048^2
+                        assert storage == 0 and walls == 0 and nx * ny < 4 << 20
+                        assert ty in (4, 16), (nx, ny, ty)
+                        continue
+                    assert tx in (64, 128, 256, 512) and 1 <= ty <= min(ny, 32), (nx, ny, tx, ty)
+                    assert tx == 64 or tx <= nx, (nx, ny, tx)
             tx, ty = lbm.default_tiles(lbm.make_params(nx, ny, walls=1, ns=True,
                                                        gravity=1e-6))
             assert (tx, ty) == (64, min(16, ny)), (nx, ny, tx, ty)

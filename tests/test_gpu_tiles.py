@@ -50,6 +50,60 @@ def test_ns_results_do_not_depend_on_tiles(lbm, walls):
         assert np.array_equal(_run(lbm, w, 80, tiles, walls=walls), ref), tiles
 
 
+def _cut(w, ny):
+    w.ny = ny
+    w.phi0 = w.phi0[:ny]
+    w.velocity = dict(w.velocity, ay=w.velocity["ay"][:ny], by=w.velocity["by"][:ny])
+    return w
+
+
+@pytest.mark.parametrize("model", [1, 2])
+def test_single_pass_tiles_match_marching_tiles(lbm, model):
+    """The single-pass tile (tx = 0: 64 columns x 4, 8 or 16 rows, all pulls at once) gives
+    bitwise the marching tiles' state: a lattice wider than its 68-column region with a
+    partial last row of tiles, and one narrower than the region (40 x 23)."""
+    for n, ny in ((200, 136), (40, 23)):
+        w = _cut(workloads.vortex(n, period=400, steps=60, model=model), ny)
+        ref = _run(lbm, w, 60, (64, 4))
+        for r in (4, 8, 16):
+            print("single pass", n, ny, r, flush=True)
+            assert np.array_equal(_run(lbm, w, 60, (0, r)), ref), (n, ny, r)
+
+
+def test_single_pass_tiles_stored_field_and_record(lbm):
+    """With a stored velocity field, and when the step also records phi of each source
+    state (the adjoint's forward pass): bitwise the marching tiles' state and record."""
+    ac = workloads.adjoint_case(n=96, steps=40)
+    U, V = ac.field()
+    out = {}
+    for tiles in ((64, 2), (0, 4), (0, 16)):
+        s = lbm.Solver(ac.n, ac.n, ac.phi0, field=(U, V), device=torch.device("cuda:0"),
+                       **ac.phys)
+        s.set_tiles(*tiles)
+        s.step(7)
+        traj = torch.empty((12, ac.n, ac.n), dtype=torch.float32, device="cuda:0")
+        s.record(12, traj)
+        s.step(5)
+        out[tiles] = (s.phi().cpu().numpy(), traj.cpu().numpy())
+        s.close()
+    for tiles in ((0, 4), (0, 16)):
+        assert np.array_equal(out[tiles][0], out[(64, 2)][0]), tiles
+        assert np.array_equal(out[tiles][1], out[(64, 2)][1]), tiles
+
+
+def test_single_pass_tiles_rejected_where_not_served(lbm):
+    w = workloads.vortex(64, period=400, steps=10)
+    s = lbm.solver_for(w)
+    for bad in ((0, 5), (0, 32), (0, 1)):
+        with pytest.raises(lbm.LbmChError):
+            s.set_tiles(*bad)
+    s.close()
+    s = lbm.solver_for(w, walls=1)
+    with pytest.raises(lbm.LbmChError):
+        s.set_tiles(0, 4)
+    s.close()
+
+
 def test_set_tiles_rejects_invalid(lbm):
     w = workloads.translation(64, steps=10)
     s = lbm.solver_for(w)
@@ -68,7 +122,8 @@ def test_autotune_restores_state(lbm):
     tiles, us = s.autotune(trial_steps=5)
     print("autotune 256^2 ->", tiles, "%.2f us/step" % us)
     assert s.step_count == 30
-    assert tiles[0] in (64, 128, 256, 512) and tiles[1] in (1, 2, 4, 8, 16, 32) and us > 0
+    # tx = 0: the single-pass tiles, a candidate on this periodic tau_g = 1 lattice
+    assert tiles[0] in (0, 64, 128, 256, 512) and tiles[1] in (1, 2, 4, 8, 16, 32) and us > 0
     s.step(40)
     got = s.phi().cpu().numpy()
     s.close()
@@ -78,16 +133,17 @@ def test_autotune_restores_state(lbm):
 
 @pytest.mark.parametrize("n,storage,expect", [
     (2048, 0, (512, 8)), (2048, 1, (512, 16)), (2048, 2, (512, 16)), (4096, 0, (512, 16)),
-    (256, 0, (256, 1)), (512, 0, (512, 2)), (768, 0, (256, 4)), (1024, 0, (512, 8)),
-    (1280, 0, (256, 8)), (1536, 0, (256, 16)), (512, 1, (512, 2)), (1024, 1, (512, 4)),
+    (256, 0, (0, 4)), (512, 0, (0, 16)), (1536, 0, (0, 16)), (512, 1, (512, 2)),
+    (1024, 1, (512, 4)),
     (4096, 1, (512, 8)), (3072, 0, (512, 8))])
 def test_default_tiles(lbm, n, storage, expect):
     """Default tile of an n^2 lattice.  From 2048^2 up: the widest, then tallest, shape
     with at least 512 blocks for float32 populations (for the 512-column tile 1024 blocks
     of 8 rows, and 16-row chunks once they give 2048 blocks) and 1024 for 16-bit ones (for
     the 512-column tile 512 blocks of 16 rows, and 8-row chunks once 16-row ones give
-    1024 blocks).  Below: the tallest chunk (16 rows at most, 4 with 16-bit storage)
-    that gives 2048 waves, then the widest strip whose strips span at most 9/8 nx."""
+    1024 blocks).  Below: single-pass tiles (tx = 0) for these periodic float32 lattices
+    at tau_g = 1; with 16-bit storage the tallest chunk (4 rows at most) that gives 2048
+    waves, then the widest strip whose strips span at most 9/8 nx."""
     w = workloads.metric2048(steps=1) if n == 2048 else workloads.vortex(n, period=80000,
                                                                           steps=1)
     s = lbm.solver_for(w, storage=storage)
