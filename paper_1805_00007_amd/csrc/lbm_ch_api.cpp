@@ -180,12 +180,11 @@ static void apply_tiles(lbm_ch_ctx* c, int tx, int ty) {
 // Default tile.  Lattices of 2048^2 nodes and more: the widest tile (fewest halo
 // columns), then the tallest (fewest halo rows per row; heights 32 down to 1), that still
 // gives at least 2 workgroups per CU on 256 CUs (float32), or 4 with 16-bit storage,
-// whose extra decode work per byte needs more waves in flight to cover memory latency.
-// The 512-column tile (8 waves per workgroup) is taken with float32 storage when it gives
-// at least 1024 workgroups, and with 16-bit storage when it gives at least 512
-// workgroups of 8 rows or more: it halves the halo columns of the 256-column tile.
-// Smaller lattices: the rule below, from sweeps of every shape.  lbm_ch_set_tiles
-// overrides; lbm_ch_autotune measures.
+// whose extra decode work per byte needs more waves in flight to cover memory latency;
+// the 512-column tile (8 waves per workgroup; half the halo columns of the 256-column
+// one) by the measured rules below.  Smaller lattices: the single-pass tile where it
+// serves, else the marching rule below; both from sweeps of every shape.
+// lbm_ch_set_tiles overrides; lbm_ch_autotune measures.
 static void default_tiles(const lbm_ch_params& p, int& tx_out, int& ty_out) {
   const int nx = p.nx, ny = p.ny;
   if (p.velocity_mode == LBM_CH_VEL_NS && (p.model == 1 || p.model == 2)) {
