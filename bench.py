@@ -178,11 +178,14 @@ def storage_variant(lbm, torch, storage, steps):
     e1.record(s.stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    tiles = s.tiles
     s.close()
+    kernel = ("k_phi_pass (16-bit storage, single-pass tiles of 64 x %d)" % tiles[1]
+              if tiles[0] == 0 else "k_phi_step (16-bit storage, %d x %d tiles)" % tiles)
     out = {"MLUPS": round(w.nx * w.ny / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 5),
-           "timed_steps": steps, "bytes_per_lu": 40,
+           "timed_steps": steps, "bytes_per_lu": 40, "tiles": list(tiles),
            "effective_GBps": round(w.nx * w.ny * 40 / (ms * 1e-3) / 1e9, 1),
-           "roofline": roofline(40, w.nx * w.ny, ms * 1e3, "k_phi_step (16-bit storage)",
+           "roofline": roofline(40, w.nx * w.ny, ms * 1e3, kernel,
                                 "profiles/phi_step_vortex2048_16bit_kernel_trace.md")}
     if os.path.exists(GOLDEN):
         g = np.load(GOLDEN)

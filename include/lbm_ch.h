@@ -211,9 +211,10 @@ int lbm_ch_load_state(lbm_ch_ctx* ctx, const void* src, size_t bytes, int64_t st
  * margin of 2 at once, for periodic float32 lattices with a prescribed velocity at
  * tau_g = 1, models 1 and 2 (LBM_CH_EINVAL elsewhere).  The default is chosen at init
  * from the lattice size and storage; it changes speed only, never results.
- *   Below 2048^2 nodes, where single-pass tiles serve: tx = 0 with ty = 4 up to 65536
- *   nodes, else 16.
- *   From 2048^2 nodes up: the widest, then tallest, shape with ty from 32 down to 1 that
+ *   Where single-pass tiles serve: with float32 storage below 2048^2 nodes, tx = 0 with
+ *   ty = 4 up to 65536 nodes, else 16; with 16-bit storage at every size, ty = 4 up to
+ *   65536 nodes, 8 below 2048^2, else 16.
+ *   Otherwise from 2048^2 nodes up: the widest, then tallest, shape with ty from 32 down to 1 that
  *   gives at least 512 blocks with float32 storage, 1024 with 16-bit; tx = 512 needs
  *   1024 blocks of ty = 8 with float32 storage (and takes ty = 16 once that gives 2048
  *   blocks), and 512 blocks of ty = 16 with 16-bit storage (ty = 16 below 1024 such

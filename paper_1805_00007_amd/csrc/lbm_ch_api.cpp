@@ -138,7 +138,7 @@ static bool live(const lbm_ch_ctx* c) { return c && c->magic == CTX_MAGIC; }
 // tau_g = 1 exactly: the collision keeps none of the pulled populations (omega = 1).
 static bool tau_one(const lbm_ch_ctx* c) { return c->p.tau_g == 1.0; }
 
-// The single-pass tile (tx = 0 in lbm_ch_set_tiles) serves periodic float32 lattices with a
+// The single-pass tile (tx = 0 in lbm_ch_set_tiles) serves periodic lattices with a
 // prescribed velocity at tau_g = 1, models 1 and 2.
 static bool pass_eligible(const lbm_ch_params& p) {
   const int vmode = p.velocity_mode == LBM_CH_VEL_FIELD ? VEL_FIELD
@@ -196,12 +196,15 @@ static void default_tiles(const lbm_ch_params& p, int& tx_out, int& ty_out) {
   }
   const bool f32 = p.storage == LBM_CH_STORE_F32;
   const long nodes = (long)nx * ny;
-  if (nodes < (4L << 20) && pass_eligible(p)) {
-    // single-pass tiles below 2048^2 where they serve (us per step, marching default /
-    // single pass: 256^2 6.78 / 4.77 (4 rows); 512^2 9.27 / 5.93, 768^2 16.1 / 12.8,
-    // 1536^2 44.0 / 39.7 (16 rows); 1024^2 20.6 / 21.0)
+  if (pass_eligible(p) && (!f32 || nodes < (4L << 20))) {
+    // single-pass tiles where they serve: below 2048^2 with float32 storage (us per step,
+    // marching default / single pass: 256^2 6.78 / 4.77 (4 rows); 512^2 9.27 / 5.93,
+    // 768^2 16.1 / 12.8, 1536^2 44.0 / 39.7 (16 rows); 1024^2 20.6 / 21.0; from 2048^2
+    // up the march is faster: 61.5 / 66.4), at every size with 16-bit storage (256^2
+    // 7.07 / 4.75 (4 rows); 768^2 17.5 / 9.7, 1536^2 42.6 / 26.8 (8 rows); 2048^2
+    // 52.4 / 42.9, 4096^2 243 / 199 (16 rows))
     tx_out = 0;
-    ty_out = nodes <= 65536 ? 4 : 16;
+    ty_out = nodes <= 65536 ? 4 : (f32 || nodes >= (4L << 20)) ? 16 : 8;
     return;
   }
   if (nodes < (4L << 20)) {
@@ -512,9 +515,15 @@ static int run_steps(lbm_ch_ctx* c, int64_t nsteps, float* phi_out, hipStream_t 
     a.xh = c->xh;
     a.xfirst = c->step == 0 ? 1 : 0;
     float* rec = phi_out ? phi_out + (size_t)s * c->p.nx * c->p.ny : nullptr;
-    if (c->tx == 0) {  // single-pass tiles (records phi itself when asked)
-      a.phi_rec = rec;
-      e = launch_phi_pass(c->ty, vmode, c->p.model, a, c->nblocks, stream);
+    if (c->tx == 0) {  // single-pass tiles (record phi themselves with float32 storage)
+      e = hipSuccess;
+      if (rec && c->p.storage != LBM_CH_STORE_F32)
+        e = launch_phi_field(walls, c->p.storage, c->g[src], c->L.pitch, c->p.nx, c->p.ny,
+                             rec, stream);
+      else
+        a.phi_rec = rec;
+      if (e == hipSuccess)
+        e = launch_phi_pass(c->ty, vmode, c->p.model, c->p.storage, a, c->nblocks, stream);
       a.phi_rec = nullptr;
     } else if (rec && phi_record_fused(walls, vmode, c->p.model, c->p.storage)) {
       // the step writes phi of its source state itself

@@ -84,12 +84,15 @@ uint32_t population_bytes(int storage, uint32_t pitch, uint32_t ny);
 hipError_t launch_phi_step(int tx, bool walls, int vmode, int model, int storage, bool t1,
                            const StepArgs& a, int nblocks, hipStream_t s);
 // The single-pass tau_g = 1 tile (64 columns x rows, rows 4, 8 or 16; nblocks =
-// ceil(nx / 64) ceil(ny / rows); a.nstrips = ceil(nx / 64)): periodic float32 lattices
-// with a prescribed velocity, models 1 and 2 (phi_pass_ok); writes phi of the source
-// state to a.phi_rec when that is set.
+// ceil(nx / 64) ceil(ny / rows); a.nstrips = ceil(nx / 64)): periodic lattices with a
+// prescribed velocity, models 1 and 2, any storage (phi_pass_ok); with float32 storage
+// it writes phi of the source state to a.phi_rec when that is set (16-bit: a.phi_rec
+// must be null).  The 16-bit instances are in lbm_ch_step16.hip (launch_phi_pass16).
 bool phi_pass_ok(bool walls, int vmode, int model, int storage, bool t1);
-hipError_t launch_phi_pass(int rows, int vmode, int model, const StepArgs& a, int nblocks,
-                           hipStream_t s);
+hipError_t launch_phi_pass(int rows, int vmode, int model, int storage, const StepArgs& a,
+                           int nblocks, hipStream_t s);
+hipError_t launch_phi_pass16(int rows, int vmode, int model, int storage, const StepArgs& a,
+                             int nblocks, hipStream_t s);
 // The 16-bit storage cases of launch_phi_step (storage ST_F16 / ST_BF16), defined in
 // lbm_ch_step16.hip.
 hipError_t launch_phi_step16(int tx, bool walls, int vmode, int model, int storage, bool t1,

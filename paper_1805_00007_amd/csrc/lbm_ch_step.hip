@@ -618,7 +618,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int L) {
 constexpr int PS_C = 64;          // output columns per workgroup
 constexpr int PS_W = PS_C + 4;    // region row length (margin 2 on each side)
 
-template <int R, int VMODE, bool MODEL2, bool REC>
+template <int R, int VMODE, bool MODEL2, bool REC, int ST>
 __global__ void __launch_bounds__(64 * R) k_phi_pass(const StepArgs a) {
   constexpr int NT = 64 * R;
   constexpr int N = (R + 4) * PS_W;
@@ -629,8 +629,8 @@ __global__ void __launch_bounds__(64 * R) k_phi_pass(const StepArgs a) {
   const Coef& c = a.c;
   const int nx = a.nx, ny = a.ny;
   const uint32_t pitch = a.pitch;
-  const rsrc_t rsrc = make_rsrc(a.src, pop_bytes(ST_F32, pitch, ny));
-  const rsrc_t rdst = make_rsrc(a.dst, pop_bytes(ST_F32, pitch, ny));
+  const rsrc_t rsrc = make_rsrc(a.src, pop_bytes(ST, pitch, ny));
+  const rsrc_t rdst = make_rsrc(a.dst, pop_bytes(ST, pitch, ny));
   int L = blockIdx.x;
   if (a.xcd_remap) {
     const int per = gridDim.x >> 3;
@@ -664,9 +664,9 @@ __global__ void __launch_bounds__(64 * R) k_phi_pass(const StepArgs a) {
     const uint32_t xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
     float g[9];
     if constexpr (decltype(lanes)::value)
-      pull9_lanes<false, ST_F32>(rsrc, pitch, ny, y, (uint32_t)x, xm, xp, g);
+      pull9_lanes<false, ST>(rsrc, pitch, ny, y, (uint32_t)x, xm, xp, g);
     else
-      pull9<false, ST_F32>(rsrc, pitch, ny, y, (uint32_t)x, xm, xp, g);
+      pull9<false, ST>(rsrc, pitch, ny, y, (uint32_t)x, xm, xp, g);
     Node n;
     n.phi = sum9(g, n.lo);
     const float f = a.tf;  // periodic: the row parity factor is 1
@@ -754,7 +754,7 @@ __global__ void __launch_bounds__(64 * R) k_phi_pass(const StepArgs a) {
   }
   float g[9];
   collide_t1(c, no.phi, s_mu[ko], no.u, no.v, fx, fy, g);
-  finish_store<ST_F32>(rdst, pitch, (uint32_t)xo, (uint32_t)yo, (double)no.phi + (double)no.lo, g);
+  finish_store<ST>(rdst, pitch, (uint32_t)xo, (uint32_t)yo, (double)no.phi + (double)no.lo, g);
 }
 #pragma clang fp contract(fast)
 
@@ -905,9 +905,9 @@ hipError_t phi_step_t(int tx, bool walls, int vmode, int model, bool t1, const S
   }
 }
 
-template <int R>
+template <int R, int ST>
 hipError_t phi_pass_r(int vmode, bool model2, bool rec, const StepArgs& a, int nb, hipStream_t s) {
-#define LBM_PASS(V, M, RC) hipLaunchKernelGGL((k_phi_pass<R, V, M, RC>), dim3(nb), dim3(64 * R), 0, s, a)
+#define LBM_PASS(V, M, RC) hipLaunchKernelGGL((k_phi_pass<R, V, M, RC, ST>), dim3(nb), dim3(64 * R), 0, s, a)
   if (vmode == VEL_SEP) {
     if (model2) { if (rec) LBM_PASS(VEL_SEP, true, true); else LBM_PASS(VEL_SEP, true, false); }
     else { if (rec) LBM_PASS(VEL_SEP, false, true); else LBM_PASS(VEL_SEP, false, false); }
@@ -917,6 +917,18 @@ hipError_t phi_pass_r(int vmode, bool model2, bool rec, const StepArgs& a, int n
   }
 #undef LBM_PASS
   return hipGetLastError();
+}
+
+template <int ST>
+hipError_t phi_pass_t(int rows, int vmode, int model, const StepArgs& a, int nb, hipStream_t s) {
+  const bool rec = a.phi_rec != nullptr, m2 = model == 2;
+  if (rec && ST != ST_F32) return hipErrorInvalidValue;  // 16-bit: phi recorded apart
+  switch (rows) {
+    case 4: return phi_pass_r<4, ST>(vmode, m2, rec, a, nb, s);
+    case 8: return phi_pass_r<8, ST>(vmode, m2, rec, a, nb, s);
+    case 16: return phi_pass_r<16, ST>(vmode, m2, rec, a, nb, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
@@ -929,6 +941,14 @@ hipError_t launch_phi_step16(int tx, bool walls, int vmode, int model, int stora
   switch (storage) {
     case ST_F16: return phi_step_t<ST_F16>(tx, walls, vmode, model, t1, a, nblocks, s);
     case ST_BF16: return phi_step_t<ST_BF16>(tx, walls, vmode, model, t1, a, nblocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+hipError_t launch_phi_pass16(int rows, int vmode, int model, int storage, const StepArgs& a,
+                             int nblocks, hipStream_t s) {
+  switch (storage) {
+    case ST_F16: return phi_pass_t<ST_F16>(rows, vmode, model, a, nblocks, s);
+    case ST_BF16: return phi_pass_t<ST_BF16>(rows, vmode, model, a, nblocks, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -968,20 +988,15 @@ hipError_t launch_phi_record(int tx, int vmode, int model, bool t1, const StepAr
 }
 
 bool phi_pass_ok(bool walls, int vmode, int model, int storage, bool t1) {
-  return !walls && storage == ST_F32 && t1 && (vmode == VEL_SEP || vmode == VEL_FIELD) &&
-         (model == 1 || model == 2);
+  return !walls && t1 && (vmode == VEL_SEP || vmode == VEL_FIELD) && (model == 1 || model == 2) &&
+         (storage == ST_F32 || storage == ST_F16 || storage == ST_BF16);
 }
 
-hipError_t launch_phi_pass(int rows, int vmode, int model, const StepArgs& a, int nblocks,
-                           hipStream_t s) {
-  if (!phi_pass_ok(false, vmode, model, ST_F32, true)) return hipErrorInvalidValue;
-  const bool rec = a.phi_rec != nullptr, m2 = model == 2;
-  switch (rows) {
-    case 4: return phi_pass_r<4>(vmode, m2, rec, a, nblocks, s);
-    case 8: return phi_pass_r<8>(vmode, m2, rec, a, nblocks, s);
-    case 16: return phi_pass_r<16>(vmode, m2, rec, a, nblocks, s);
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_phi_pass(int rows, int vmode, int model, int storage, const StepArgs& a,
+                           int nblocks, hipStream_t s) {
+  if (!phi_pass_ok(false, vmode, model, storage, true)) return hipErrorInvalidValue;
+  if (storage != ST_F32) return launch_phi_pass16(rows, vmode, model, storage, a, nblocks, s);
+  return phi_pass_t<ST_F32>(rows, vmode, model, a, nblocks, s);
 }
 
 hipError_t launch_phi_step(int tx, bool walls, int vmode, int model, int storage, bool t1,

@@ -158,14 +158,15 @@ def test_missing_library_fails_loudly(tmp_path):
 
 
 @pytest.mark.parametrize("n,storage,expect", [
-    (2048, 0, (512, 8)), (2048, 1, (512, 16)), (2048, 2, (512, 16)), (3072, 0, (512, 8)),
-    (4096, 0, (512, 16)), (4096, 1, (512, 8)), (7680, 0, (512, 16)),
+    (2048, 0, (512, 8)), (2048, 1, (0, 16)), (2048, 2, (0, 16)), (3072, 0, (512, 8)),
+    (4096, 0, (512, 16)), (4096, 1, (0, 16)), (7680, 0, (512, 16)),
     (128, 0, (0, 4)), (256, 0, (0, 4)), (512, 0, (0, 16)), (1536, 0, (0, 16)), (8, 0, (0, 4)),
-    (512, 1, (512, 2)), (1024, 1, (512, 4))])
+    (256, 1, (0, 4)), (512, 1, (0, 8)), (1024, 2, (0, 8))])
 def test_default_tiles_rule(n, storage, expect):
     """The default tile rule (include/lbm_ch.h) on the host, without a device: the
     shapes the size sweeps picked for square lattices (periodic, tau_g = 1, separable
-    velocity, Model-II: single-pass tiles below 2048^2 with float32 storage)."""
+    velocity, Model-II: single-pass tiles below 2048^2 with float32 storage, at every
+    size with 16-bit storage)."""
     assert lbm.default_tiles(lbm.make_params(n, n, storage=storage)) == expect
 
 
@@ -175,6 +176,13 @@ def test_default_tiles_rule(n, storage, expect):
 def test_default_marching_tiles_rule(n, expect):
     """Where single-pass tiles do not serve (here tau_g != 1) the marching tiles' rule."""
     assert lbm.default_tiles(lbm.make_params(n, n, tau_g=0.8)) == expect
+
+
+@pytest.mark.parametrize("n,storage,expect", [(2048, 1, (512, 16)), (4096, 1, (512, 8)),
+                                              (3072, 2, (512, 8))])
+def test_default_marching_tiles_rule_16bit(n, storage, expect):
+    """16-bit storage where single-pass tiles do not serve (walls): the marching rule."""
+    assert lbm.default_tiles(lbm.make_params(n, n, storage=storage, walls=1)) == expect
 
 
 def test_default_tiles_invariants():
@@ -190,9 +198,9 @@ def test_default_tiles_invariants():
                 for walls in (0, 1):
                     tx, ty = lbm.default_tiles(lbm.make_params(nx, ny, storage=storage,
                                                                walls=walls))
-                    if tx == 0:  # single pass: periodic float32, below 2048^2
-                        assert storage == 0 and walls == 0 and nx * ny < 4 << 20
-                        assert ty in (4, 16), (nx, ny, ty)
+                    if tx == 0:  # single pass: periodic; float32 below 2048^2
+                        assert walls == 0 and (storage != 0 or nx * ny < 4 << 20)
+                        assert ty in (4, 8, 16), (nx, ny, ty)
                         continue
                     assert tx in (64, 128, 256, 512) and 1 <= ty <= min(ny, 32), (nx, ny, tx, ty)
                     assert tx == 64 or tx <= nx, (nx, ny, tx)

@@ -57,20 +57,22 @@ def _cut(w, ny):
     return w
 
 
-@pytest.mark.parametrize("model", [1, 2])
-def test_single_pass_tiles_match_marching_tiles(lbm, model):
+@pytest.mark.parametrize("model,storage", [(1, 0), (2, 0), (2, 1), (2, 2)])
+def test_single_pass_tiles_match_marching_tiles(lbm, model, storage):
     """The single-pass tile (tx = 0: 64 columns x 4, 8 or 16 rows, all pulls at once) gives
-    bitwise the marching tiles' state: a lattice wider than its 68-column region with a
-    partial last row of tiles, and one narrower than the region (40 x 23)."""
+    bitwise the marching tiles' state, with float32 and 16-bit storage: a lattice wider
+    than its 68-column region with a partial last row of tiles, and one narrower than the
+    region (40 x 23)."""
     for n, ny in ((200, 136), (40, 23)):
         w = _cut(workloads.vortex(n, period=400, steps=60, model=model), ny)
-        ref = _run(lbm, w, 60, (64, 4))
+        ref = _run(lbm, w, 60, (64, 4), storage=storage)
         for r in (4, 8, 16):
-            print("single pass", n, ny, r, flush=True)
-            assert np.array_equal(_run(lbm, w, 60, (0, r)), ref), (n, ny, r)
+            print("single pass", n, ny, r, "storage", storage, flush=True)
+            assert np.array_equal(_run(lbm, w, 60, (0, r), storage=storage), ref), (n, ny, r)
 
 
-def test_single_pass_tiles_stored_field_and_record(lbm):
+@pytest.mark.parametrize("storage", [0, 1])
+def test_single_pass_tiles_stored_field_and_record(lbm, storage):
     """With a stored velocity field, and when the step also records phi of each source
     state (the adjoint's forward pass): bitwise the marching tiles' state and record."""
     ac = workloads.adjoint_case(n=96, steps=40)
@@ -78,7 +80,7 @@ def test_single_pass_tiles_stored_field_and_record(lbm):
     out = {}
     for tiles in ((64, 2), (0, 4), (0, 16)):
         s = lbm.Solver(ac.n, ac.n, ac.phi0, field=(U, V), device=torch.device("cuda:0"),
-                       **ac.phys)
+                       storage=storage, **ac.phys)
         s.set_tiles(*tiles)
         s.step(7)
         traj = torch.empty((12, ac.n, ac.n), dtype=torch.float32, device="cuda:0")
@@ -132,18 +134,17 @@ def test_autotune_restores_state(lbm):
 
 
 @pytest.mark.parametrize("n,storage,expect", [
-    (2048, 0, (512, 8)), (2048, 1, (512, 16)), (2048, 2, (512, 16)), (4096, 0, (512, 16)),
-    (256, 0, (0, 4)), (512, 0, (0, 16)), (1536, 0, (0, 16)), (512, 1, (512, 2)),
-    (1024, 1, (512, 4)),
-    (4096, 1, (512, 8)), (3072, 0, (512, 8))])
+    (2048, 0, (512, 8)), (2048, 1, (0, 16)), (2048, 2, (0, 16)), (4096, 0, (512, 16)),
+    (256, 0, (0, 4)), (512, 0, (0, 16)), (1536, 0, (0, 16)), (512, 1, (0, 8)),
+    (1024, 1, (0, 8)), (4096, 1, (0, 16)), (3072, 0, (512, 8))])
 def test_default_tiles(lbm, n, storage, expect):
     """Default tile of an n^2 lattice.  From 2048^2 up: the widest, then tallest, shape
     with at least 512 blocks for float32 populations (for the 512-column tile 1024 blocks
     of 8 rows, and 16-row chunks once they give 2048 blocks) and 1024 for 16-bit ones (for
     the 512-column tile 512 blocks of 16 rows, and 8-row chunks once 16-row ones give
-    1024 blocks).  Below: single-pass tiles (tx = 0) for these periodic float32 lattices
-    at tau_g = 1; with 16-bit storage the tallest chunk (4 rows at most) that gives 2048
-    waves, then the widest strip whose strips span at most 9/8 nx."""
+    1024 blocks), where single-pass tiles do not serve.  These periodic tau_g = 1
+    lattices take single-pass tiles (tx = 0) below 2048^2 with float32 storage and at
+    every size with 16-bit storage."""
     w = workloads.metric2048(steps=1) if n == 2048 else workloads.vortex(n, period=80000,
                                                                           steps=1)
     s = lbm.solver_for(w, storage=storage)
